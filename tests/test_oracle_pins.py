@@ -1,0 +1,386 @@
+"""Pins of the FP64 oracle against what the mathematics fixes (CPU only).
+
+Each test checks the oracle against something other than itself: a library
+routine, a closed form, an invariant, or brute force.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy.special import eval_jacobi
+
+from oracle import assembly, basis, geometry, operators as op, quadrature, sumfac
+from oracle.jacobi import jacobi, jacobi_deriv
+from paper_2606_20917_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+SHAPES = [basis.HEX, basis.PRISM, basis.TET]
+
+
+def _num(s):
+    return float(eval(s, {"sqrt": math.sqrt}))
+
+
+# ------------------------------------------------------------------ Jacobi
+@pytest.mark.parametrize("a,b", [(0, 0), (1, 1), (1, 0), (2, 0), (3, 1), (5, 1), (17, 1)])
+def test_jacobi_matches_library(a, b):
+    x = np.linspace(-1, 1, 37)
+    for n in range(12):
+        assert np.allclose(jacobi(n, a, b, x), eval_jacobi(n, a, b, x), rtol=1e-13, atol=1e-13)
+        assert abs(jacobi(n, a, b, 1.0) - math.comb(n + a, n)) < 1e-12 * math.comb(n + a, n)
+
+
+@pytest.mark.parametrize("a,b", [(0, 0), (1, 1), (2, 0), (3, 1)])
+def test_jacobi_derivative_by_interpolation(a, b):
+    # interpolate the library's P_n exactly in a Chebyshev series and differentiate that
+    xs = np.cos(np.linspace(0, np.pi, 16))
+    x = np.linspace(-1, 1, 23)
+    for n in range(1, 12):
+        cheb = np.polynomial.Chebyshev.fit(xs, eval_jacobi(n, a, b, xs), n, domain=[-1, 1])
+        assert np.allclose(jacobi_deriv(n, a, b, x), cheb.deriv()(x), rtol=1e-10, atol=1e-10)
+
+
+# ------------------------------------------------------------------ quadrature
+def test_quadrature_closed_forms():
+    g = json.load(open(os.path.join(GOLDEN, "quadrature_closed_forms.json")))
+    for q, ref in g["gll"].items():
+        x, w = quadrature.gauss_lobatto_legendre(int(q))
+        assert np.allclose(x, [_num(s) for s in ref["x"]], atol=1e-15)
+        assert np.allclose(w, [_num(s) for s in ref["w"]], atol=1e-15)
+    for ref in g["grj"].values():
+        x, w = quadrature.gauss_radau_jacobi(2, ref["alpha"])
+        assert np.allclose(x, [_num(s) for s in ref["x"]], atol=1e-15)
+        assert np.allclose(w, [_num(s) for s in ref["w"]], atol=1e-15)
+
+
+def _exact_moment(alpha, k):
+    """int_{-1}^{1} (1-x)^alpha x^k dx in exact rational arithmetic."""
+    tot = Fraction(0)
+    for j in range(alpha + 1):
+        c = Fraction(math.comb(alpha, j)) * (-1) ** j
+        deg = j + k
+        tot += c * (Fraction(2, deg + 1) if deg % 2 == 0 else 0)
+    return float(tot)
+
+
+@pytest.mark.parametrize("q", range(2, 12))
+def test_gll_exactness_degree(q):
+    x, w = quadrature.gauss_lobatto_legendre(q)
+    assert np.all(w > 0)
+    for k in range(2 * q - 2):
+        assert abs(w @ x ** k - _exact_moment(0, k)) < 1e-14
+    assert abs(w @ x ** (2 * q - 2) - _exact_moment(0, 2 * q - 2)) > 1e-8
+
+
+@pytest.mark.parametrize("alpha", [0, 1, 2])
+@pytest.mark.parametrize("q", range(2, 12))
+def test_grj_exactness_degree(alpha, q):
+    x, w = quadrature.gauss_radau_jacobi(q, alpha)
+    assert x[0] == -1.0 and np.all(np.diff(x) > 0) and x[-1] < 1.0
+    assert np.all(w > 0)
+    for k in range(2 * q - 1):
+        ref = _exact_moment(alpha, k)
+        assert abs(w @ x ** k - ref) < 1e-13 * max(1.0, abs(ref))
+    assert abs(w @ x ** (2 * q - 1) - _exact_moment(alpha, 2 * q - 1)) > 1e-8
+
+
+# ------------------------------------------------------------------ basis
+def _random_ref_points(shape, n, rng):
+    if shape == basis.HEX:
+        return rng.uniform(-1, 1, (3, n))
+    e = rng.uniform(-0.98, 0.98, (3, n))
+    return np.array(basis.xi_from_eta(shape, *e))
+
+
+def _monomials(shape, deg, x):
+    cols = []
+    for a in range(deg + 1):
+        for b in range(deg + 1):
+            for c in range(deg + 1):
+                if shape == basis.TET and a + b + c > deg:
+                    continue
+                if shape == basis.PRISM and a + c > deg:
+                    continue
+                cols.append(x[0] ** a * x[1] ** b * x[2] ** c)
+    return np.array(cols).T
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("P", [2, 3, 4, 5])
+def test_basis_spans_polynomial_space(shape, P):
+    """Every mode is a polynomial of the shape's space, and the modes are a basis of it."""
+    rng = np.random.default_rng(7)
+    x = _random_ref_points(shape, 500, rng)
+    phi, _ = basis.eval_basis_xi(shape, P, *basis.eta_from_xi(shape, *x))
+    V = _monomials(shape, P - 1, x)
+    assert V.shape[1] == basis.nmodes(shape, P)
+    coef = np.linalg.lstsq(V, phi, rcond=None)[0]
+    assert np.abs(V @ coef - phi).max() < 1e-11
+    assert np.linalg.matrix_rank(coef) == basis.nmodes(shape, P)
+
+
+def test_uncorrected_tet_modes_are_not_polynomial():
+    """Without the collapsed-vertex corrections, modes (0,0,1), (0,1,0), (0,1,1) leave the space."""
+    rng = np.random.default_rng(3)
+    x = _random_ref_points(basis.TET, 400, rng)
+    e1, e2, e3 = basis.eta_from_xi(basis.TET, *x)
+    V = _monomials(basis.TET, 2, x)
+    for (p, q, r) in [(0, 0, 1), (0, 1, 0), (0, 1, 1)]:
+        raw = basis.psi_a(p, e1) * basis.psi_b(p, q, e2) * basis.psi_b(p + q, r, e3)
+        res = V @ np.linalg.lstsq(V, raw, rcond=None)[0] - raw
+        assert np.abs(res).max() > 1e-3
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("P", [2, 4, 6])
+def test_vertex_modes_are_barycentric(shape, P):
+    rng = np.random.default_rng(11)
+    x = _random_ref_points(shape, 200, rng)
+    phi, _ = basis.eval_basis_xi(shape, P, *basis.eta_from_xi(shape, *x))
+    N, _ = geometry.shape_functions(shape, *x)
+    for m, v in basis.vertex_modes(shape, P):
+        assert np.abs(phi[:, m] - N[v]).max() < 1e-13
+    assert np.abs(sum(phi[:, m] for m, _ in basis.vertex_modes(shape, P)) - 1).max() < 1e-13
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_basis_gradient_by_finite_differences(shape):
+    rng = np.random.default_rng(5)
+    P = 5
+    x = _random_ref_points(shape, 60, rng) * 0.9
+    _, d = basis.eval_basis_xi(shape, P, *basis.eta_from_xi(shape, *x))
+    h = 1e-6
+    for j in range(3):
+        xp, xm = x.copy(), x.copy()
+        xp[j] += h
+        xm[j] -= h
+        fd = (basis.eval_basis_xi(shape, P, *basis.eta_from_xi(shape, *xp))[0]
+              - basis.eval_basis_xi(shape, P, *basis.eta_from_xi(shape, *xm))[0]) / (2 * h)
+        assert np.abs(fd - d[j]).max() < 1e-7
+
+
+def _face_points(shape, face, n, rng):
+    """Random points on one reference face."""
+    if shape == basis.TET:
+        a, b = rng.uniform(0, 1, (2, n))
+        s = a + b > 1
+        a[s], b[s] = 1 - a[s], 1 - b[s]
+        u, v = -1 + 2 * a, -1 + 2 * b
+        if face == 0:
+            return np.array([u, v, -np.ones(n)])
+        if face == 1:
+            return np.array([u, -np.ones(n), v])
+        if face == 2:
+            return np.array([-np.ones(n), u, v])
+        return np.array([u, v, -u - v - 1])
+    raise ValueError
+
+
+@pytest.mark.parametrize("P", [3, 4, 5])
+def test_tet_face_modes_count(P):
+    """C0 modal structure: on each face of the tet, exactly P(P+1)/2 modes are non-zero,
+    and their traces span the polynomials of degree P-1 on that face."""
+    rng = np.random.default_rng(2)
+    for face in range(4):
+        x = _face_points(basis.TET, face, 300, rng)
+        phi, _ = basis.eval_basis_xi(basis.TET, P, *basis.eta_from_xi(basis.TET, *x))
+        nz = np.abs(phi).max(axis=0) > 1e-12
+        assert nz.sum() == P * (P + 1) // 2
+        assert np.linalg.matrix_rank(phi[:, nz], tol=1e-9) == P * (P + 1) // 2
+
+
+def test_reference_volumes_and_moments():
+    for shape, vol in [(basis.HEX, 8.0), (basis.PRISM, 4.0), (basis.TET, 4.0 / 3.0)]:
+        for Q in range(2, 12):
+            r = basis.element_rule(shape, Q)
+            assert abs(r["w"].sum() - vol) < 1e-13
+    r = basis.element_rule(basis.TET, 4)
+    x1, _, _ = basis.xi_from_eta(basis.TET, r["e1"], r["e2"], r["e3"])
+    assert abs(r["w"] @ x1 ** 2 - 8.0 / 15.0) < 1e-14
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("P", [2, 4, 7])
+def test_collocation_derivative_is_exact_on_basis(shape, P):
+    """D_eta B = B_eta because every 1-D factor has degree < Q (eq. (22) on the basis)."""
+    tab = op.Tables(shape, P, P + 1)
+    r = tab.rule
+    _, deta = basis.eval_basis_eta(shape, P, r["e1"], r["e2"], r["e3"])
+    for k in range(3):
+        assert np.abs(tab.D_eta[k] @ tab.B - deta[k]).max() < 1e-11 * max(1, np.abs(deta[k]).max())
+    for j in range(3):
+        assert np.abs(tab.D_xi[j] @ tab.B - tab.dB[j]).max() < 1e-10 * max(1, np.abs(tab.dB[j]).max())
+
+
+def test_collocation_derivative_on_monomials():
+    for Q in range(2, 12):
+        z, _ = quadrature.gauss_lobatto_legendre(Q)
+        D = op.collocation_derivative_1d(z)
+        for k in range(Q):
+            ref = k * z ** (k - 1) if k else 0 * z
+            assert np.abs(D @ z ** k - ref).max() < 1e-11
+
+
+# ------------------------------------------------------------------ index maps
+def _closed_form_index(shape, P, p, q, r):
+    if shape == basis.HEX:
+        return (p * P + q) * P + r
+    if shape == basis.PRISM:
+        return sum(P * (P - pp) for pp in range(p)) + q * (P - p) + r
+    T = lambda n: n * (n + 1) * (n + 2) // 6
+    return (T(P) - T(P - p)) + (q * (P - p) - q * (q - 1) // 2) + r
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_mode_index_closed_form(shape):
+    for P in range(1, 12):
+        ml = basis.modes(shape, P)
+        assert len(ml) == inputs.nmodes(shape, P)
+        for m, (p, q, r) in enumerate(ml):
+            assert _closed_form_index(shape, P, p, q, r) == m
+
+
+# ------------------------------------------------------------------ geometry + operators
+def _mesh(shape, P, n=3, amp=0.0, jitter=0.05, seed=0):
+    rng = np.random.default_rng(seed)
+    if shape == basis.HEX:
+        verts = inputs.hex_mesh(n, rng, jitter)
+    elif shape == basis.PRISM:
+        verts = inputs.prism_mesh(n, rng, jitter)
+    else:
+        verts = inputs.tet_mesh(n, rng, jitter)
+    tab = op.Tables(shape, P, P + 1)
+    return verts, tab, geometry.Geometry(shape, P + 1, verts, amp)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_affine_tet_jacobian_closed_form(shape):
+    if shape != basis.TET:
+        pytest.skip("closed form only for the affine tet")
+    verts, tab, geo = _mesh(shape, 3)
+    A = np.stack([verts[:, 1] - verts[:, 0], verts[:, 2] - verts[:, 0], verts[:, 3] - verts[:, 0]], axis=2)
+    det = np.linalg.det(A)
+    assert np.allclose(geo.detJ, det[:, None] / 8.0, rtol=1e-13)
+    assert np.allclose(geo.W.sum(axis=1), det / 6.0, rtol=1e-13)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("P", [2, 3, 5])
+def test_mass_integrates_volume_and_laplacian_kills_constants(shape, P):
+    verts, tab, geo = _mesh(shape, P)
+    ne = len(verts)
+    one = np.tile(op.constant_coefficients(tab), (ne, 1))
+    assert abs((op.mass(tab, geo, one) * one).sum() - 1.0) < 1e-13
+    L1 = op.helmholtz(tab, geo, 0.0, one)
+    assert np.abs(L1).max() < 1e-13
+    # IProductWRTBase(1) . u^_1 = volume as well
+    assert abs((op.iprod_wrt_base(tab, geo, np.ones((ne, tab.nq))) * one).sum() - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("P", [2, 4])
+def test_energy_identity_and_exact_gradient(shape, P):
+    """u = x_d is exactly representable on vertex maps: grad u = e_d, (grad u, grad u) = volume."""
+    verts, tab, geo = _mesh(shape, P)
+    ne = len(verts)
+    one = np.tile(op.constant_coefficients(tab), (ne, 1))
+    for d in range(3):
+        ux = op.linear_coefficients(tab, verts, d)
+        assert abs((op.helmholtz(tab, geo, 0.0, ux) * ux).sum() - 1.0) < 1e-12
+        assert abs((op.helmholtz(tab, geo, 0.0, ux) * one).sum()) < 1e-12
+        grads = op.phys_deriv(tab, geo, op.bwd_trans(tab, ux))
+        for i in range(3):
+            assert np.abs(grads[i] - (1.0 if i == d else 0.0)).max() < 1e-11
+        # IProductWRTDerivBase of the constant field e_d against u = x_d and u = 1
+        f = [np.full((ne, tab.nq), 1.0 if i == d else 0.0) for i in range(3)]
+        r = op.iprod_wrt_deriv_base(tab, geo, *f)
+        assert abs((r * ux).sum() - 1.0) < 1e-12
+        assert abs((r * one).sum()) < 1e-12
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_helmholtz_matrix_symmetric_positive_definite(shape):
+    verts, tab, geo = _mesh(shape, 4, n=2, amp=0.1)
+    for e in range(3):
+        H = op.helmholtz_matrix(tab, geo, e, 1.0)
+        assert np.abs(H - H.T).max() < 1e-13 * np.abs(H).max()
+        assert np.linalg.eigvalsh(H).min() > 0
+        L = op.helmholtz_matrix(tab, geo, e, 0.0)
+        ev = np.linalg.eigvalsh(L)
+        assert ev.min() > -1e-12 * ev.max()
+        assert np.sum(ev < 1e-10 * ev.max()) == 1        # only the constants are annihilated
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("lam", [0.0, 0.5, 1.0, 3.0])
+def test_helmholtz_equals_composition(shape, lam):
+    """H u^ = IProdDeriv(PhysDeriv(Bwd u^)) + lambda IProd(Bwd u^): analytic basis gradients
+    on one side, collocation derivatives on the other."""
+    verts, tab, geo = _mesh(shape, 4, n=2, amp=0.1)
+    rng = np.random.default_rng(1)
+    uh = rng.uniform(-1, 1, (len(verts), tab.M))
+    u = op.bwd_trans(tab, uh)
+    comp = op.iprod_wrt_deriv_base(tab, geo, *op.phys_deriv(tab, geo, u)) + lam * op.iprod_wrt_base(tab, geo, u)
+    ref = op.helmholtz(tab, geo, lam, uh)
+    assert np.abs(comp - ref).max() < 1e-11 * np.abs(ref).max()
+    # and the explicit elemental matrix gives the same
+    for e in range(2):
+        assert np.abs(op.helmholtz_matrix(tab, geo, e, lam) @ uh[e] - ref[e]).max() < 1e-12 * np.abs(ref[e]).max()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("P", [2, 3])
+def test_dense_matrices_equal_sum_factorised_brute_force(shape, P):
+    Q = P + 1
+    verts, tab, geo = _mesh(shape, P, n=1, amp=0.1)
+    rng = np.random.default_rng(4)
+    uh = rng.uniform(-1, 1, tab.M)
+    assert np.abs(sumfac.bwd_trans(shape, P, Q, uh) - tab.B @ uh).max() < 1e-14
+    f = rng.uniform(-1, 1, tab.nq)
+    ref = op.iprod_wrt_base(tab, geo, f[None, :])[0]
+    assert np.abs(sumfac.iprod_wrt_base(shape, P, Q, f, geo.detJ[0]) - ref).max() < 1e-14
+
+
+def test_standard_derivative_brute_force():
+    Q = 4
+    z, _ = quadrature.gauss_lobatto_legendre(Q)
+    tab = op.Tables(basis.HEX, 3, Q)
+    u = np.random.default_rng(9).uniform(-1, 1, tab.nq)
+    assert np.abs(sumfac.std_deriv_xi1(Q, z, u) - tab.D_eta[0] @ u).max() < 1e-13
+
+
+# ------------------------------------------------------------------ assembly + CG
+@pytest.mark.parametrize("n,P", [(1, 2), (2, 3), (3, 4), (2, 6)])
+def test_c0_map_closed_form_equals_matching(n, P):
+    a, na = assembly.c0_map_closed_form(n, P)
+    b, nb = assembly.c0_map_by_matching(n, P)
+    assert na == nb == (n * (P - 1) + 1) ** 3
+    assert set(np.unique(a)) == set(range(na))
+    # same partition of the (element, mode) pairs
+    relabel = {}
+    for x, y in zip(a.ravel(), b.ravel()):
+        assert relabel.setdefault(x, y) == y
+
+
+def test_assembled_cg_small_mesh():
+    n, P, lam = 2, 4, 1.0
+    verts = inputs.hex_mesh(n)
+    tab = op.Tables(basis.HEX, P, P + 1)
+    geo = geometry.Geometry(basis.HEX, P + 1, verts, 0.1)
+    l2g, ng = assembly.c0_map_closed_form(n, P)
+    A = np.zeros((ng, ng))
+    for e in range(n ** 3):
+        A[np.ix_(l2g[e], l2g[e])] += op.helmholtz_matrix(tab, geo, e, lam)
+    assert np.abs(A - A.T).max() < 1e-12 * np.abs(A).max()
+    x = np.random.default_rng(0).uniform(-1, 1, ng)
+    assert np.abs(assembly.assembled_apply(tab, geo, lam, l2g, ng, x) - A @ x).max() < 1e-12 * np.abs(A @ x).max()
+    diag = assembly.assembled_diagonal(tab, geo, lam, l2g, ng)
+    assert np.abs(diag - np.diag(A)).max() < 1e-13 * np.abs(diag).max()
+    b = assembly.manufactured_rhs(tab, geo, lam, l2g, ng)
+    xs, it, res = assembly.pcg(lambda v: A @ v, diag, b, rtol=1e-10)
+    assert res <= 1e-10
+    ref = np.linalg.solve(A, b)
+    assert np.abs(xs - ref).max() < 1e-8 * np.abs(ref).max()
