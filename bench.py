@@ -1,0 +1,179 @@
+"""Throughput of the fused Helmholtz apply on one MI355X.
+
+Workload (one step): the FP64 fused Helmholtz apply y = (L + lambda M) x, lambda = 1, on
+the 32^3 curved-hex mesh (sin deformation of amplitude 0.1, per-point geometric
+factors) at every P in {2, 4, 6, 8, 10}, Q = P+1: five launches, one per order.
+Throughput = (modes x elements) / time (the paper's throughput definition,
+section 4.2), summed over the five orders.  Inputs are resident in HBM before the
+timed region; buffer sets rotate so that every launch streams from HBM (a working
+set under 1.2 GB is replicated until the rotation exceeds it).
+
+Prints one JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+ROTATE_BYTES = 1.2e9
+
+
+def hex_bytes(P, s=8):
+    Q = P + 1
+    return s * (2 * P ** 3 + 7 * Q ** 3)
+
+
+def hex_flops(P):
+    Q = P + 1
+    return 4 * (P ** 3 * Q + P ** 2 * Q ** 2 + P * Q ** 3) + 12 * Q ** 4 + 21 * Q ** 3
+
+
+def setup(P, dtype_name, n=32):
+    import torch
+    from paper_2606_20917_amd import inputs, nir
+    c = inputs.hex_sin32(P, n)
+    Q, ne = P + 1, len(c["verts"])
+    dev = torch.device("cuda")
+    basis = nir.Basis(nir.HEX, P)
+    b64 = nir.batch(nir.HEX, P, ne, nir.F64, 1)
+    helm = torch.empty(ne, 7, Q ** 3, dtype=torch.float64, device=dev)
+    helm32 = torch.empty(ne, 7, Q ** 3, dtype=torch.float32, device=dev) if dtype_name == "f32" else None
+    nir.nir_geom_from_vertices(b64, basis, torch.tensor(c["verts"], device=dev), nir.MAP_VERTEX_SIN, c["amp"],
+                               None, None, helm, helm32)
+    if dtype_name == "f32":
+        helm, tdt, b = helm32, torch.float32, nir.batch(nir.HEX, P, ne, nir.F32, 1)
+    else:
+        tdt, b = torch.float64, b64
+    x = torch.tensor(c["coef"], dtype=tdt, device=dev)
+    s = 8 if dtype_name == "f64" else 4
+    per_set = s * (2 * ne * P ** 3 + 7 * ne * Q ** 3)
+    nsets = max(1, math.ceil(ROTATE_BYTES / per_set))
+    sets = [(helm, x, torch.empty_like(x))]
+    for _ in range(nsets - 1):
+        sets.append((helm.clone(), x.clone(), torch.empty_like(x)))
+    torch.cuda.synchronize()
+    return dict(P=P, Q=Q, ne=ne, basis=basis, b=b, sets=sets, verts=c["verts"], coef=c["coef"],
+                amp=c["amp"], nsets=nsets)
+
+
+def cpu_baseline(cases, budget_s):
+    """The FP64 oracle (dense matrices, numpy/BLAS) on a bounded sample of each order."""
+    from threadpoolctl import threadpool_info
+    from oracle import geometry as og, operators as op
+    dof, t_tot, samples, errs = 0, 0.0, [], {}
+    per_p = budget_s / len(cases)
+    for c in cases:
+        P, Q = c["P"], c["Q"]
+        tab = op.Tables(0, P, Q)
+        # size the sample from a short probe
+        n_probe = 16
+        geo = og.Geometry(0, Q, c["verts"][:n_probe], c["amp"])
+        t = time.perf_counter()
+        op.helmholtz(tab, geo, 1.0, c["coef"][:n_probe])
+        dt = time.perf_counter() - t
+        n = int(min(c["ne"], max(n_probe, n_probe * per_p / max(dt, 1e-6))))
+        geo = og.Geometry(0, Q, c["verts"][:n], c["amp"])
+        t = time.perf_counter()
+        ref = op.helmholtz(tab, geo, 1.0, c["coef"][:n])
+        dt = time.perf_counter() - t
+        dof += n * P ** 3
+        t_tot += dt
+        samples.append(f"P={P}:{n}")
+        y = c["sets"][0][2][:n].double().cpu().numpy()
+        errs[P] = float((np.linalg.norm(y - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    return {"value": dof / t_tot / 1e9, "unit": "GDoF/s", "cores": int(threads), "kind": "oracle",
+            "sample": "first elements of the same mesh per order (" + ", ".join(samples) + f"), {t_tot:.1f} s"}, errs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--ps", default="2,4,6,8,10")
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus must be 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2606_20917_amd import nir
+    nir.lib()
+    ps = [int(p) for p in args.ps.split(",")]
+    cases = [setup(P, args.dtype) for P in ps]
+    stream = torch.cuda.current_stream()
+
+    def launch(c, it):
+        helm, x, y = c["sets"][it % c["nsets"]]
+        nir.nir_helmholtz_apply(c["b"], c["basis"], nir.geom(None, None, helm), 1.0, x, y, stream)
+
+    for it in range(args.warmup):
+        for c in cases:
+            launch(c, it)
+    torch.cuda.synchronize()
+    ev = {c["P"]: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(args.steps)] for c in cases}
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter()
+    t0.record(stream)
+    for it in range(args.steps):
+        for c in cases:
+            a, b = ev[c["P"]][it]
+            a.record(stream)
+            launch(c, it)
+            b.record(stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall
+    total_ms = t0.elapsed_time(t1)
+    dof_step = sum(c["ne"] * c["P"] ** 3 for c in cases)
+    value = dof_step * args.steps / (total_ms * 1e-3) / 1e9
+    s = 8 if args.dtype == "f64" else 4
+    breakdown = {}
+    for c in cases:
+        ms = sum(a.elapsed_time(b) for a, b in ev[c["P"]]) / args.steps
+        gb = hex_bytes(c["P"], s) * c["ne"] / 1e9
+        breakdown[f"P{c['P']}"] = {"ms": round(ms, 4), "gdofs": round(c["ne"] * c["P"] ** 3 / ms / 1e6, 3),
+                                   "gbs": round(gb / (ms * 1e-3), 1),
+                                   "frac_hbm": round(gb / (ms * 1e-3) / HBM_PEAK_GBS, 4),
+                                   "rotating_sets": c["nsets"]}
+    dom = max(cases, key=lambda c: breakdown[f"P{c['P']}"]["ms"])
+    dms = breakdown[f"P{dom['P']}"]["ms"]
+    achieved = hex_bytes(dom["P"], s) * dom["ne"] / (dms * 1e-3) / 1e9
+    out = {
+        "metric": "Helmholtz apply GDoF/s & %HBM roofline, FP64 vs FP32/mixed, hex P=2-10",
+        "value": round(value, 3), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(total_ms / args.steps, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": "hex_sin32: 32^3 = 32768 curved hexes (sin deformation 0.1), per-point factors, "
+                               "fused Helmholtz lambda=1, P in {" + ",".join(map(str, ps)) + "}, Q=P+1",
+                   "nelmt": cases[0]["ne"], "orders": ps, "kernel": "nir_helmholtz_apply"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"hex Helmholtz P={dom['P']}",
+                     "bytes_per_launch": hex_bytes(dom["P"], s) * dom["ne"]},
+        "breakdown": breakdown,
+        "wall_s": round(wall, 3),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"], errs = cpu_baseline(cases, args.cpu_seconds)
+        out["max_rel_err_vs_oracle"] = {f"P{p}": e for p, e in errs.items()}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

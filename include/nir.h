@@ -1,0 +1,190 @@
+/*
+ * nir.h - C ABI of the MI355X matrix-free spectral/hp operator library (libnir.so).
+ *
+ * The library evaluates the elemental operators of the spectral/hp element
+ * method on batches ("blocks") of alike elements - hexahedra, prisms and
+ * tetrahedra with a modified C0 Jacobi basis - and composes them into the
+ * Helmholtz operator H = L + lambda M.  The paper's statement of the problem
+ * (section 3.1: a block of elements sharing shape, order, quadrature and a
+ * deformed flag; operators that take basis/weight/derivative tensors and
+ * produce a new block materialised into a caller's destination) is mirrored
+ * by: a batch descriptor, library-owned basis tables, caller-owned geometry,
+ * and distinct input and output buffers.
+ *
+ * Conventions shared by every call:
+ *  - Pointers named "device" are device pointers (hipMalloc'd or torch CUDA
+ *    tensors); pointers named "host" are ordinary host memory.  The caller
+ *    owns every data array; the library owns only the opaque handles it
+ *    creates (nir_basis, nir_mixed_plan, nir_cg_plan) and what they hold.
+ *  - P is the number of modes per direction (polynomial order P-1), 2..10.
+ *    Q is the number of quadrature points per direction; only Q = P+1 is
+ *    supported by the kernels (NIR_ENOTSUP otherwise).
+ *  - Modes of an element are stored contiguously, p outermost, r fastest,
+ *    over the shape's mode set (hex p,q,r < P; prism r < P-p; tet q < P-p,
+ *    r < P-p-q): the packed order of the tet map, section 2.2 eq. (18),
+ *    read lexicographically.  M = nir_nmodes(shape, P).
+ *  - Quadrature values are stored [elem][i][j][k], k fastest, npts = Q^3.
+ *  - Geometry is stored SoA within an element: [elem][component][npts], or
+ *    [elem][component] when the batch is not deformed (affine elements).
+ *  - Every call validates its arguments on the host before any launch and
+ *    returns NIR_EINVAL / NIR_ENOTSUP without touching the device; a failed
+ *    launch returns NIR_EHIP.  nir_last_error() explains the last failure of
+ *    the calling thread.  No C++ exception crosses the ABI.
+ *  - Device work is enqueued on `stream` (a hipStream_t; NULL = the null
+ *    stream) and is asynchronous; only nir_cg_solve and the *_create calls
+ *    synchronise.  Inputs and outputs must not alias.
+ *  - nelmt == 0 is valid and enqueues nothing.
+ */
+#ifndef NIR_H
+#define NIR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NIR_OK = 0,
+  NIR_EINVAL = 1,      /* invalid argument (null/misaligned pointer, bad size, aliasing) */
+  NIR_ENOTSUP = 2,     /* valid but unsupported combination (e.g. Q != P+1) */
+  NIR_ENOMEM = 3,      /* device or host allocation failed */
+  NIR_EHIP = 4,        /* a HIP runtime call or kernel launch failed */
+  NIR_ENONFINITE = 5,  /* NaN/Inf met in a solver input or iterate */
+  NIR_EBREAKDOWN = 6,  /* CG breakdown (p^T A p <= 0) */
+  NIR_ENOCONV = 7      /* iteration limit reached before the tolerance */
+} nir_status;
+
+typedef enum { NIR_HEX = 0, NIR_PRISM = 1, NIR_TET = 2 } nir_shape;
+typedef enum { NIR_F64 = 0, NIR_F32 = 1 } nir_dtype;               /* storage of coef/phys/geom */
+typedef enum { NIR_MATH_NATIVE = 0, NIR_MATH_F16SPLIT = 1 } nir_math; /* contraction arithmetic */
+
+/* A block of alike elements (paper section 3.1.1, the block type: shape,
+ * basis/quadrature, Deformed flag, Size).  Enum-valued fields are int32_t
+ * so that the layout is fixed. */
+typedef struct {
+  int32_t shape;     /* nir_shape */
+  int32_t nmodes;    /* P, modes per direction, 2..10 */
+  int32_t nquad;     /* Q, points per direction (must be P+1) */
+  int32_t deformed;  /* 1: geometric factors per quadrature point; 0: per element */
+  int64_t nelmt;     /* number of elements, >= 0 */
+  int32_t dtype;     /* nir_dtype of coefficient, quadrature and geometry arrays */
+  int32_t math;      /* nir_math: NIR_MATH_F16SPLIT only with NIR_F32 */
+} nir_batch;
+
+/* Number of modes per element: P^3 (hex), P^2(P+1)/2 (prism), P(P+1)(P+2)/6 (tet); -1 if invalid. */
+int64_t nir_nmodes(int32_t shape, int32_t P);
+
+/* Thread-local description of the last non-OK status returned on this thread. */
+const char* nir_last_error(void);
+
+/* Library version string. */
+const char* nir_version(void);
+
+/* ------------------------------------------------------------------ tables
+ * 1-D quadrature on [-1,1] (host, no device needed).  rule 0: Gauss-Lobatto-
+ * Legendre; rule 1: Gauss-Radau-Jacobi including x = -1 for the weight
+ * (1-x)^alpha (alpha = 0, 1, 2).  Paper section 2.2 (collapsed directions
+ * avoid the singular end point).  z, w: host arrays of Q doubles. */
+nir_status nir_quadrature_host(int32_t rule, int32_t alpha, int32_t Q, double* z, double* w);
+
+/* Identifiers of the per-(shape,P,Q) tables the kernels use (host copies via
+ * nir_table_host).  Sizes in doubles (or int32 for the index tables):
+ *  Z1,Z2,Z3 [Q]       points per direction (eta coordinates; eta = xi for the hex)
+ *  W1,W2,W3 [Q]       weights per direction, collapse factors 1/2, 1/4 included
+ *  T1,DT1   [P][Q]    direction-1 factor psi^a_p(eta_1i) and its derivative
+ *  T2,DT2   [NP][Q]   direction-2 factor per (p,q) pair: psi^a_q (hex, prism) or psi^b_pq (tet)
+ *  T3,DT3   [M][Q]    direction-3 factor per mode: psi^a_r, psi^b_pr (prism), psi^b_{p+q,r} (tet)
+ *  D1,D2,D3 [Q][Q]    collocation derivative matrices D[i][l] = h_l'(z_i), section 2.2 eq. (22)
+ *  WQ       [Q^3]     reference weight of each point (w1 w2 w3)
+ *  XI       [3][Q^3]  reference coordinates xi of each point
+ *  MODE_PQR [M][3]    int32: (p,q,r) of each mode                     (index table)
+ *  POINT_IJK[Q^3][3]  int32: (i,j,k) of each point                    (index table)
+ *  PAIR     [NP][4]   int32: (p, q, first mode m(p,q,0), count of r) of each (p,q) pair
+ * NP = P^2 for hex and prism, P(P+1)/2 for the tet. */
+typedef enum {
+  NIR_TAB_Z1 = 0, NIR_TAB_Z2, NIR_TAB_Z3, NIR_TAB_W1, NIR_TAB_W2, NIR_TAB_W3,
+  NIR_TAB_T1, NIR_TAB_DT1, NIR_TAB_T2, NIR_TAB_DT2, NIR_TAB_T3, NIR_TAB_DT3,
+  NIR_TAB_D1, NIR_TAB_D2, NIR_TAB_D3, NIR_TAB_WQ, NIR_TAB_XI,
+  NIR_TAB_MODE_PQR, NIR_TAB_POINT_IJK, NIR_TAB_PAIR, NIR_TAB_COUNT
+} nir_table_id;
+
+/* Number of elements of table `id` for (shape, P, Q); -1 if invalid. */
+int64_t nir_table_size(int32_t shape, int32_t P, int32_t Q, int32_t id);
+
+/* Copy table `id` into `out` (host; double* for FP tables, int32_t* for index tables;
+ * `out` must hold nir_table_size() elements).  Host only, no device needed. */
+nir_status nir_table_host(int32_t shape, int32_t P, int32_t Q, int32_t id, void* out);
+
+/* Library-owned device copies of every table of (shape, P, Q) in FP64 and FP32. */
+typedef struct nir_basis nir_basis;
+nir_status nir_basis_create(int32_t shape, int32_t P, int32_t Q, nir_basis** out);
+nir_status nir_basis_destroy(nir_basis* basis);
+/* Device pointer of table `id` inside the handle (FP64, or int32 for index tables). */
+const void* nir_basis_table_device(const nir_basis* basis, int32_t id);
+
+/* ------------------------------------------------------------------ geometry
+ * Caller-owned device geometry of a batch.  Paper section 2.1: W holds the
+ * quadrature weight times det J (text after eq. (8)); PhysDeriv needs
+ * d xi_j / d x_i at each point (eq. (9)).  npts = Q^3 if deformed, else 1.
+ *   dxi_dx [nelmt][9][npts]  component 3a+i = d xi_a / d x_i
+ *   jac    [nelmt][npts]     det J
+ *   helm   [nelmt][7][npts]  fused Helmholtz factors: G_ab (ab = 00,01,02,11,12,22)
+ *                            and Jw, with G_ab = Jw sum_i (d xi_a/d x_i)(d xi_b/d x_i),
+ *                            Jw = det J * w_n (deformed) or det J (affine: the
+ *                            kernels multiply by the point weight w_n).
+ * Element type follows nir_batch.dtype.  Pointers not needed by a call may be NULL. */
+typedef struct {
+  const void* dxi_dx;
+  const void* jac;
+  const void* helm;
+} nir_geom;
+
+typedef enum { NIR_MAP_VERTEX = 0, NIR_MAP_VERTEX_SIN = 1 } nir_map;
+
+/* FP64 geometric factors on the GPU from element vertices (device, [nelmt][nv][3]).
+ * Reference vertices, in storage order:
+ *   hex   (nv=8): (-1,-1,-1) (1,-1,-1) (1,1,-1) (-1,1,-1) (-1,-1,1) (1,-1,1) (1,1,1) (-1,1,1)
+ *   prism (nv=6): (-1,-1,-1) (1,-1,-1) (1,1,-1) (-1,1,-1) (-1,-1,1) (-1,1,1)
+ *   tet   (nv=4): (-1,-1,-1) (1,-1,-1) (-1,1,-1) (-1,-1,1)
+ * Map: trilinear hex / linear-triangle x linear prism / affine tet of the vertices; with
+ * NIR_MAP_VERTEX_SIN every component is then moved by amp*sin(2 pi x)sin(2 pi y)sin(2 pi z).
+ * Outputs (device, FP64, any may be NULL): dxi_dx, jac, helm64 with npts as above;
+ * helm32 (FP32, optional) = round-to-nearest copy of helm64.  The batch dtype is
+ * ignored (geometry is always computed in FP64).  det J is not checked on the device:
+ * the caller's mesh must be orientation preserving at every quadrature point. */
+nir_status nir_geom_from_vertices(const nir_batch* batch, const nir_basis* basis, const double* verts,
+                                  int32_t map, double amp, double* dxi_dx, double* jac,
+                                  double* helm64, float* helm32, void* stream);
+
+/* ------------------------------------------------------------------ operators
+ * BwdTrans u = B u^ (section 2.2, eqs. (14)-(17)): coef [nelmt][M] -> phys [nelmt][Q^3]. */
+nir_status nir_bwd_trans(const nir_batch* batch, const nir_basis* basis, const void* coef,
+                         void* phys, void* stream);
+
+/* PhysDeriv d_i = sum_j (d xi_j/d x_i) D_xi_j u (eq. (9), with the eta-to-xi chain rule
+ * of eq. (23) for collapsed shapes): phys [nelmt][Q^3] -> d0, d1, d2 [nelmt][Q^3].
+ * Uses geom->dxi_dx. */
+nir_status nir_phys_deriv(const nir_batch* batch, const nir_basis* basis, const nir_geom* geom,
+                          const void* phys, void* d0, void* d1, void* d2, void* stream);
+
+/* IProductWRTBase u^ = B^T W f (eqs. (19)-(21)): phys [nelmt][Q^3] -> coef [nelmt][M].
+ * Uses geom->jac (W = w_n det J). */
+nir_status nir_iprod_wrt_base(const nir_batch* batch, const nir_basis* basis, const nir_geom* geom,
+                              const void* phys, void* coef, void* stream);
+
+/* IProductWRTDerivBase u^ = sum_i (D_{x_i} B)^T W f_i (the test_grad operation, section 3.1.2;
+ * with eq. (7)): f0, f1, f2 [nelmt][Q^3] -> coef [nelmt][M].  Uses geom->dxi_dx and geom->jac. */
+nir_status nir_iprod_wrt_deriv_base(const nir_batch* batch, const nir_basis* basis, const nir_geom* geom,
+                                    const void* f0, const void* f1, const void* f2, void* coef,
+                                    void* stream);
+
+/* Fused Helmholtz y = (L + lambda M) u^ (section 2.1, eqs. (6), (7)) with every intermediate
+ * on chip: coef_in [nelmt][M] -> coef_out [nelmt][M].  Uses geom->helm only. */
+nir_status nir_helmholtz_apply(const nir_batch* batch, const nir_basis* basis, const nir_geom* geom,
+                               double lambda, const void* coef_in, void* coef_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NIR_H */

@@ -1,0 +1,375 @@
+// Public C ABI of libnir: argument validation (host only, before any launch),
+// handle management and dispatch to the kernels.
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "nir_internal.h"
+
+namespace nir {
+
+static thread_local char g_err[512] = "";
+
+nir_status fail(nir_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return s;
+}
+nir_status ok() { return NIR_OK; }
+nir_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return NIR_OK;
+  return fail(NIR_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- validation
+static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+static nir_status check_batch(const nir_batch* b, const nir_basis* basis) {
+  if (!b) return fail(NIR_EINVAL, "batch descriptor is NULL");
+  if (b->shape < kHex || b->shape > kTet) return fail(NIR_EINVAL, "invalid shape %d", b->shape);
+  if (b->nmodes < kMinP || b->nmodes > kMaxP)
+    return fail(NIR_EINVAL, "nmodes P=%d outside [%d, %d]", b->nmodes, kMinP, kMaxP);
+  if (b->nquad < b->nmodes) return fail(NIR_EINVAL, "nquad Q=%d < P=%d", b->nquad, b->nmodes);
+  if (b->nquad != b->nmodes + 1) return fail(NIR_ENOTSUP, "only Q = P+1 is supported (Q=%d, P=%d)", b->nquad, b->nmodes);
+  if (b->nelmt < 0) return fail(NIR_EINVAL, "nelmt=%lld < 0", (long long)b->nelmt);
+  if (b->deformed != 0 && b->deformed != 1) return fail(NIR_EINVAL, "deformed must be 0 or 1");
+  if (b->dtype != NIR_F64 && b->dtype != NIR_F32) return fail(NIR_EINVAL, "invalid dtype %d", b->dtype);
+  if (b->math != NIR_MATH_NATIVE && b->math != NIR_MATH_F16SPLIT) return fail(NIR_EINVAL, "invalid math %d", b->math);
+  if (b->math == NIR_MATH_F16SPLIT && b->dtype != NIR_F32)
+    return fail(NIR_EINVAL, "F16-split contractions need FP32 storage");
+  if (!basis) return fail(NIR_EINVAL, "basis handle is NULL");
+  if (basis->shape != b->shape || basis->P != b->nmodes || basis->Q != b->nquad)
+    return fail(NIR_EINVAL, "basis (shape %d, P %d, Q %d) does not match the batch (shape %d, P %d, Q %d)",
+                basis->shape, basis->P, basis->Q, b->shape, b->nmodes, b->nquad);
+  return NIR_OK;
+}
+
+static size_t elem_size(const nir_batch* b) { return b->dtype == NIR_F64 ? 8 : 4; }
+
+static nir_status check_ptr(const nir_batch* b, const void* p, const char* name) {
+  if (!p) return fail(NIR_EINVAL, "%s is NULL", name);
+  if (!aligned(p, elem_size(b))) return fail(NIR_EINVAL, "%s is not %zu-byte aligned", name, elem_size(b));
+  return NIR_OK;
+}
+
+// [p, p+n) and [q, q+m) overlap?
+static bool overlap(const void* p, size_t n, const void* q, size_t m) {
+  const char* a = static_cast<const char*>(p);
+  const char* c = static_cast<const char*>(q);
+  return a < c + m && c < a + n;
+}
+
+#define NIR_TRY(x)                  \
+  do {                              \
+    nir_status _s = (x);            \
+    if (_s != NIR_OK) return _s;    \
+  } while (0)
+
+static nir_status check_geom(const nir_batch* b, const nir_geom* g, bool need_dxi, bool need_jac, bool need_helm) {
+  if (!g) return fail(NIR_EINVAL, "geometry descriptor is NULL");
+  if (need_dxi) NIR_TRY(check_ptr(b, g->dxi_dx, "geom->dxi_dx"));
+  if (need_jac) NIR_TRY(check_ptr(b, g->jac, "geom->jac"));
+  if (need_helm) NIR_TRY(check_ptr(b, g->helm, "geom->helm"));
+  return NIR_OK;
+}
+
+}  // namespace nir
+
+using namespace nir;
+
+extern "C" {
+
+int64_t nir_nmodes(int32_t shape, int32_t P) {
+  if (P < 1) return -1;
+  return modes_of(shape, P);
+}
+
+const char* nir_last_error(void) { return g_err; }
+
+const char* nir_version(void) { return "libnir 0.1 (gfx950)"; }
+
+nir_status nir_quadrature_host(int32_t rule, int32_t alpha, int32_t Q, double* z, double* w) {
+  if (!z || !w) return fail(NIR_EINVAL, "z or w is NULL");
+  if (Q < 1 || Q > 64) return fail(NIR_EINVAL, "Q=%d outside [1, 64]", Q);
+  if (!quadrature_1d(rule, alpha, Q, z, w)) return fail(NIR_EINVAL, "invalid rule %d / alpha %d / Q %d", rule, alpha, Q);
+  return NIR_OK;
+}
+
+int64_t nir_table_size(int32_t shape, int32_t P, int32_t Q, int32_t id) {
+  if (shape < kHex || shape > kTet || P < 1 || P > 16 || Q < 2 || Q > 17) return -1;
+  const int64_t M = modes_of(shape, P), NP = pairs_of(shape, P), NQ = int64_t(Q) * Q * Q;
+  switch (id) {
+    case NIR_TAB_Z1: case NIR_TAB_Z2: case NIR_TAB_Z3:
+    case NIR_TAB_W1: case NIR_TAB_W2: case NIR_TAB_W3: return Q;
+    case NIR_TAB_T1: case NIR_TAB_DT1: return int64_t(P) * Q;
+    case NIR_TAB_T2: case NIR_TAB_DT2: return NP * Q;
+    case NIR_TAB_T3: case NIR_TAB_DT3: return M * Q;
+    case NIR_TAB_D1: case NIR_TAB_D2: case NIR_TAB_D3: return int64_t(Q) * Q;
+    case NIR_TAB_WQ: return NQ;
+    case NIR_TAB_XI: return 3 * NQ;
+    case NIR_TAB_MODE_PQR: return 3 * M;
+    case NIR_TAB_POINT_IJK: return 3 * NQ;
+    case NIR_TAB_PAIR: return 4 * NP;
+    default: return -1;
+  }
+}
+
+nir_status nir_table_host(int32_t shape, int32_t P, int32_t Q, int32_t id, void* out) {
+  if (!out) return fail(NIR_EINVAL, "out is NULL");
+  if (nir_table_size(shape, P, Q, id) < 0) return fail(NIR_EINVAL, "invalid table request");
+  HostTables t;
+  if (!build_tables(shape, P, Q, t)) return fail(NIR_EINVAL, "cannot build tables for shape %d P %d Q %d", shape, P, Q);
+  int64_t n;
+  bool is_int;
+  const void* src = host_table(t, id, &n, &is_int);
+  if (!src) return fail(NIR_EINVAL, "invalid table id %d", id);
+  std::memcpy(out, src, size_t(n) * (is_int ? 4 : 8));
+  return NIR_OK;
+}
+
+nir_status nir_basis_create(int32_t shape, int32_t P, int32_t Q, nir_basis** out) {
+  if (!out) return fail(NIR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (shape < kHex || shape > kTet) return fail(NIR_EINVAL, "invalid shape %d", shape);
+  if (P < kMinP || P > kMaxP) return fail(NIR_EINVAL, "P=%d outside [%d, %d]", P, kMinP, kMaxP);
+  if (Q != P + 1) return fail(NIR_ENOTSUP, "only Q = P+1 is supported");
+  nir_basis* b = new (std::nothrow) nir_basis();
+  if (!b) return fail(NIR_ENOMEM, "host allocation failed");
+  b->shape = shape;
+  b->P = P;
+  b->Q = Q;
+  if (!build_tables(shape, P, Q, b->host)) {
+    delete b;
+    return fail(NIR_EINVAL, "cannot build tables");
+  }
+  b->M = b->host.M;
+  b->NP = b->host.NP;
+  // pack FP tables contiguously (FP64 and FP32), index tables separately
+  size_t total = 0;
+  int64_t cnt[NIR_TAB_COUNT];
+  size_t off[NIR_TAB_COUNT];
+  bool isint[NIR_TAB_COUNT];
+  for (int id = 0; id < NIR_TAB_COUNT; ++id) host_table(b->host, id, &cnt[id], &isint[id]);
+  size_t fp_total = 0, int_total = 0;
+  for (int id = 0; id < NIR_TAB_COUNT; ++id) {
+    if (isint[id]) {
+      off[id] = int_total;
+      int_total += size_t(cnt[id]);
+    } else {
+      off[id] = fp_total;
+      fp_total += size_t((cnt[id] + 1) / 2 * 2);   // keep FP32 copies 8-byte aligned
+    }
+  }
+  (void)total;
+  std::vector<double> h64(fp_total, 0.0);
+  std::vector<float> h32(fp_total, 0.0f);
+  std::vector<int32_t> hint(int_total, 0);
+  for (int id = 0; id < NIR_TAB_COUNT; ++id) {
+    int64_t n;
+    bool ii;
+    const void* src = host_table(b->host, id, &n, &ii);
+    if (ii) {
+      std::memcpy(hint.data() + off[id], src, size_t(n) * 4);
+    } else {
+      const double* s = static_cast<const double*>(src);
+      for (int64_t k = 0; k < n; ++k) {
+        h64[off[id] + k] = s[k];
+        h32[off[id] + k] = float(s[k]);
+      }
+    }
+  }
+  nir_status st = NIR_OK;
+  if ((st = hip_check(hipMalloc(&b->dev64, fp_total * 8), "hipMalloc tables")) != NIR_OK ||
+      (st = hip_check(hipMalloc(&b->dev32, fp_total * 4), "hipMalloc tables")) != NIR_OK ||
+      (st = hip_check(hipMalloc(&b->devint, int_total * 4), "hipMalloc tables")) != NIR_OK ||
+      (st = hip_check(hipMemcpy(b->dev64, h64.data(), fp_total * 8, hipMemcpyHostToDevice), "copy tables")) != NIR_OK ||
+      (st = hip_check(hipMemcpy(b->dev32, h32.data(), fp_total * 4, hipMemcpyHostToDevice), "copy tables")) != NIR_OK ||
+      (st = hip_check(hipMemcpy(b->devint, hint.data(), int_total * 4, hipMemcpyHostToDevice), "copy tables")) != NIR_OK) {
+    nir_basis_destroy(b);
+    return st;
+  }
+  const double* d64 = static_cast<const double*>(b->dev64);
+  const float* d32 = static_cast<const float*>(b->dev32);
+  const int32_t* di = static_cast<const int32_t*>(b->devint);
+  for (int id = 0; id < NIR_TAB_COUNT; ++id)
+    b->table_dev[id] = isint[id] ? static_cast<const void*>(di + off[id]) : static_cast<const void*>(d64 + off[id]);
+  auto fill = [&](auto& t, auto base) {
+    for (int d = 0; d < 3; ++d) {
+      t.z[d] = base + off[NIR_TAB_Z1 + d];
+      t.w[d] = base + off[NIR_TAB_W1 + d];
+      t.D[d] = base + off[NIR_TAB_D1 + d];
+    }
+    t.T1 = base + off[NIR_TAB_T1];
+    t.dT1 = base + off[NIR_TAB_DT1];
+    t.T2 = base + off[NIR_TAB_T2];
+    t.dT2 = base + off[NIR_TAB_DT2];
+    t.T3 = base + off[NIR_TAB_T3];
+    t.dT3 = base + off[NIR_TAB_DT3];
+    t.wq = base + off[NIR_TAB_WQ];
+    t.xi = base + off[NIR_TAB_XI];
+    t.pair = di + off[NIR_TAB_PAIR];
+    t.mode_pqr = di + off[NIR_TAB_MODE_PQR];
+  };
+  fill(b->t64, d64);
+  fill(b->t32, d32);
+  *out = b;
+  return NIR_OK;
+}
+
+nir_status nir_basis_destroy(nir_basis* b) {
+  if (!b) return NIR_OK;
+  if (b->dev64) (void)hipFree(b->dev64);
+  if (b->dev32) (void)hipFree(b->dev32);
+  if (b->devint) (void)hipFree(b->devint);
+  delete b;
+  return NIR_OK;
+}
+
+const void* nir_basis_table_device(const nir_basis* b, int32_t id) {
+  if (!b || id < 0 || id >= NIR_TAB_COUNT) return nullptr;
+  return b->table_dev[id];
+}
+
+nir_status nir_geom_from_vertices(const nir_batch* batch, const nir_basis* basis, const double* verts,
+                                  int32_t map, double amp, double* dxi_dx, double* jac, double* helm64,
+                                  float* helm32, void* stream) {
+  NIR_TRY(check_batch(batch, basis));
+  if (map != NIR_MAP_VERTEX && map != NIR_MAP_VERTEX_SIN) return fail(NIR_EINVAL, "invalid map %d", map);
+  if (batch->nelmt == 0) return NIR_OK;
+  if (!verts || !aligned(verts, 8)) return fail(NIR_EINVAL, "verts is NULL or misaligned");
+  if (!dxi_dx && !jac && !helm64 && !helm32) return fail(NIR_EINVAL, "no output requested");
+  for (const void* p : {(const void*)dxi_dx, (const void*)jac, (const void*)helm64})
+    if (p && !aligned(p, 8)) return fail(NIR_EINVAL, "geometry output misaligned");
+  if (helm32 && !aligned(helm32, 4)) return fail(NIR_EINVAL, "helm32 misaligned");
+  if (map == NIR_MAP_VERTEX_SIN && batch->deformed == 0)
+    return fail(NIR_EINVAL, "the sin deformation is not affine: use deformed = 1");
+  return launch_geom(basis, batch->deformed, batch->nelmt, verts, map, map == NIR_MAP_VERTEX_SIN ? amp : 0.0,
+                     dxi_dx, jac, helm64, helm32, static_cast<hipStream_t>(stream));
+}
+
+nir_status nir_bwd_trans(const nir_batch* b, const nir_basis* basis, const void* coef, void* phys, void* stream) {
+  NIR_TRY(check_batch(b, basis));
+  if (b->nelmt == 0) return NIR_OK;
+  NIR_TRY(check_ptr(b, coef, "coef"));
+  NIR_TRY(check_ptr(b, phys, "phys"));
+  const size_t es = elem_size(b), n = size_t(b->nelmt);
+  if (overlap(coef, n * basis->M * es, phys, n * basis->Q * basis->Q * basis->Q * es))
+    return fail(NIR_EINVAL, "coef and phys overlap");
+  OpArgs a{};
+  a.in0 = coef;
+  a.out0 = phys;
+  a.nelmt = b->nelmt;
+  return launch_generic(basis, kOpBwd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+}
+
+nir_status nir_iprod_wrt_base(const nir_batch* b, const nir_basis* basis, const nir_geom* g, const void* phys,
+                              void* coef, void* stream) {
+  NIR_TRY(check_batch(b, basis));
+  if (b->nelmt == 0) return NIR_OK;
+  NIR_TRY(check_geom(b, g, false, true, false));
+  NIR_TRY(check_ptr(b, phys, "phys"));
+  NIR_TRY(check_ptr(b, coef, "coef"));
+  const size_t es = elem_size(b), n = size_t(b->nelmt), nq = size_t(basis->Q) * basis->Q * basis->Q;
+  if (overlap(coef, n * basis->M * es, phys, n * nq * es) ||
+      overlap(coef, n * basis->M * es, g->jac, n * (b->deformed ? nq : 1) * es))
+    return fail(NIR_EINVAL, "output coef overlaps an input");
+  OpArgs a{};
+  a.in0 = phys;
+  a.out0 = coef;
+  a.jac = g->jac;
+  a.nelmt = b->nelmt;
+  return launch_generic(basis, kOpIProd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+}
+
+nir_status nir_phys_deriv(const nir_batch* b, const nir_basis* basis, const nir_geom* g, const void* phys,
+                          void* d0, void* d1, void* d2, void* stream) {
+  NIR_TRY(check_batch(b, basis));
+  if (b->nelmt == 0) return NIR_OK;
+  NIR_TRY(check_geom(b, g, true, false, false));
+  NIR_TRY(check_ptr(b, phys, "phys"));
+  NIR_TRY(check_ptr(b, d0, "d0"));
+  NIR_TRY(check_ptr(b, d1, "d1"));
+  NIR_TRY(check_ptr(b, d2, "d2"));
+  const size_t es = elem_size(b), n = size_t(b->nelmt), nq = size_t(basis->Q) * basis->Q * basis->Q;
+  const size_t fb = n * nq * es;
+  const void* outs[3] = {d0, d1, d2};
+  for (int i = 0; i < 3; ++i) {
+    if (overlap(outs[i], fb, phys, fb) || overlap(outs[i], fb, g->dxi_dx, n * 9 * (b->deformed ? nq : 1) * es))
+      return fail(NIR_EINVAL, "output d%d overlaps an input", i);
+    for (int j = 0; j < i; ++j)
+      if (overlap(outs[i], fb, outs[j], fb)) return fail(NIR_EINVAL, "outputs d%d and d%d overlap", j, i);
+  }
+  OpArgs a{};
+  a.in0 = phys;
+  a.out0 = d0;
+  a.out1 = d1;
+  a.out2 = d2;
+  a.dxi_dx = g->dxi_dx;
+  a.nelmt = b->nelmt;
+  return launch_generic(basis, kOpPhysDeriv, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+}
+
+nir_status nir_iprod_wrt_deriv_base(const nir_batch* b, const nir_basis* basis, const nir_geom* g,
+                                    const void* f0, const void* f1, const void* f2, void* coef, void* stream) {
+  NIR_TRY(check_batch(b, basis));
+  if (b->nelmt == 0) return NIR_OK;
+  NIR_TRY(check_geom(b, g, true, true, false));
+  NIR_TRY(check_ptr(b, f0, "f0"));
+  NIR_TRY(check_ptr(b, f1, "f1"));
+  NIR_TRY(check_ptr(b, f2, "f2"));
+  NIR_TRY(check_ptr(b, coef, "coef"));
+  const size_t es = elem_size(b), n = size_t(b->nelmt), nq = size_t(basis->Q) * basis->Q * basis->Q;
+  const size_t cb = n * basis->M * es;
+  for (const void* in : {f0, f1, f2})
+    if (overlap(coef, cb, in, n * nq * es)) return fail(NIR_EINVAL, "coef overlaps an input field");
+  if (overlap(coef, cb, g->dxi_dx, n * 9 * (b->deformed ? nq : 1) * es) ||
+      overlap(coef, cb, g->jac, n * (b->deformed ? nq : 1) * es))
+    return fail(NIR_EINVAL, "coef overlaps the geometry");
+  OpArgs a{};
+  a.in0 = f0;
+  a.in1 = f1;
+  a.in2 = f2;
+  a.out0 = coef;
+  a.dxi_dx = g->dxi_dx;
+  a.jac = g->jac;
+  a.nelmt = b->nelmt;
+  return launch_generic(basis, kOpIProdDeriv, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+}
+
+nir_status nir_helmholtz_apply(const nir_batch* b, const nir_basis* basis, const nir_geom* g, double lambda,
+                               const void* coef_in, void* coef_out, void* stream) {
+  NIR_TRY(check_batch(b, basis));
+  if (b->nelmt == 0) return NIR_OK;
+  NIR_TRY(check_geom(b, g, false, false, true));
+  NIR_TRY(check_ptr(b, coef_in, "coef_in"));
+  NIR_TRY(check_ptr(b, coef_out, "coef_out"));
+  const size_t es = elem_size(b), n = size_t(b->nelmt), nq = size_t(basis->Q) * basis->Q * basis->Q;
+  const size_t cb = n * basis->M * es;
+  if (overlap(coef_out, cb, coef_in, cb)) return fail(NIR_EINVAL, "coef_in and coef_out overlap");
+  if (overlap(coef_out, cb, g->helm, n * 7 * (b->deformed ? nq : 1) * es))
+    return fail(NIR_EINVAL, "coef_out overlaps the geometry");
+  if (!(lambda == lambda)) return fail(NIR_EINVAL, "lambda is NaN");
+  OpArgs a{};
+  a.in0 = coef_in;
+  a.out0 = coef_out;
+  a.helm = g->helm;
+  a.lambda = lambda;
+  a.nelmt = b->nelmt;
+  return launch_generic(basis, kOpHelm, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+namespace nir {
+nir_status launch_generic(const nir_basis* b, int op, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
+  switch (b->shape) {
+    case kHex: return launch_generic_hex(b, op, dtype, deformed, a, s);
+    case kPrism: return launch_generic_prism(b, op, dtype, deformed, a, s);
+    case kTet: return launch_generic_tet(b, op, dtype, deformed, a, s);
+    default: return fail(NIR_EINVAL, "invalid shape");
+  }
+}
+}  // namespace nir

@@ -1,0 +1,173 @@
+// Geometric factors in FP64 on the GPU from element vertices.
+//
+// Paper section 2.1: the weights matrix W is the quadrature weight times the
+// Jacobian determinant (text after eq. (8)) and the physical derivative needs
+// d xi_j / d x_i at every point (eq. (9)).  The element map is the vertex map
+// of the shape (trilinear hex, linear-triangle x linear prism, affine tet),
+// optionally followed by x_d += amp * sin(2 pi x) sin(2 pi y) sin(2 pi z).
+// One thread per (element, point); outputs are SoA per element, so a wave
+// writes consecutive points of one component (coalesced).
+
+#include "nir_internal.h"
+
+namespace nir {
+namespace {
+
+template <int SHAPE>
+__device__ __forceinline__ void shape_fn(double x1, double x2, double x3, double N[8], double dN[8][3]) {
+  if (SHAPE == kHex) {
+    const double s[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                            {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const double f1 = 0.5 * (1.0 + s[v][0] * x1), f2 = 0.5 * (1.0 + s[v][1] * x2), f3 = 0.5 * (1.0 + s[v][2] * x3);
+      N[v] = f1 * f2 * f3;
+      dN[v][0] = 0.5 * s[v][0] * f2 * f3;
+      dN[v][1] = 0.5 * s[v][1] * f1 * f3;
+      dN[v][2] = 0.5 * s[v][2] * f1 * f2;
+    }
+  } else if (SHAPE == kPrism) {
+    const double l[3] = {-0.5 * (x1 + x3), 0.5 * (1.0 + x1), 0.5 * (1.0 + x3)};
+    const double dl[3][3] = {{-0.5, 0.0, -0.5}, {0.5, 0.0, 0.0}, {0.0, 0.0, 0.5}};
+    const double g[2] = {0.5 * (1.0 - x2), 0.5 * (1.0 + x2)};
+    const double dg[2] = {-0.5, 0.5};
+    const int tri[6] = {0, 1, 1, 0, 2, 2}, lin[6] = {0, 0, 1, 1, 0, 1};
+#pragma unroll
+    for (int v = 0; v < 6; ++v) {
+      const int a = tri[v], b = lin[v];
+      N[v] = l[a] * g[b];
+      dN[v][0] = dl[a][0] * g[b];
+      dN[v][1] = l[a] * dg[b];
+      dN[v][2] = dl[a][2] * g[b];
+    }
+  } else {
+    N[0] = -0.5 * (1.0 + x1 + x2 + x3);
+    N[1] = 0.5 * (1.0 + x1);
+    N[2] = 0.5 * (1.0 + x2);
+    N[3] = 0.5 * (1.0 + x3);
+    const double d[4][3] = {{-0.5, -0.5, -0.5}, {0.5, 0, 0}, {0, 0.5, 0}, {0, 0, 0.5}};
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      for (int c = 0; c < 3; ++c) dN[v][c] = d[v][c];
+  }
+}
+
+template <int SHAPE>
+__global__ void __launch_bounds__(256) k_geom(const double* __restrict__ verts, int64_t nelmt, int npts,
+                                              const double* __restrict__ xi, const double* __restrict__ wq, int NQ,
+                                              double amp, double* __restrict__ dxi_dx, double* __restrict__ jac,
+                                              double* __restrict__ helm64, float* __restrict__ helm32) {
+  constexpr int NV = SHAPE == kHex ? 8 : (SHAPE == kPrism ? 6 : 4);
+  const int64_t total = nelmt * npts;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t e = t / npts;
+    const int n = int(t - e * npts);
+    double r1, r2, r3, w;
+    if (npts == NQ) {
+      r1 = xi[n];
+      r2 = xi[NQ + n];
+      r3 = xi[2 * NQ + n];
+      w = wq[n];
+    } else {   // affine batch: constant Jacobian, evaluated at the reference centroid
+      r1 = SHAPE == kHex ? 0.0 : (SHAPE == kPrism ? -1.0 / 3.0 : -0.5);
+      r2 = SHAPE == kTet ? -0.5 : 0.0;
+      r3 = r1;
+      w = 1.0;
+    }
+    double N[8], dN[8][3];
+    shape_fn<SHAPE>(r1, r2, r3, N, dN);
+    double x[3] = {0, 0, 0}, J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    const double* V = verts + e * NV * 3;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double X = V[v * 3 + d];
+        x[d] += N[v] * X;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) J[d][j] += X * dN[v][j];
+      }
+    if (amp != 0.0) {
+      const double tp = 2.0 * M_PI;
+      double sx, cx, sy, cy, sz, cz;
+      sincos(tp * x[0], &sx, &cx);
+      sincos(tp * x[1], &sy, &cy);
+      sincos(tp * x[2], &sz, &cz);
+      const double g[3] = {tp * cx * sy * sz, tp * sx * cy * sz, tp * sx * sy * cz};
+      double gJ[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) gJ[j] = g[0] * J[0][j] + g[1] * J[1][j] + g[2] * J[2][j];
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) J[d][j] += amp * gJ[j];
+    }
+    // inverse by the adjugate: inv[a][i] = d xi_a / d x_i
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const double id = 1.0 / det;
+    double inv[3][3];
+    inv[0][0] = c00 * id;
+    inv[1][0] = c01 * id;
+    inv[2][0] = c02 * id;
+    inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    if (dxi_dx) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) dxi_dx[(e * 9 + 3 * a + i) * npts + n] = inv[a][i];
+    }
+    if (jac) jac[e * npts + n] = det;
+    if (helm64 || helm32) {
+      const double Jw = det * w;
+      double h[7];
+      const int ab[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const int a = ab[c][0], b = ab[c][1];
+        h[c] = Jw * (inv[a][0] * inv[b][0] + inv[a][1] * inv[b][1] + inv[a][2] * inv[b][2]);
+      }
+      h[6] = Jw;
+#pragma unroll
+      for (int c = 0; c < 7; ++c) {
+        if (helm64) helm64[(e * 7 + c) * npts + n] = h[c];
+        if (helm32) helm32[(e * 7 + c) * npts + n] = float(h[c]);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+nir_status launch_geom(const nir_basis* b, int deformed, int64_t nelmt, const double* verts, int map, double amp,
+                       double* dxi_dx, double* jac, double* helm64, float* helm32, hipStream_t s) {
+  (void)map;
+  const int NQ = b->Q * b->Q * b->Q;
+  const int npts = deformed ? NQ : 1;
+  const int64_t total = nelmt * npts;
+  const int64_t nb = (total + 255) / 256;
+  const dim3 grid(unsigned(nb < (1 << 20) ? nb : (1 << 20))), block(256);
+  const double* xi = b->t64.xi;
+  const double* wq = b->t64.wq;
+  switch (b->shape) {
+    case kHex:
+      hipLaunchKernelGGL(k_geom<kHex>, grid, block, 0, s, verts, nelmt, npts, xi, wq, NQ, amp, dxi_dx, jac, helm64, helm32);
+      break;
+    case kPrism:
+      hipLaunchKernelGGL(k_geom<kPrism>, grid, block, 0, s, verts, nelmt, npts, xi, wq, NQ, amp, dxi_dx, jac, helm64, helm32);
+      break;
+    default:
+      hipLaunchKernelGGL(k_geom<kTet>, grid, block, 0, s, verts, nelmt, npts, xi, wq, NQ, amp, dxi_dx, jac, helm64, helm32);
+      break;
+  }
+  return hip_check(hipGetLastError(), "geometry kernel launch");
+}
+
+}  // namespace nir

@@ -1,0 +1,124 @@
+// Internal declarations of libnir: host tables, device table views, the
+// opaque handles and error reporting.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/nir.h"
+
+namespace nir {
+
+constexpr int kHex = 0, kPrism = 1, kTet = 2;
+constexpr int kMinP = 2, kMaxP = 10;
+
+inline int64_t modes_of(int shape, int P) {
+  switch (shape) {
+    case kHex: return int64_t(P) * P * P;
+    case kPrism: return int64_t(P) * P * (P + 1) / 2;
+    case kTet: return int64_t(P) * (P + 1) * (P + 2) / 6;
+    default: return -1;
+  }
+}
+inline int pairs_of(int shape, int P) { return shape == kTet ? P * (P + 1) / 2 : P * P; }
+inline int verts_of(int shape) { return shape == kHex ? 8 : (shape == kPrism ? 6 : 4); }
+
+// ---------------------------------------------------------------- host tables
+// Built on the host in FP64 for one (shape, P, Q); see tables.cpp.
+struct HostTables {
+  int shape = 0, P = 0, Q = 0, M = 0, NP = 0;
+  std::vector<double> z[3], w[3];      // 1-D points (eta) and weights per direction
+  std::vector<double> T1, dT1;         // [P][Q]
+  std::vector<double> T2, dT2;         // [NP][Q]
+  std::vector<double> T3, dT3;         // [M][Q]
+  std::vector<double> D[3];            // [Q][Q]
+  std::vector<double> wq;              // [Q^3]
+  std::vector<double> xi;              // [3][Q^3]
+  std::vector<int32_t> mode_pqr;       // [M][3]
+  std::vector<int32_t> point_ijk;      // [Q^3][3]
+  std::vector<int32_t> pair;           // [NP][4] = (p, q, m0, nr)
+};
+
+// Builds every table; returns false (and sets the error) on invalid input.
+bool build_tables(int shape, int P, int Q, HostTables& t);
+// Pointer/size of table `id` in host tables (FP tables as double, index tables as int32).
+const void* host_table(const HostTables& t, int id, int64_t* count, bool* is_int);
+
+// 1-D rules (rule 0 GLL, rule 1 Gauss-Radau-Jacobi at -1 with weight (1-x)^alpha).
+bool quadrature_1d(int rule, int alpha, int Q, double* z, double* w);
+
+// ---------------------------------------------------------------- device views
+// Plain pointer views of the device copies, passed by value to kernels.
+template <class T>
+struct DevTab {
+  const T* z[3];
+  const T* w[3];
+  const T* T1;
+  const T* dT1;
+  const T* T2;
+  const T* dT2;
+  const T* T3;
+  const T* dT3;
+  const T* D[3];
+  const T* wq;
+  const T* xi;
+  const int32_t* pair;
+  const int32_t* mode_pqr;
+};
+
+}  // namespace nir
+
+struct nir_basis {
+  int shape, P, Q, M, NP;
+  nir::HostTables host;
+  void* dev64 = nullptr;     // FP64 tables (one allocation)
+  void* dev32 = nullptr;     // FP32 copies
+  void* devint = nullptr;    // int32 index tables
+  nir::DevTab<double> t64;
+  nir::DevTab<float> t32;
+  const void* table_dev[NIR_TAB_COUNT];
+};
+
+namespace nir {
+
+// ---------------------------------------------------------------- errors
+nir_status fail(nir_status s, const char* fmt, ...);
+nir_status ok();
+nir_status hip_check(hipError_t e, const char* what);
+
+// ---------------------------------------------------------------- launchers
+// Generic (any shape) operator kernels, one entry per operation; implemented in
+// ops_{hex,prism,tet}.hip.  `a` carries every pointer the op needs.
+struct OpArgs {
+  const void* in0;      // coef or phys or f0
+  const void* in1;      // f1
+  const void* in2;      // f2
+  void* out0;           // phys / coef / d0
+  void* out1;           // d1
+  void* out2;           // d2
+  const void* dxi_dx;
+  const void* jac;
+  const void* helm;
+  double lambda;
+  int64_t nelmt;
+};
+
+enum OpKind { kOpBwd = 0, kOpIProd = 1, kOpPhysDeriv = 2, kOpIProdDeriv = 3, kOpHelm = 4 };
+
+nir_status launch_generic(const nir_basis* b, int op, int dtype, int deformed, const OpArgs& a,
+                          hipStream_t s);
+nir_status launch_generic_hex(const nir_basis* b, int op, int dtype, int deformed, const OpArgs& a,
+                              hipStream_t s);
+nir_status launch_generic_prism(const nir_basis* b, int op, int dtype, int deformed, const OpArgs& a,
+                                hipStream_t s);
+nir_status launch_generic_tet(const nir_basis* b, int op, int dtype, int deformed, const OpArgs& a,
+                              hipStream_t s);
+
+nir_status launch_geom(const nir_basis* b, int deformed, int64_t nelmt, const double* verts, int map,
+                       double amp, double* dxi_dx, double* jac, double* helm64, float* helm32,
+                       hipStream_t s);
+
+}  // namespace nir

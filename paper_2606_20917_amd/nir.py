@@ -1,0 +1,206 @@
+"""Thin ctypes binding of libnir.so (argument marshalling only).
+
+Every function has the name of the C entry point it calls and takes torch
+tensors (or raw integer addresses) where the C ABI takes pointers.  Device
+tensors must be contiguous CUDA/HIP tensors; the current torch stream is
+used unless a stream is given.  Nothing here computes: if the library is
+missing the first call raises, there is no fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libnir.so")
+
+HEX, PRISM, TET = 0, 1, 2
+F64, F32 = 0, 1
+MATH_NATIVE, MATH_F16SPLIT = 0, 1
+MAP_VERTEX, MAP_VERTEX_SIN = 0, 1
+
+(TAB_Z1, TAB_Z2, TAB_Z3, TAB_W1, TAB_W2, TAB_W3, TAB_T1, TAB_DT1, TAB_T2, TAB_DT2, TAB_T3, TAB_DT3,
+ TAB_D1, TAB_D2, TAB_D3, TAB_WQ, TAB_XI, TAB_MODE_PQR, TAB_POINT_IJK, TAB_PAIR) = range(20)
+INT_TABLES = (TAB_MODE_PQR, TAB_POINT_IJK, TAB_PAIR)
+
+STATUS = {0: "NIR_OK", 1: "NIR_EINVAL", 2: "NIR_ENOTSUP", 3: "NIR_ENOMEM", 4: "NIR_EHIP",
+          5: "NIR_ENONFINITE", 6: "NIR_EBREAKDOWN", 7: "NIR_ENOCONV"}
+
+
+class NirError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class nir_batch(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int32), ("nmodes", ctypes.c_int32), ("nquad", ctypes.c_int32),
+                ("deformed", ctypes.c_int32), ("nelmt", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("math", ctypes.c_int32)]
+
+
+class nir_geom(ctypes.Structure):
+    _fields_ = [("dxi_dx", ctypes.c_void_p), ("jac", ctypes.c_void_p), ("helm", ctypes.c_void_p)]
+
+
+class nir_cg_info(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int32), ("inner_iters", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+_lib = None
+_vp, _i32, _i64, _dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_SIGS = {
+    "nir_nmodes": (_i64, [_i32, _i32]),
+    "nir_last_error": (ctypes.c_char_p, []),
+    "nir_version": (ctypes.c_char_p, []),
+    "nir_quadrature_host": (_i32, [_i32, _i32, _i32, _vp, _vp]),
+    "nir_table_size": (_i64, [_i32, _i32, _i32, _i32]),
+    "nir_table_host": (_i32, [_i32, _i32, _i32, _i32, _vp]),
+    "nir_basis_create": (_i32, [_i32, _i32, _i32, ctypes.POINTER(_vp)]),
+    "nir_basis_destroy": (_i32, [_vp]),
+    "nir_basis_table_device": (_vp, [_vp, _i32]),
+    "nir_geom_from_vertices": (_i32, [ctypes.POINTER(nir_batch), _vp, _vp, _i32, _dbl, _vp, _vp, _vp, _vp, _vp]),
+    "nir_bwd_trans": (_i32, [ctypes.POINTER(nir_batch), _vp, _vp, _vp, _vp]),
+    "nir_phys_deriv": (_i32, [ctypes.POINTER(nir_batch), _vp, ctypes.POINTER(nir_geom), _vp, _vp, _vp, _vp, _vp]),
+    "nir_iprod_wrt_base": (_i32, [ctypes.POINTER(nir_batch), _vp, ctypes.POINTER(nir_geom), _vp, _vp, _vp]),
+    "nir_iprod_wrt_deriv_base": (_i32, [ctypes.POINTER(nir_batch), _vp, ctypes.POINTER(nir_geom), _vp, _vp, _vp,
+                                        _vp, _vp]),
+    "nir_helmholtz_apply": (_i32, [ctypes.POINTER(nir_batch), _vp, ctypes.POINTER(nir_geom), _dbl, _vp, _vp, _vp]),
+}
+
+
+def lib():
+    """The loaded libnir.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is missing: build it with `python -m paper_2606_20917_amd.build`")
+        L = ctypes.CDLL(LIBPATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name, None)
+            if f is None:
+                continue
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != 0:
+        raise NirError(st, lib().nir_last_error().decode())
+
+
+def _ptr(x):
+    """Address of a tensor (contiguous) or an int; None -> NULL."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if not x.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def batch(shape, P, nelmt, dtype=F64, deformed=1, math=MATH_NATIVE, Q=None):
+    return nir_batch(shape, P, P + 1 if Q is None else Q, deformed, nelmt, dtype, math)
+
+
+def geom(dxi_dx=None, jac=None, helm=None):
+    return nir_geom(_ptr(dxi_dx), _ptr(jac), _ptr(helm))
+
+
+class Basis:
+    """Owner of a nir_basis handle."""
+
+    def __init__(self, shape, P, Q=None):
+        self.shape, self.P, self.Q = shape, P, P + 1 if Q is None else Q
+        h = ctypes.c_void_p()
+        _check(lib().nir_basis_create(shape, P, self.Q, ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.nir_basis_destroy(self.handle)
+            self.handle = None
+
+    @property
+    def _as_parameter_(self):
+        return self.handle
+
+
+def _basis(b):
+    return b.handle if isinstance(b, Basis) else b
+
+
+# ------------------------------------------------------------------ entry points
+def nir_nmodes(shape, P):
+    return lib().nir_nmodes(shape, P)
+
+
+def nir_version():
+    return lib().nir_version().decode()
+
+
+def nir_last_error():
+    return lib().nir_last_error().decode()
+
+
+def nir_quadrature_host(rule, alpha, Q):
+    import numpy as np
+    z, w = np.zeros(Q), np.zeros(Q)
+    _check(lib().nir_quadrature_host(rule, alpha, Q, z.ctypes.data, w.ctypes.data))
+    return z, w
+
+
+def nir_table_size(shape, P, Q, tid):
+    return lib().nir_table_size(shape, P, Q, tid)
+
+
+def nir_table_host(shape, P, Q, tid):
+    import numpy as np
+    n = nir_table_size(shape, P, Q, tid)
+    if n < 0:
+        raise NirError(1, "invalid table request")
+    out = np.zeros(n, dtype=np.int32 if tid in INT_TABLES else np.float64)
+    _check(lib().nir_table_host(shape, P, Q, tid, out.ctypes.data))
+    return out
+
+
+def nir_basis_create(shape, P, Q=None):
+    return Basis(shape, P, Q)
+
+
+def nir_geom_from_vertices(b, basis, verts, map_, amp, dxi_dx=None, jac=None, helm64=None, helm32=None,
+                           stream=None):
+    _check(lib().nir_geom_from_vertices(ctypes.byref(b), _basis(basis), _ptr(verts), map_, amp, _ptr(dxi_dx),
+                                        _ptr(jac), _ptr(helm64), _ptr(helm32), _stream(stream)))
+
+
+def nir_bwd_trans(b, basis, coef, phys, stream=None):
+    _check(lib().nir_bwd_trans(ctypes.byref(b), _basis(basis), _ptr(coef), _ptr(phys), _stream(stream)))
+
+
+def nir_phys_deriv(b, basis, g, phys, d0, d1, d2, stream=None):
+    _check(lib().nir_phys_deriv(ctypes.byref(b), _basis(basis), ctypes.byref(g), _ptr(phys), _ptr(d0), _ptr(d1),
+                                _ptr(d2), _stream(stream)))
+
+
+def nir_iprod_wrt_base(b, basis, g, phys, coef, stream=None):
+    _check(lib().nir_iprod_wrt_base(ctypes.byref(b), _basis(basis), ctypes.byref(g), _ptr(phys), _ptr(coef),
+                                    _stream(stream)))
+
+
+def nir_iprod_wrt_deriv_base(b, basis, g, f0, f1, f2, coef, stream=None):
+    _check(lib().nir_iprod_wrt_deriv_base(ctypes.byref(b), _basis(basis), ctypes.byref(g), _ptr(f0), _ptr(f1),
+                                          _ptr(f2), _ptr(coef), _stream(stream)))
+
+
+def nir_helmholtz_apply(b, basis, g, lam, coef_in, coef_out, stream=None):
+    _check(lib().nir_helmholtz_apply(ctypes.byref(b), _basis(basis), ctypes.byref(g), lam, _ptr(coef_in),
+                                     _ptr(coef_out), _stream(stream)))
