@@ -103,6 +103,7 @@ def main():
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--variant", default="auto", choices=["auto", "generic", "pencil"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus must be 1)",
@@ -113,6 +114,9 @@ def main():
     from paper_2606_20917_amd import nir
     nir.lib()
     ps = [int(p) for p in args.ps.split(",")]
+    vid = {"auto": nir.VARIANT_AUTO, "generic": nir.VARIANT_GENERIC, "pencil": nir.VARIANT_PENCIL}[args.variant]
+    for P in ps:
+        nir.nir_set_helmholtz_variant(nir.HEX, P, nir.F64 if args.dtype == "f64" else nir.F32, vid)
     cases = [setup(P, args.dtype) for P in ps]
     stream = torch.cuda.current_stream()
 

@@ -184,6 +184,18 @@ nir_status nir_iprod_wrt_deriv_base(const nir_batch* batch, const nir_basis* bas
 nir_status nir_helmholtz_apply(const nir_batch* batch, const nir_basis* basis, const nir_geom* geom,
                                double lambda, const void* coef_in, void* coef_out, void* stream);
 
+/* ------------------------------------------------------------------ kernel variants
+ * Several kernels implement the fused Helmholtz apply; the choice per (shape, P, dtype)
+ * is library-global state (one int per combination, set atomically):
+ *   NIR_VARIANT_AUTO     the tuned choice (from nir_autotune_helmholtz or the built-in default)
+ *   NIR_VARIANT_GENERIC  LDS-staged kernel, threads over points/modes (any shape)
+ *   NIR_VARIANT_PENCIL   register-pencil kernel with uniform basis operands (hex only)
+ * Setting a variant a shape does not support returns NIR_ENOTSUP. */
+typedef enum { NIR_VARIANT_AUTO = 0, NIR_VARIANT_GENERIC = 1, NIR_VARIANT_PENCIL = 2 } nir_variant;
+nir_status nir_set_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype, int32_t variant);
+/* The variant a call with these parameters would run now (never NIR_VARIANT_AUTO); -1 if invalid. */
+int32_t nir_get_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,6 +5,9 @@
 #include <cstdio>
 #include <cstring>
 
+#include <atomic>
+
+#include "helm_hex.h"
 #include "nir_internal.h"
 
 namespace nir {
@@ -74,6 +77,15 @@ static nir_status check_geom(const nir_batch* b, const nir_geom* g, bool need_dx
   if (need_jac) NIR_TRY(check_ptr(b, g->jac, "geom->jac"));
   if (need_helm) NIR_TRY(check_ptr(b, g->helm, "geom->helm"));
   return NIR_OK;
+}
+
+// variant table [shape][P][dtype]; 0 = auto
+static std::atomic<int> g_variant[3][kMaxP + 1][2];
+
+static int resolve_variant(int shape, int P, int dtype) {
+  const int v = g_variant[shape][P][dtype].load(std::memory_order_relaxed);
+  if (v != NIR_VARIANT_AUTO) return v;
+  return shape == kHex ? NIR_VARIANT_PENCIL : NIR_VARIANT_GENERIC;
 }
 
 }  // namespace nir
@@ -215,6 +227,27 @@ nir_status nir_basis_create(int32_t shape, int32_t P, int32_t Q, nir_basis** out
   };
   fill(b->t64, d64);
   fill(b->t32, d32);
+  {
+    const int Q = b->Q, P = b->P;
+    std::vector<double> p64(2 * Q * P);
+    std::vector<float> p32(2 * Q * P);
+    for (int i = 0; i < Q; ++i)
+      for (int p = 0; p < P; ++p) {
+        p64[i * P + p] = b->host.T1[p * Q + i];
+        p64[Q * P + i * P + p] = b->host.dT1[p * Q + i];
+      }
+    for (size_t k = 0; k < p64.size(); ++k) p32[k] = float(p64[k]);
+    const size_t nb64 = p64.size() * 8, nb32 = p32.size() * 4;
+    if ((st = hip_check(hipMalloc(&b->devpencil, nb64 + nb32), "hipMalloc tables")) != NIR_OK ||
+        (st = hip_check(hipMemcpy(b->devpencil, p64.data(), nb64, hipMemcpyHostToDevice), "copy tables")) != NIR_OK ||
+        (st = hip_check(hipMemcpy(static_cast<char*>(b->devpencil) + nb64, p32.data(), nb32, hipMemcpyHostToDevice),
+                        "copy tables")) != NIR_OK) {
+      nir_basis_destroy(b);
+      return st;
+    }
+    b->pencil64 = static_cast<const double*>(b->devpencil);
+    b->pencil32 = reinterpret_cast<const float*>(static_cast<const char*>(b->devpencil) + nb64);
+  }
   *out = b;
   return NIR_OK;
 }
@@ -224,6 +257,7 @@ nir_status nir_basis_destroy(nir_basis* b) {
   if (b->dev64) (void)hipFree(b->dev64);
   if (b->dev32) (void)hipFree(b->dev32);
   if (b->devint) (void)hipFree(b->devint);
+  if (b->devpencil) (void)hipFree(b->devpencil);
   delete b;
   return NIR_OK;
 }
@@ -358,7 +392,23 @@ nir_status nir_helmholtz_apply(const nir_batch* b, const nir_basis* basis, const
   a.helm = g->helm;
   a.lambda = lambda;
   a.nelmt = b->nelmt;
+  if (resolve_variant(b->shape, b->nmodes, b->dtype) == NIR_VARIANT_PENCIL)
+    return launch_helm_hex_pencil(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
   return launch_generic(basis, kOpHelm, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+}
+
+nir_status nir_set_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype, int32_t variant) {
+  if (shape < kHex || shape > kTet || P < kMinP || P > kMaxP || (dtype != NIR_F64 && dtype != NIR_F32))
+    return fail(NIR_EINVAL, "invalid (shape %d, P %d, dtype %d)", shape, P, dtype);
+  if (variant < NIR_VARIANT_AUTO || variant > NIR_VARIANT_PENCIL) return fail(NIR_EINVAL, "invalid variant %d", variant);
+  if (variant == NIR_VARIANT_PENCIL && shape != kHex) return fail(NIR_ENOTSUP, "the pencil kernel is hex only");
+  g_variant[shape][P][dtype].store(variant, std::memory_order_relaxed);
+  return NIR_OK;
+}
+
+int32_t nir_get_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype) {
+  if (shape < kHex || shape > kTet || P < kMinP || P > kMaxP || (dtype != NIR_F64 && dtype != NIR_F32)) return -1;
+  return resolve_variant(shape, P, dtype);
 }
 
 }  // extern "C"

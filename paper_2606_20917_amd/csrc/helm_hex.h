@@ -1,0 +1,36 @@
+// Kernel-argument basis tables of the hexahedral pencil kernels.
+#pragma once
+
+#include "nir_internal.h"
+
+namespace nir {
+
+// B[i][p] = psi^a_p(z_i), D[i][p] = d psi^a_p / dz (z_i): the same 1-D factor serves all
+// three directions of the hex (GLL points in every direction).
+template <int P, class T>
+struct HexTab {
+  T B[P + 1][P];
+  T D[P + 1][P];
+};
+
+// Read-only view of the same tables in global memory, indexed with uniform
+// indices so that the loads go through the scalar unit.
+template <int P, class T>
+struct HexTabView {
+  const T* __restrict__ p;
+  struct Row {
+    const T* __restrict__ r;
+    __device__ __forceinline__ T operator[](int q) const { return r[q]; }
+  };
+  struct Mat {
+    const T* __restrict__ m;
+    __device__ __forceinline__ Row operator[](int i) const { return Row{m + i * P}; }
+  };
+  Mat B{p};
+  Mat D{p + (P + 1) * P};
+  __device__ __forceinline__ HexTabView(const T* __restrict__ base) : p(base), B{base}, D{base + (P + 1) * P} {}
+};
+
+nir_status launch_helm_hex_pencil(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
+
+}  // namespace nir

@@ -79,6 +79,11 @@ struct nir_basis {
   void* devint = nullptr;    // int32 index tables
   nir::DevTab<double> t64;
   nir::DevTab<float> t32;
+  // direction-1 factor and its derivative in [point][mode] order ([Q][P] each, B then B'),
+  // the uniform operands of the register-pencil kernels
+  void* devpencil = nullptr;
+  const double* pencil64 = nullptr;
+  const float* pencil32 = nullptr;
   const void* table_dev[NIR_TAB_COUNT];
 };
 

@@ -16,6 +16,7 @@ HEX, PRISM, TET = 0, 1, 2
 F64, F32 = 0, 1
 MATH_NATIVE, MATH_F16SPLIT = 0, 1
 MAP_VERTEX, MAP_VERTEX_SIN = 0, 1
+VARIANT_AUTO, VARIANT_GENERIC, VARIANT_PENCIL = 0, 1, 2
 
 (TAB_Z1, TAB_Z2, TAB_Z3, TAB_W1, TAB_W2, TAB_W3, TAB_T1, TAB_DT1, TAB_T2, TAB_DT2, TAB_T3, TAB_DT3,
  TAB_D1, TAB_D2, TAB_D3, TAB_WQ, TAB_XI, TAB_MODE_PQR, TAB_POINT_IJK, TAB_PAIR) = range(20)
@@ -65,6 +66,8 @@ _SIGS = {
     "nir_iprod_wrt_deriv_base": (_i32, [ctypes.POINTER(nir_batch), _vp, ctypes.POINTER(nir_geom), _vp, _vp, _vp,
                                         _vp, _vp]),
     "nir_helmholtz_apply": (_i32, [ctypes.POINTER(nir_batch), _vp, ctypes.POINTER(nir_geom), _dbl, _vp, _vp, _vp]),
+    "nir_set_helmholtz_variant": (_i32, [_i32, _i32, _i32, _i32]),
+    "nir_get_helmholtz_variant": (_i32, [_i32, _i32, _i32]),
 }
 
 
@@ -204,3 +207,11 @@ def nir_iprod_wrt_deriv_base(b, basis, g, f0, f1, f2, coef, stream=None):
 def nir_helmholtz_apply(b, basis, g, lam, coef_in, coef_out, stream=None):
     _check(lib().nir_helmholtz_apply(ctypes.byref(b), _basis(basis), ctypes.byref(g), lam, _ptr(coef_in),
                                      _ptr(coef_out), _stream(stream)))
+
+
+def nir_set_helmholtz_variant(shape, P, dtype, variant):
+    _check(lib().nir_set_helmholtz_variant(shape, P, dtype, variant))
+
+
+def nir_get_helmholtz_variant(shape, P, dtype):
+    return lib().nir_get_helmholtz_variant(shape, P, dtype)

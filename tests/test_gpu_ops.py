@@ -131,10 +131,17 @@ def test_operators_match_oracle(case, P, dtype):
     torch.cuda.synchronize()
     assert elem_relerr(cout.cpu().numpy(), op.iprod_wrt_deriv_base(tab, geo, *f)) <= tol * 10
 
-    for lam in (1.0, 0.0, 0.5, 3.0):
-        nir.nir_helmholtz_apply(b, s["basis"], g, lam, dc, cout)
-        torch.cuda.synchronize()
-        assert elem_relerr(cout.cpu().numpy(), op.helmholtz(tab, geo, lam, coef)) <= tol * 10, lam
+    variants = [nir.VARIANT_GENERIC] + ([nir.VARIANT_PENCIL] if shape == nir.HEX else [])
+    try:
+        for v in variants:
+            nir.nir_set_helmholtz_variant(shape, P, dtype, v)
+            assert nir.nir_get_helmholtz_variant(shape, P, dtype) == v
+            for lam in (1.0, 0.0, 0.5, 3.0):
+                nir.nir_helmholtz_apply(b, s["basis"], g, lam, dc, cout)
+                torch.cuda.synchronize()
+                assert elem_relerr(cout.cpu().numpy(), op.helmholtz(tab, geo, lam, coef)) <= tol * 10, (v, lam)
+    finally:
+        nir.nir_set_helmholtz_variant(shape, P, dtype, nir.VARIANT_AUTO)
 
 
 def test_config_hex_jitter64_full():
