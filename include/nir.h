@@ -157,6 +157,11 @@ nir_status nir_geom_from_vertices(const nir_batch* batch, const nir_basis* basis
                                   int32_t map, double amp, double* dxi_dx, double* jac,
                                   double* helm64, float* helm32, void* stream);
 
+/* Physical coordinates of the quadrature points (same maps as above): xyz [nelmt][3][Q^3]
+ * FP64 device array.  Used to sample forcing functions at the points. */
+nir_status nir_points_from_vertices(const nir_batch* batch, const nir_basis* basis, const double* verts,
+                                   int32_t map, double amp, double* xyz, void* stream);
+
 /* ------------------------------------------------------------------ operators
  * BwdTrans u = B u^ (section 2.2, eqs. (14)-(17)): coef [nelmt][M] -> phys [nelmt][Q^3]. */
 nir_status nir_bwd_trans(const nir_batch* batch, const nir_basis* basis, const void* coef,
@@ -183,6 +188,65 @@ nir_status nir_iprod_wrt_deriv_base(const nir_batch* batch, const nir_basis* bas
  * on chip: coef_in [nelmt][M] -> coef_out [nelmt][M].  Uses geom->helm only. */
 nir_status nir_helmholtz_apply(const nir_batch* batch, const nir_basis* basis, const nir_geom* geom,
                                double lambda, const void* coef_in, void* coef_out, void* stream);
+
+/* ------------------------------------------------------------------ C0 assembly
+ * Structured n x n x n hex mesh on a cube, element e = ix + n*(iy + n*iz), every element with
+ * the same orientation (the paper leaves assembly out of scope, section 2.1).  The 1-D global
+ * index of mode p of element i is i(P-1) + {0 if p = 0; P-1 if p = 1; p-1 if p >= 2}, and
+ * the 3-D index is gx + ng*(gy + ng*gz), ng = n(P-1)+1; shared modes need no sign change.
+ * Number of global unknowns (n(P-1)+1)^3; -1 if invalid. */
+int64_t nir_c0_nglobal_hex(int32_t n, int32_t P);
+/* l2g [n^3][P^3] int32 local-to-global map: host version (host array) and device version
+ * (device array, enqueued on stream).  NIR_EINVAL if the numbering exceeds int32. */
+nir_status nir_c0_map_hex_host(int32_t n, int32_t P, int32_t* l2g);
+nir_status nir_c0_map_hex(int32_t n, int32_t P, int32_t* l2g, void* stream);
+
+/* Library-owned copy of a local-to-global map (device l2g [nelmt][M], values in [0, nglobal),
+ * every global index used at least once) plus its inverse in CSR form, built on the host by a
+ * stable counting sort: the entries of a global unknown are summed in ascending (element,
+ * mode) order, so nir_scatter_add is deterministic.  Synchronous. */
+typedef struct nir_assembly nir_assembly;
+nir_status nir_assembly_create(const int32_t* l2g, int64_t nelmt, int32_t M, int64_t nglobal, nir_assembly** out);
+nir_status nir_assembly_destroy(nir_assembly* a);
+/* xl[e][m] = xg[l2g[e][m]]  (device arrays of `dtype`, xg [nglobal], xl [nelmt][M]) */
+nir_status nir_gather(const nir_assembly* a, int32_t dtype, const void* xg, void* xl, void* stream);
+/* yg[G] = sum of yl[e][m] over l2g[e][m] = G, fixed order (overwrites yg) */
+nir_status nir_scatter_add(const nir_assembly* a, int32_t dtype, const void* yl, void* yg, void* stream);
+
+/* Jacobi diagonal of the elemental Helmholtz operators: dl[e][m] = (H_e)_mm (device
+ * [nelmt][M]); scatter-add gives the assembled diagonal.  Hex only (NIR_ENOTSUP otherwise).
+ * Uses geom->helm. */
+nir_status nir_helmholtz_diagonal(const nir_batch* batch, const nir_basis* basis, const nir_geom* geom,
+                                  double lambda, void* dl, void* stream);
+
+/* ------------------------------------------------------------------ CG solver
+ * Jacobi-preconditioned CG on the assembled system A x = b, A = sum_e P_e^T H_e P_e (hex, FP64
+ * batch).  The plan owns its workspace, a stream of its own (default priority) and the
+ * hipGraphs that replay k = 10 PCG iterations with alpha/beta kept on the device; the host
+ * reads the residual between graph launches.  Every solve is iterative refinement: the FP64
+ * residual r = b - A x, an inner PCG on A d = r/||r||, and x += ||r|| d, until ||b - A x|| <=
+ * rtol ||b||.  Modes:
+ *   NIR_CG_FP64       inner PCG in FP64 run to the final tolerance (plain FP64 PCG)
+ *   NIR_CG_MIXED_F32  inner PCG with FP32 vectors, FP32 element apply on the FP32 factors
+ *                     (helm32 given at plan creation), FP64 dot products, stopped at inner_rtol
+ * Errors: NIR_ENONFINITE (NaN/Inf in b or x0, or a non-finite residual), NIR_EBREAKDOWN
+ * (FP64 p^T A p <= 0), NIR_ENOCONV (maxit inner iterations used; x and info still hold the
+ * last iterate).  x holds x0 on entry (warm start / resume) and the solution on return.
+ * Synchronous: returns after the solution is in x.  Not thread-safe per plan. */
+typedef struct nir_cg_plan nir_cg_plan;
+typedef enum { NIR_CG_FP64 = 0, NIR_CG_MIXED_F32 = 1 } nir_cg_mode;
+typedef struct {
+  int32_t outer_iters;    /* refinement steps (FP64 residual evaluations after the first) */
+  int32_t inner_iters;    /* PCG iterations over all inner solves */
+  double rel_residual;    /* ||b - A x|| / ||b|| of the returned x, evaluated in FP64 */
+  double seconds;         /* wall time of the solve */
+} nir_cg_info;
+nir_status nir_cg_plan_create(const nir_batch* batch64, const nir_basis* basis, const nir_geom* geom64,
+                              const float* helm32, const nir_assembly* assembly, double lambda,
+                              nir_cg_plan** out);
+nir_status nir_cg_solve(nir_cg_plan* plan, int32_t mode, const double* b, double* x, double rtol, int32_t maxit,
+                        double inner_rtol, nir_cg_info* info, void* stream);
+nir_status nir_cg_plan_destroy(nir_cg_plan* plan);
 
 /* ------------------------------------------------------------------ kernel variants
  * Several kernels implement the fused Helmholtz apply; the choice per (shape, P, dtype)

@@ -43,6 +43,18 @@ def c0_map_closed_form(n, P):
     return l2g, ng ** 3
 
 
+def c0_map_closed_form_vec(n, P):
+    """The closed form above evaluated with array broadcasting (for large meshes)."""
+    def g1(i, p):
+        return i * (P - 1) + np.where(p == 0, 0, np.where(p == 1, P - 1, p - 1))
+    ng = n * (P - 1) + 1
+    e = np.arange(n ** 3)[:, None]
+    m = np.arange(P ** 3)[None, :]
+    ix, iy, iz = e % n, (e // n) % n, e // (n * n)
+    p, q, r = m // (P * P), (m // P) % P, m % P
+    return (g1(ix, p) + ng * (g1(iy, q) + ng * g1(iz, r))).astype(np.int64), ng ** 3
+
+
 def c0_map_by_matching(n, P):
     """The same map built by matching mode anchors: a vertex mode is anchored at a mesh
     vertex, a bubble mode at (element, bubble index) along its direction.  Equal anchors

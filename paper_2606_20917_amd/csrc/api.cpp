@@ -79,6 +79,8 @@ static nir_status check_geom(const nir_batch* b, const nir_geom* g, bool need_dx
   return NIR_OK;
 }
 
+nir_status nir_validate_batch(const nir_batch* b, const nir_basis* basis) { return check_batch(b, basis); }
+
 // variant table [shape][P][dtype]; 0 = auto
 static std::atomic<int> g_variant[3][kMaxP + 1][2];
 
@@ -282,6 +284,16 @@ nir_status nir_geom_from_vertices(const nir_batch* batch, const nir_basis* basis
     return fail(NIR_EINVAL, "the sin deformation is not affine: use deformed = 1");
   return launch_geom(basis, batch->deformed, batch->nelmt, verts, map, map == NIR_MAP_VERTEX_SIN ? amp : 0.0,
                      dxi_dx, jac, helm64, helm32, static_cast<hipStream_t>(stream));
+}
+
+nir_status nir_points_from_vertices(const nir_batch* batch, const nir_basis* basis, const double* verts, int32_t map,
+                                   double amp, double* xyz, void* stream) {
+  NIR_TRY(check_batch(batch, basis));
+  if (map != NIR_MAP_VERTEX && map != NIR_MAP_VERTEX_SIN) return fail(NIR_EINVAL, "invalid map %d", map);
+  if (batch->nelmt == 0) return NIR_OK;
+  if (!verts || !xyz || !aligned(verts, 8) || !aligned(xyz, 8)) return fail(NIR_EINVAL, "NULL or misaligned pointer");
+  return launch_points(basis, batch->nelmt, verts, map == NIR_MAP_VERTEX_SIN ? amp : 0.0, xyz,
+                       static_cast<hipStream_t>(stream));
 }
 
 nir_status nir_bwd_trans(const nir_batch* b, const nir_basis* basis, const void* coef, void* phys, void* stream) {

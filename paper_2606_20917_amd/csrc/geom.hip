@@ -144,7 +144,44 @@ __global__ void __launch_bounds__(256) k_geom(const double* __restrict__ verts, 
   }
 }
 
+template <int SHAPE>
+__global__ void __launch_bounds__(256) k_points(const double* __restrict__ verts, int64_t nelmt,
+                                                const double* __restrict__ xi, int NQ, double amp,
+                                                double* __restrict__ xyz) {
+  constexpr int NV = SHAPE == kHex ? 8 : (SHAPE == kPrism ? 6 : 4);
+  const int64_t total = nelmt * NQ;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t e = t / NQ;
+    const int n = int(t - e * NQ);
+    double N[8], dN[8][3];
+    shape_fn<SHAPE>(xi[n], xi[NQ + n], xi[2 * NQ + n], N, dN);
+    double x[3] = {0, 0, 0};
+    const double* V = verts + e * NV * 3;
+    for (int v = 0; v < NV; ++v)
+      for (int d = 0; d < 3; ++d) x[d] += N[v] * V[v * 3 + d];
+    if (amp != 0.0) {
+      const double s = sin(2.0 * M_PI * x[0]) * sin(2.0 * M_PI * x[1]) * sin(2.0 * M_PI * x[2]);
+      for (int d = 0; d < 3; ++d) x[d] += amp * s;
+    }
+    for (int d = 0; d < 3; ++d) xyz[(e * 3 + d) * NQ + n] = x[d];
+  }
+}
+
 }  // namespace
+
+nir_status launch_points(const nir_basis* b, int64_t nelmt, const double* verts, double amp, double* xyz,
+                         hipStream_t s) {
+  const int NQ = b->Q * b->Q * b->Q;
+  const int64_t nb = (nelmt * NQ + 255) / 256;
+  const dim3 grid(unsigned(nb < (1 << 20) ? nb : (1 << 20))), block(256);
+  if (b->shape == kHex)
+    hipLaunchKernelGGL(k_points<kHex>, grid, block, 0, s, verts, nelmt, b->t64.xi, NQ, amp, xyz);
+  else if (b->shape == kPrism)
+    hipLaunchKernelGGL(k_points<kPrism>, grid, block, 0, s, verts, nelmt, b->t64.xi, NQ, amp, xyz);
+  else
+    hipLaunchKernelGGL(k_points<kTet>, grid, block, 0, s, verts, nelmt, b->t64.xi, NQ, amp, xyz);
+  return hip_check(hipGetLastError(), "points kernel launch");
+}
 
 nir_status launch_geom(const nir_basis* b, int deformed, int64_t nelmt, const double* verts, int map, double amp,
                        double* dxi_dx, double* jac, double* helm64, float* helm32, hipStream_t s) {

@@ -69,6 +69,9 @@ struct DevTab {
   const int32_t* mode_pqr;
 };
 
+nir_status launch_points(const nir_basis* b, int64_t nelmt, const double* verts, double amp, double* xyz,
+                         hipStream_t s);
+
 }  // namespace nir
 
 struct nir_basis {
@@ -90,7 +93,14 @@ struct nir_basis {
 namespace nir {
 
 // ---------------------------------------------------------------- errors
+#define NIR_TRYS(x)                 \
+  do {                              \
+    nir_status _st = (x);           \
+    if (_st != NIR_OK) return _st;  \
+  } while (0)
 nir_status fail(nir_status s, const char* fmt, ...);
+// host validation of a batch against its basis handle (no device access)
+nir_status nir_validate_batch(const nir_batch* b, const nir_basis* basis);
 nir_status ok();
 nir_status hip_check(hipError_t e, const char* what);
 
@@ -125,5 +135,8 @@ nir_status launch_generic_tet(const nir_basis* b, int op, int dtype, int deforme
 nir_status launch_geom(const nir_basis* b, int deformed, int64_t nelmt, const double* verts, int map,
                        double amp, double* dxi_dx, double* jac, double* helm64, float* helm32,
                        hipStream_t s);
+
+nir_status launch_points(const nir_basis* b, int64_t nelmt, const double* verts, double amp, double* xyz,
+                         hipStream_t s);
 
 }  // namespace nir

@@ -17,6 +17,7 @@ F64, F32 = 0, 1
 MATH_NATIVE, MATH_F16SPLIT = 0, 1
 MAP_VERTEX, MAP_VERTEX_SIN = 0, 1
 VARIANT_AUTO, VARIANT_GENERIC, VARIANT_PENCIL = 0, 1, 2
+CG_FP64, CG_MIXED_F32 = 0, 1
 
 (TAB_Z1, TAB_Z2, TAB_Z3, TAB_W1, TAB_W2, TAB_W3, TAB_T1, TAB_DT1, TAB_T2, TAB_DT2, TAB_T3, TAB_DT3,
  TAB_D1, TAB_D2, TAB_D3, TAB_WQ, TAB_XI, TAB_MODE_PQR, TAB_POINT_IJK, TAB_PAIR) = range(20)
@@ -67,6 +68,19 @@ _SIGS = {
                                         _vp, _vp]),
     "nir_helmholtz_apply": (_i32, [ctypes.POINTER(nir_batch), _vp, ctypes.POINTER(nir_geom), _dbl, _vp, _vp, _vp]),
     "nir_set_helmholtz_variant": (_i32, [_i32, _i32, _i32, _i32]),
+    "nir_points_from_vertices": (_i32, [ctypes.POINTER(nir_batch), _vp, _vp, _i32, _dbl, _vp, _vp]),
+    "nir_c0_nglobal_hex": (_i64, [_i32, _i32]),
+    "nir_c0_map_hex_host": (_i32, [_i32, _i32, _vp]),
+    "nir_c0_map_hex": (_i32, [_i32, _i32, _vp, _vp]),
+    "nir_assembly_create": (_i32, [_vp, _i64, _i32, _i64, ctypes.POINTER(_vp)]),
+    "nir_assembly_destroy": (_i32, [_vp]),
+    "nir_gather": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "nir_scatter_add": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "nir_helmholtz_diagonal": (_i32, [ctypes.POINTER(nir_batch), _vp, ctypes.POINTER(nir_geom), _dbl, _vp, _vp]),
+    "nir_cg_plan_create": (_i32, [ctypes.POINTER(nir_batch), _vp, ctypes.POINTER(nir_geom), _vp, _vp, _dbl,
+                                  ctypes.POINTER(_vp)]),
+    "nir_cg_solve": (_i32, [_vp, _i32, _vp, _vp, _dbl, _i32, _dbl, ctypes.POINTER(nir_cg_info), _vp]),
+    "nir_cg_plan_destroy": (_i32, [_vp]),
     "nir_get_helmholtz_variant": (_i32, [_i32, _i32, _i32]),
 }
 
@@ -215,3 +229,84 @@ def nir_set_helmholtz_variant(shape, P, dtype, variant):
 
 def nir_get_helmholtz_variant(shape, P, dtype):
     return lib().nir_get_helmholtz_variant(shape, P, dtype)
+
+
+def nir_points_from_vertices(b, basis, verts, map_, amp, xyz, stream=None):
+    _check(lib().nir_points_from_vertices(ctypes.byref(b), _basis(basis), _ptr(verts), map_, amp, _ptr(xyz),
+                                          _stream(stream)))
+
+
+def nir_c0_nglobal_hex(n, P):
+    return lib().nir_c0_nglobal_hex(n, P)
+
+
+def nir_c0_map_hex_host(n, P):
+    import numpy as np
+    out = np.zeros((n ** 3, P ** 3), dtype=np.int32)
+    _check(lib().nir_c0_map_hex_host(n, P, out.ctypes.data))
+    return out
+
+
+def nir_c0_map_hex(n, P, l2g, stream=None):
+    _check(lib().nir_c0_map_hex(n, P, _ptr(l2g), _stream(stream)))
+
+
+class Assembly:
+    """Owner of a nir_assembly handle (built from a device l2g tensor)."""
+
+    def __init__(self, l2g, nglobal):
+        h = ctypes.c_void_p()
+        _check(lib().nir_assembly_create(_ptr(l2g), l2g.shape[0], l2g.shape[1], nglobal, ctypes.byref(h)))
+        self.handle, self.nglobal = h, nglobal
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.nir_assembly_destroy(self.handle)
+            self.handle = None
+
+
+def nir_assembly_create(l2g, nglobal):
+    return Assembly(l2g, nglobal)
+
+
+def nir_gather(a, dtype, xg, xl, stream=None):
+    _check(lib().nir_gather(a.handle, dtype, _ptr(xg), _ptr(xl), _stream(stream)))
+
+
+def nir_scatter_add(a, dtype, yl, yg, stream=None):
+    _check(lib().nir_scatter_add(a.handle, dtype, _ptr(yl), _ptr(yg), _stream(stream)))
+
+
+def nir_helmholtz_diagonal(b, basis, g, lam, dl, stream=None):
+    _check(lib().nir_helmholtz_diagonal(ctypes.byref(b), _basis(basis), ctypes.byref(g), lam, _ptr(dl),
+                                        _stream(stream)))
+
+
+class CGPlan:
+    """Owner of a nir_cg_plan handle; keeps the objects it points into alive."""
+
+    def __init__(self, b64, basis, g64, helm32, assembly, lam):
+        h = ctypes.c_void_p()
+        _check(lib().nir_cg_plan_create(ctypes.byref(b64), _basis(basis), ctypes.byref(g64), _ptr(helm32),
+                                        assembly.handle, lam, ctypes.byref(h)))
+        self.handle = h
+        self._keep = (b64, basis, g64, helm32, assembly)
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.nir_cg_plan_destroy(self.handle)
+            self.handle = None
+
+
+def nir_cg_plan_create(b64, basis, g64, helm32, assembly, lam):
+    return CGPlan(b64, basis, g64, helm32, assembly, lam)
+
+
+def nir_cg_solve(plan, mode, b, x, rtol=1e-10, maxit=100000, inner_rtol=1e-4, stream=None, check=True):
+    """Returns (status, nir_cg_info); raises on a non-OK status when check is True."""
+    info = nir_cg_info()
+    st = lib().nir_cg_solve(plan.handle, mode, _ptr(b), _ptr(x), rtol, maxit, inner_rtol, ctypes.byref(info),
+                            _stream(stream))
+    if check:
+        _check(st)
+    return st, info
