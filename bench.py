@@ -94,6 +94,77 @@ def cpu_baseline(cases, budget_s):
             "sample": "first elements of the same mesh per order (" + ", ".join(samples) + f"), {t_tot:.1f} s"}, errs
 
 
+def oracle_residual(verts, amp, n, P, lam, x, chunk=2048):
+    """||b - A x|| / ||b|| with the oracle's FP64 assembled operator and right-hand side,
+    geometry built chunk by chunk."""
+    from oracle import assembly, geometry as og, operators as op
+    Q = P + 1
+    tab = op.Tables(0, P, Q)
+    l2g, ng = assembly.c0_map_closed_form_vec(n, P)
+    b = np.zeros(ng)
+    Ax = np.zeros(ng)
+    for s in range(0, len(verts), chunk):
+        sl = slice(s, min(len(verts), s + chunk))
+        geo = og.Geometry(0, Q, verts[sl], amp)
+        xg = geo.x
+        u = np.sin(np.pi * xg[..., 0]) * np.cos(np.pi * xg[..., 1]) * np.sin(np.pi * xg[..., 2])
+        b += assembly.scatter_add(l2g[sl], op.iprod_wrt_base(tab, geo, (3 * np.pi ** 2 + lam) * u), ng)
+        Ax += assembly.scatter_add(l2g[sl], op.helmholtz(tab, geo, lam, x[l2g[sl]]), ng)
+    return float(np.linalg.norm(b - Ax) / np.linalg.norm(b))
+
+
+def bench_cg(args):
+    """Assembled Jacobi-PCG on 48^3 curved hexes, P=6: FP64 vs FP32-inner refinement, time to 1e-10."""
+    import torch
+    from paper_2606_20917_amd import inputs, nir
+    c = inputs.cg48()
+    n, P, Q, amp, lam = c["n"], c["P"], c["P"] + 1, c["amp"], 1.0
+    ne = len(c["verts"])
+    dev = torch.device("cuda")
+    basis = nir.Basis(nir.HEX, P)
+    b64 = nir.batch(nir.HEX, P, ne, nir.F64, 1)
+    dv = torch.tensor(c["verts"], device=dev)
+    helm = torch.empty(ne, 7, Q ** 3, dtype=torch.float64, device=dev)
+    helm32 = torch.empty(ne, 7, Q ** 3, dtype=torch.float32, device=dev)
+    jac = torch.empty(ne, Q ** 3, dtype=torch.float64, device=dev)
+    nir.nir_geom_from_vertices(b64, basis, dv, nir.MAP_VERTEX_SIN, amp, None, jac, helm, helm32)
+    ng = nir.nir_c0_nglobal_hex(n, P)
+    l2g = torch.empty(ne, P ** 3, dtype=torch.int32, device=dev)
+    nir.nir_c0_map_hex(n, P, l2g)
+    A = nir.Assembly(l2g, ng)
+    xyz = torch.empty(ne, 3, Q ** 3, dtype=torch.float64, device=dev)
+    nir.nir_points_from_vertices(b64, basis, dv, nir.MAP_VERTEX_SIN, amp, xyz)
+    f = ((3 * np.pi ** 2 + lam) * torch.sin(np.pi * xyz[:, 0]) * torch.cos(np.pi * xyz[:, 1])
+         * torch.sin(np.pi * xyz[:, 2])).contiguous()
+    del xyz
+    bl = torch.empty(ne, P ** 3, dtype=torch.float64, device=dev)
+    nir.nir_iprod_wrt_base(b64, basis, nir.geom(None, jac, None), f, bl)
+    bg = torch.empty(ng, dtype=torch.float64, device=dev)
+    nir.nir_scatter_add(A, nir.F64, bl, bg)
+    del f, bl, jac
+    plan = nir.CGPlan(b64, basis, nir.geom(None, None, helm), helm32, A, lam)
+    out = {"metric": "assembled Jacobi-PCG time to ||b-Ax||/||b|| <= 1e-10 (FP64 vs FP32-inner refinement)",
+           "unit": "s", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "cg48: 48^3 = 110592 curved hexes (sin deformation 0.1), P=6, Q=7, lambda=1, "
+                                  "13,997,521 global unknowns, x0 = 0, manufactured forcing",
+                      "inner_rtol": args.inner_rtol}}
+    for name, mode in (("fp64", nir.CG_FP64), ("mixed_f32", nir.CG_MIXED_F32)):
+        x = torch.zeros(ng, dtype=torch.float64, device=dev)
+        nir.nir_cg_solve(plan, mode, bg, x, rtol=1e-10, maxit=200000, inner_rtol=args.inner_rtol)  # warm-up + capture
+        x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, info = nir.nir_cg_solve(plan, mode, bg, x, rtol=1e-10, maxit=200000, inner_rtol=args.inner_rtol)
+        wall = time.perf_counter() - t
+        out[name] = {"seconds": round(wall, 4), "inner_iters": info.inner_iters, "outer_iters": info.outer_iters,
+                     "rel_residual_gpu": info.rel_residual, "xsum": float(x.sum())}
+        if not args.no_cpu:
+            out[name]["rel_residual_oracle"] = oracle_residual(c["verts"], amp, n, P, lam, x.cpu().numpy())
+    out["value"] = out["mixed_f32"]["seconds"]
+    out["speedup_mixed_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed_f32"]["seconds"], 3)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +175,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variant", default="auto", choices=["auto", "generic", "pencil"])
+    ap.add_argument("--workload", default="helm", choices=["helm", "cg48"])
+    ap.add_argument("--inner-rtol", type=float, default=1e-4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus must be 1)",
@@ -113,6 +186,8 @@ def main():
     import torch
     from paper_2606_20917_amd import nir
     nir.lib()
+    if args.workload == "cg48":
+        return bench_cg(args)
     ps = [int(p) for p in args.ps.split(",")]
     vid = {"auto": nir.VARIANT_AUTO, "generic": nir.VARIANT_GENERIC, "pencil": nir.VARIANT_PENCIL}[args.variant]
     for P in ps:
