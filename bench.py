@@ -36,7 +36,7 @@ def hex_flops(P):
     return 4 * (P ** 3 * Q + P ** 2 * Q ** 2 + P * Q ** 3) + 12 * Q ** 4 + 21 * Q ** 3
 
 
-def setup(P, dtype_name, n=32):
+def setup(P, dtype_name, n=32, mathmode=0):
     import torch
     from paper_2606_20917_amd import inputs, nir
     c = inputs.hex_sin32(P, n)
@@ -49,7 +49,7 @@ def setup(P, dtype_name, n=32):
     nir.nir_geom_from_vertices(b64, basis, torch.tensor(c["verts"], device=dev), nir.MAP_VERTEX_SIN, c["amp"],
                                None, None, helm, helm32)
     if dtype_name == "f32":
-        helm, tdt, b = helm32, torch.float32, nir.batch(nir.HEX, P, ne, nir.F32, 1)
+        helm, tdt, b = helm32, torch.float32, nir.batch(nir.HEX, P, ne, nir.F32, 1, math=mathmode)
     else:
         tdt, b = torch.float64, b64
     x = torch.tensor(c["coef"], dtype=tdt, device=dev)
@@ -148,7 +148,8 @@ def bench_cg(args):
            "config": {"workload": "cg48: 48^3 = 110592 curved hexes (sin deformation 0.1), P=6, Q=7, lambda=1, "
                                   "13,997,521 global unknowns, x0 = 0, manufactured forcing",
                       "inner_rtol": args.inner_rtol}}
-    for name, mode in (("fp64", nir.CG_FP64), ("mixed_f32", nir.CG_MIXED_F32)):
+    for name, mode in (("fp64", nir.CG_FP64), ("mixed_f32", nir.CG_MIXED_F32),
+                       ("mixed_f16split", nir.CG_MIXED_F16SPLIT)):
         x = torch.zeros(ng, dtype=torch.float64, device=dev)
         nir.nir_cg_solve(plan, mode, bg, x, rtol=1e-10, maxit=200000, inner_rtol=args.inner_rtol)  # warm-up + capture
         x.zero_()
@@ -162,6 +163,75 @@ def bench_cg(args):
             out[name]["rel_residual_oracle"] = oracle_residual(c["verts"], amp, n, P, lam, x.cpu().numpy())
     out["value"] = out["mixed_f32"]["seconds"]
     out["speedup_mixed_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed_f32"]["seconds"], 3)
+    out["speedup_f16split_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed_f16split"]["seconds"], 3)
+    print(json.dumps(out), flush=True)
+
+
+def bench_mixed(args):
+    """100k mixed elements (hex/prism/tet, P in 3..8, curved): one persistent graph-replayed launch
+    vs per-(shape, P) launches, FP32 and FP64."""
+    import torch
+    from paper_2606_20917_amd import inputs, nir
+    c = inputs.mixed100k()
+    dev = torch.device("cuda")
+    groups = {}
+    for i, (s, p) in enumerate(zip(c["shapes"], c["P"])):
+        groups.setdefault((int(s), int(p)), []).append(i)
+    bs = []
+    for (s, p), idx in sorted(groups.items()):
+        Q, ne = p + 1, len(idx)
+        basis = nir.Basis(s, p)
+        verts = torch.tensor(np.stack([c["verts"][i] for i in idx]), device=dev)
+        helm = torch.empty(ne, 7, Q ** 3, dtype=torch.float64, device=dev)
+        helm32 = torch.empty(ne, 7, Q ** 3, dtype=torch.float32, device=dev)
+        nir.nir_geom_from_vertices(nir.batch(s, p, ne, nir.F64, 1), basis, verts, nir.MAP_VERTEX_SIN, c["amp"],
+                                   None, None, helm, helm32)
+        x = torch.tensor(np.stack([c["coef"][i] for i in idx]), device=dev)
+        bs.append(dict(shape=s, P=p, ne=ne, basis=basis, helm=helm, helm32=helm32, x64=x, x32=x.float(),
+                       M=x.shape[1], Q=Q))
+    out = {"metric": "mixed-mesh Helmholtz apply GDoF/s (one persistent launch vs per-(shape,P) launches)",
+           "unit": "GDoF/s", "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "mixed100k: 100000 independent elements, 50/30/20% hex/prism/tet, P in 3..8, "
+                                  "sin deformation 0.1, per-point factors, lambda=1", "batches": len(bs)}}
+    dof = sum(b["ne"] * b["M"] for b in bs)
+    for dt_name, dt in (("f32", nir.F32), ("f64", nir.F64)):
+        tdt = torch.float32 if dt == nir.F32 else torch.float64
+        s = 4 if dt == nir.F32 else 8
+        byts = sum(b["ne"] * s * (2 * b["M"] + 7 * b["Q"] ** 3) for b in bs)
+        batches = [nir.batch(b["shape"], b["P"], b["ne"], dt, 1) for b in bs]
+        geoms = [nir.geom(None, None, b["helm32"] if dt == nir.F32 else b["helm"]) for b in bs]
+        xs = [b["x32"] if dt == nir.F32 else b["x64"] for b in bs]
+        ys = [torch.empty_like(x) for x in xs]
+        stream = torch.cuda.current_stream()
+
+        def per_batch():
+            for k, b in enumerate(bs):
+                nir.nir_helmholtz_apply(batches[k], b["basis"], geoms[k], 1.0, xs[k], ys[k], stream)
+        plan = nir.MixedPlan(batches, [b["basis"] for b in bs], geoms)
+
+        def persistent():
+            nir.nir_mixed_helmholtz_apply(plan, 1.0, xs, ys, stream)
+        res = {}
+        for name, fn in (("per_batch", per_batch), ("persistent", persistent)):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(args.steps):
+                fn()
+            e.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(e) / args.steps
+            res[name] = {"ms": round(ms, 4), "gdofs": round(dof / ms / 1e6, 3),
+                         "gbs": round(byts / ms / 1e6, 1), "frac_hbm": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        ref = [y.clone() for y in ys]
+        per_batch()
+        torch.cuda.synchronize()
+        res["persistent_equals_per_batch"] = all(torch.equal(r, y) for r, y in zip(ref, ys))
+        res["plan"] = plan.info()
+        out[dt_name] = res
+    out["value"] = out["f32"]["persistent"]["gdofs"]
     print(json.dumps(out), flush=True)
 
 
@@ -175,7 +245,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variant", default="auto", choices=["auto", "generic", "pencil"])
-    ap.add_argument("--workload", default="helm", choices=["helm", "cg48"])
+    ap.add_argument("--math", default="native", choices=["native", "f16split"])
+    ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k"])
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -188,11 +259,17 @@ def main():
     nir.lib()
     if args.workload == "cg48":
         return bench_cg(args)
+    if args.workload == "mixed100k":
+        return bench_mixed(args)
     ps = [int(p) for p in args.ps.split(",")]
     vid = {"auto": nir.VARIANT_AUTO, "generic": nir.VARIANT_GENERIC, "pencil": nir.VARIANT_PENCIL}[args.variant]
     for P in ps:
         nir.nir_set_helmholtz_variant(nir.HEX, P, nir.F64 if args.dtype == "f64" else nir.F32, vid)
-    cases = [setup(P, args.dtype) for P in ps]
+    if args.math == "f16split" and args.dtype != "f32":
+        print("--math f16split needs --dtype f32", file=sys.stderr)
+        sys.exit(2)
+    cases = [setup(P, args.dtype, mathmode=nir.MATH_F16SPLIT if args.math == "f16split" else nir.MATH_NATIVE)
+             for P in ps]
     stream = torch.cuda.current_stream()
 
     def launch(c, it):
@@ -237,7 +314,8 @@ def main():
         "metric": "Helmholtz apply GDoF/s & %HBM roofline, FP64 vs FP32/mixed, hex P=2-10",
         "value": round(value, 3), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(total_ms / args.steps, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "vs_baseline": None, "dtype": args.dtype + ("+f16split-mfma" if args.math == "f16split" else ""),
+        "data": "synthetic",
         "config": {"workload": "hex_sin32: 32^3 = 32768 curved hexes (sin deformation 0.1), per-point factors, "
                                "fused Helmholtz lambda=1, P in {" + ",".join(map(str, ps)) + "}, Q=P+1",
                    "nelmt": cases[0]["ne"], "orders": ps, "kernel": "nir_helmholtz_apply"},

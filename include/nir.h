@@ -185,9 +185,37 @@ nir_status nir_iprod_wrt_deriv_base(const nir_batch* batch, const nir_basis* bas
                                     void* stream);
 
 /* Fused Helmholtz y = (L + lambda M) u^ (section 2.1, eqs. (6), (7)) with every intermediate
- * on chip: coef_in [nelmt][M] -> coef_out [nelmt][M].  Uses geom->helm only. */
+ * on chip: coef_in [nelmt][M] -> coef_out [nelmt][M].  Uses geom->helm only.
+ * batch->math = NIR_MATH_F16SPLIT (FP32 storage, hexahedra only; NIR_ENOTSUP otherwise) runs
+ * the contractions as FP16 hi/lo split products on the matrix cores with FP32 accumulation.
+ * The other operators accept NIR_MATH_NATIVE only. */
 nir_status nir_helmholtz_apply(const nir_batch* batch, const nir_basis* basis, const nir_geom* geom,
                                double lambda, const void* coef_in, void* coef_out, void* stream);
+
+/* ------------------------------------------------------------------ mixed batches
+ * One persistent launch of the fused Helmholtz apply over several batches of different shape
+ * and order (a mixed mesh grouped by (shape, P)).  The plan builds a work list of element
+ * groups sorted by decreasing cost; workgroup b of the persistent grid of G runs items b,
+ * b+G, b+2G, ...  Results equal the per-batch nir_helmholtz_apply launches bit for bit (same device
+ * code per item).  All batches share one dtype and NIR_MATH_NATIVE and have P <= 8 (the orders
+ * compiled into the persistent kernel; NIR_ENOTSUP above); the arrays batches[],
+ * bases[], geoms[] (geoms[b].helm used) are copied, the objects they point to must outlive the
+ * plan.  The first apply tunes the kernel's register budget (2..4 waves per SIMD) and the grid
+ * size (1..8 workgroups per CU), timed on the caller's operands, and captures the launch into a
+ * hipGraph that later applies replay.
+ * Changing the coefficient pointers or lambda between applies re-uploads the descriptors
+ * (synchronising the stream).  Not thread-safe per plan. */
+typedef struct nir_mixed_plan nir_mixed_plan;
+nir_status nir_mixed_plan_create(int32_t nbatch, const nir_batch* batches, const nir_basis* const* bases,
+                                 const nir_geom* geoms, nir_mixed_plan** out);
+/* coef_in[b], coef_out[b]: device arrays [nelmt_b][M_b] of batch b */
+nir_status nir_mixed_helmholtz_apply(nir_mixed_plan* plan, double lambda, const void* const* coef_in,
+                                     void* const* coef_out, void* stream);
+/* work items, tuned grid size (0 before the first apply), its measured time per apply (ms),
+ * algorithmic bytes and DoF of one apply; any pointer may be NULL */
+nir_status nir_mixed_plan_info(const nir_mixed_plan* plan, int32_t* nitems, int32_t* grid, double* tuned_ms,
+                               int64_t* bytes, int64_t* dof);
+nir_status nir_mixed_plan_destroy(nir_mixed_plan* plan);
 
 /* ------------------------------------------------------------------ C0 assembly
  * Structured n x n x n hex mesh on a cube, element e = ix + n*(iy + n*iz), every element with
@@ -229,12 +257,14 @@ nir_status nir_helmholtz_diagonal(const nir_batch* batch, const nir_basis* basis
  *   NIR_CG_FP64       inner PCG in FP64 run to the final tolerance (plain FP64 PCG)
  *   NIR_CG_MIXED_F32  inner PCG with FP32 vectors, FP32 element apply on the FP32 factors
  *                     (helm32 given at plan creation), FP64 dot products, stopped at inner_rtol
+ *   NIR_CG_MIXED_F16SPLIT  as NIR_CG_MIXED_F32 with the element apply's contractions as
+ *                     FP16-split products on the matrix cores (FP32 accumulation)
  * Errors: NIR_ENONFINITE (NaN/Inf in b or x0, or a non-finite residual), NIR_EBREAKDOWN
  * (FP64 p^T A p <= 0), NIR_ENOCONV (maxit inner iterations used; x and info still hold the
  * last iterate).  x holds x0 on entry (warm start / resume) and the solution on return.
  * Synchronous: returns after the solution is in x.  Not thread-safe per plan. */
 typedef struct nir_cg_plan nir_cg_plan;
-typedef enum { NIR_CG_FP64 = 0, NIR_CG_MIXED_F32 = 1 } nir_cg_mode;
+typedef enum { NIR_CG_FP64 = 0, NIR_CG_MIXED_F32 = 1, NIR_CG_MIXED_F16SPLIT = 2 } nir_cg_mode;
 typedef struct {
   int32_t outer_iters;    /* refinement steps (FP64 residual evaluations after the first) */
   int32_t inner_iters;    /* PCG iterations over all inner solves */

@@ -3,9 +3,11 @@
 
 #include <cstdarg>
 #include <cstdio>
-#include <cstring>
-
+#include <algorithm>
 #include <atomic>
+#include <cmath>
+#include <cstring>
+#include <vector>
 
 #include "helm_hex.h"
 #include "nir_internal.h"
@@ -80,6 +82,12 @@ static nir_status check_geom(const nir_batch* b, const nir_geom* g, bool need_dx
 }
 
 nir_status nir_validate_batch(const nir_batch* b, const nir_basis* basis) { return check_batch(b, basis); }
+
+static nir_status native_only(const nir_batch* b) {
+  if (b->math != NIR_MATH_NATIVE)
+    return fail(NIR_ENOTSUP, "FP16-split contractions are implemented for the fused Helmholtz apply on hexahedra");
+  return NIR_OK;
+}
 
 // variant table [shape][P][dtype]; 0 = auto
 static std::atomic<int> g_variant[3][kMaxP + 1][2];
@@ -249,6 +257,30 @@ nir_status nir_basis_create(int32_t shape, int32_t P, int32_t Q, nir_basis** out
     }
     b->pencil64 = static_cast<const double*>(b->devpencil);
     b->pencil32 = reinterpret_cast<const float*>(static_cast<const char*>(b->devpencil) + nb64);
+    // MFMA basis tiles: 0 = B^T [r][k], 1 = B'^T [r][k], 2 = B [i][p], 3 = B' [i][p]
+    std::vector<float> mt(4 * 256, 0.f), ms(4, 1.f);
+    for (int p = 0; p < P; ++p)
+      for (int i = 0; i < Q; ++i) {
+        const double v = b->host.T1[p * Q + i], d = b->host.dT1[p * Q + i];
+        mt[0 * 256 + p * 16 + i] = float(v);
+        mt[1 * 256 + p * 16 + i] = float(d);
+        mt[2 * 256 + i * 16 + p] = float(v);
+        mt[3 * 256 + i * 16 + p] = float(d);
+      }
+    for (int q = 0; q < 4; ++q) {
+      float m = 0.f;
+      for (int k = 0; k < 256; ++k) m = std::max(m, std::fabs(mt[q * 256 + k]));
+      int e = 0;
+      std::frexp(m, &e);
+      ms[q] = std::ldexp(1.f, -e);
+    }
+    if ((st = hip_check(hipMalloc((void**)&b->mfma_tabs, mt.size() * 4), "hipMalloc tables")) != NIR_OK ||
+        (st = hip_check(hipMalloc((void**)&b->mfma_scale, ms.size() * 4), "hipMalloc tables")) != NIR_OK ||
+        (st = hip_check(hipMemcpy(b->mfma_tabs, mt.data(), mt.size() * 4, hipMemcpyHostToDevice), "copy tables")) != NIR_OK ||
+        (st = hip_check(hipMemcpy(b->mfma_scale, ms.data(), ms.size() * 4, hipMemcpyHostToDevice), "copy tables")) != NIR_OK) {
+      nir_basis_destroy(b);
+      return st;
+    }
   }
   *out = b;
   return NIR_OK;
@@ -260,6 +292,8 @@ nir_status nir_basis_destroy(nir_basis* b) {
   if (b->dev32) (void)hipFree(b->dev32);
   if (b->devint) (void)hipFree(b->devint);
   if (b->devpencil) (void)hipFree(b->devpencil);
+  if (b->mfma_tabs) (void)hipFree(b->mfma_tabs);
+  if (b->mfma_scale) (void)hipFree(b->mfma_scale);
   delete b;
   return NIR_OK;
 }
@@ -298,6 +332,7 @@ nir_status nir_points_from_vertices(const nir_batch* batch, const nir_basis* bas
 
 nir_status nir_bwd_trans(const nir_batch* b, const nir_basis* basis, const void* coef, void* phys, void* stream) {
   NIR_TRY(check_batch(b, basis));
+  NIR_TRY(native_only(b));
   if (b->nelmt == 0) return NIR_OK;
   NIR_TRY(check_ptr(b, coef, "coef"));
   NIR_TRY(check_ptr(b, phys, "phys"));
@@ -314,6 +349,7 @@ nir_status nir_bwd_trans(const nir_batch* b, const nir_basis* basis, const void*
 nir_status nir_iprod_wrt_base(const nir_batch* b, const nir_basis* basis, const nir_geom* g, const void* phys,
                               void* coef, void* stream) {
   NIR_TRY(check_batch(b, basis));
+  NIR_TRY(native_only(b));
   if (b->nelmt == 0) return NIR_OK;
   NIR_TRY(check_geom(b, g, false, true, false));
   NIR_TRY(check_ptr(b, phys, "phys"));
@@ -333,6 +369,7 @@ nir_status nir_iprod_wrt_base(const nir_batch* b, const nir_basis* basis, const 
 nir_status nir_phys_deriv(const nir_batch* b, const nir_basis* basis, const nir_geom* g, const void* phys,
                           void* d0, void* d1, void* d2, void* stream) {
   NIR_TRY(check_batch(b, basis));
+  NIR_TRY(native_only(b));
   if (b->nelmt == 0) return NIR_OK;
   NIR_TRY(check_geom(b, g, true, false, false));
   NIR_TRY(check_ptr(b, phys, "phys"));
@@ -361,6 +398,7 @@ nir_status nir_phys_deriv(const nir_batch* b, const nir_basis* basis, const nir_
 nir_status nir_iprod_wrt_deriv_base(const nir_batch* b, const nir_basis* basis, const nir_geom* g,
                                     const void* f0, const void* f1, const void* f2, void* coef, void* stream) {
   NIR_TRY(check_batch(b, basis));
+  NIR_TRY(native_only(b));
   if (b->nelmt == 0) return NIR_OK;
   NIR_TRY(check_geom(b, g, true, true, false));
   NIR_TRY(check_ptr(b, f0, "f0"));
@@ -404,6 +442,10 @@ nir_status nir_helmholtz_apply(const nir_batch* b, const nir_basis* basis, const
   a.helm = g->helm;
   a.lambda = lambda;
   a.nelmt = b->nelmt;
+  if (b->math == NIR_MATH_F16SPLIT) {
+    if (b->shape != kHex) return fail(NIR_ENOTSUP, "FP16-split contractions are implemented for hexahedra");
+    return launch_helm_hex_f16split(basis, b->deformed, a, static_cast<hipStream_t>(stream));
+  }
   if (resolve_variant(b->shape, b->nmodes, b->dtype) == NIR_VARIANT_PENCIL)
     return launch_helm_hex_pencil(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
   return launch_generic(basis, kOpHelm, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));

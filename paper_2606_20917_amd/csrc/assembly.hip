@@ -283,7 +283,8 @@ struct nir_cg_plan {
   double* sc = nullptr;      // scalars: 0 rz, 1 rz_new, 2 pAp, 3 alpha, 4 beta, 5 rr, 6 ||r||^2 (outer), 7 bb
   int* flag = nullptr;
   hipStream_t cap = nullptr;
-  hipGraphExec_t g_iter64 = nullptr, g_iter32 = nullptr;
+  hipGraphExec_t g_iter64 = nullptr, g_iter32 = nullptr, g_iter16 = nullptr;
+  bool f16split = false;      // inner FP32 apply with FP16-split MFMA contractions
   int k_per_graph = 10;
   double* host_sc = nullptr;  // pinned
 };
@@ -311,7 +312,10 @@ static nir_status apply_local(nir_cg_plan* pl, int dtype, hipStream_t s, const v
     a.in0 = pl->xl32;
     a.out0 = pl->yl32;
     a.helm = pl->g32.helm;
-    NIR_TRYS(launch_helm_hex_pencil(pl->basis, NIR_F32, pl->b64.deformed, a, s));
+    if (pl->f16split)
+      NIR_TRYS(launch_helm_hex_f16split(pl->basis, pl->b64.deformed, a, s));
+    else
+      NIR_TRYS(launch_helm_hex_pencil(pl->basis, NIR_F32, pl->b64.deformed, a, s));
     hipLaunchKernelGGL(k_scatter<float>, grid_for(pl->ng), dim3(256), 0, s, A->off, A->idx, pl->yl32,
                        static_cast<float*>(yg), pl->ng);
   }
@@ -582,6 +586,7 @@ nir_status nir_cg_plan_destroy(nir_cg_plan* pl) {
   if (!pl) return NIR_OK;
   if (pl->g_iter64) (void)hipGraphExecDestroy(pl->g_iter64);
   if (pl->g_iter32) (void)hipGraphExecDestroy(pl->g_iter32);
+  if (pl->g_iter16) (void)hipGraphExecDestroy(pl->g_iter16);
   for (void* v : {(void*)pl->xl, (void*)pl->yl, (void*)pl->bvec, (void*)pl->xs, (void*)pl->rout, (void*)pl->Ax,
                   (void*)pl->d, (void*)pl->r, (void*)pl->z, (void*)pl->p, (void*)pl->Ap, (void*)pl->dinv,
                   (void*)pl->diag, (void*)pl->xl32, (void*)pl->yl32, (void*)pl->d32, (void*)pl->r32, (void*)pl->z32,
@@ -596,10 +601,12 @@ nir_status nir_cg_plan_destroy(nir_cg_plan* pl) {
 nir_status nir_cg_solve(nir_cg_plan* pl, int32_t mode, const double* b, double* x, double rtol, int32_t maxit,
                         double inner_rtol, nir_cg_info* info, void* stream) {
   if (!pl || !b || !x) return fail(NIR_EINVAL, "NULL argument");
-  if (mode != NIR_CG_FP64 && mode != NIR_CG_MIXED_F32) return fail(NIR_ENOTSUP, "unsupported CG mode %d", mode);
-  if (mode == NIR_CG_MIXED_F32 && !pl->g32.helm) return fail(NIR_EINVAL, "mixed mode needs the FP32 factors");
+  if (mode != NIR_CG_FP64 && mode != NIR_CG_MIXED_F32 && mode != NIR_CG_MIXED_F16SPLIT)
+    return fail(NIR_ENOTSUP, "unsupported CG mode %d", mode);
+  if (mode != NIR_CG_FP64 && !pl->g32.helm) return fail(NIR_EINVAL, "mixed modes need the FP32 factors");
   if (!(rtol > 0.0) || maxit < 1) return fail(NIR_EINVAL, "rtol must be > 0 and maxit >= 1");
-  if (mode == NIR_CG_MIXED_F32 && !(inner_rtol > 0.0 && inner_rtol < 1.0)) return fail(NIR_EINVAL, "inner_rtol in (0,1)");
+  if (mode != NIR_CG_FP64 && !(inner_rtol > 0.0 && inner_rtol < 1.0)) return fail(NIR_EINVAL, "inner_rtol in (0,1)");
+  pl->f16split = mode == NIR_CG_MIXED_F16SPLIT;
   hipStream_t s = pl->cap;   // the plan's own stream: the captured graphs replay on it
   const auto t0 = std::chrono::steady_clock::now();
   const int64_t ng = pl->ng;
@@ -644,11 +651,13 @@ nir_status nir_cg_solve(nir_cg_plan* pl, int32_t mode, const double* b, double* 
       } else {
         hipLaunchKernelGGL(k_scale_down<float>, grid_for(ng), dim3(256), 0, s, pl->rout, pl->r32, pl->sc, ng);
         NIR_TRYS(pcg_start<float>(pl, s, pl->d32, pl->r32, pl->z32, pl->p32, pl->dinv32));
-        if (!pl->g_iter32) NIR_TRYS(capture_iters<float>(pl, &pl->g_iter32, pl->d32, pl->r32, pl->z32, pl->p32, pl->Ap32, pl->dinv32));
+        hipGraphExec_t* gx = pl->f16split ? &pl->g_iter16 : &pl->g_iter32;
+        if (!*gx) NIR_TRYS(capture_iters<float>(pl, gx, pl->d32, pl->r32, pl->z32, pl->p32, pl->Ap32, pl->dinv32));
       }
       bool broke = false;
       while (inf.inner_iters < maxit) {
-        NIR_TRYS(hip_check(hipGraphLaunch(mode == NIR_CG_FP64 ? pl->g_iter64 : pl->g_iter32, s), "graph launch"));
+        NIR_TRYS(hip_check(hipGraphLaunch(mode == NIR_CG_FP64 ? pl->g_iter64
+                                          : (pl->f16split ? pl->g_iter16 : pl->g_iter32), s), "graph launch"));
         inf.inner_iters += pl->k_per_graph;
         NIR_TRYS(read_scalars(pl, s, &flag));
         if (flag) { broke = true; break; }

@@ -386,15 +386,25 @@ __global__ void __launch_bounds__(256) k_iprod_deriv(KArgs<T> a) {
   }
 }
 
-template <int SHAPE, int P, class T, bool DEF>
-__global__ void __launch_bounds__(256) k_helm(KArgs<T> a) {
+// LDS values of T the fused Helmholtz group needs: E x (coefficients, direction-3 rows incl.
+// correction rows, direction-2 planes, u, three flux fields and the mass term)
+template <int SHAPE, int P>
+constexpr int helm_generic_lds() {
   using D = Dims<SHAPE, P>;
-  __shared__ T s_c[D::E * D::M];
-  __shared__ T s_f1[D::E * (D::NP + D::NX) * D::Q];
-  __shared__ T s_f2[D::E * P * D::Q2];
-  __shared__ T s_u[D::E * 4 * D::NQ];
+  return D::E * (D::M + (D::NP + D::NX) * D::Q + P * D::Q2 + 5 * D::NQ);
+}
+
+// One group of up to E elements starting at `base` on a block of 256 threads; `lds` holds
+// helm_generic_lds<SHAPE,P>() values.  Every thread of the block must call it.
+template <int SHAPE, int P, class T, bool DEF>
+__device__ __forceinline__ void helm_generic_group(const KArgs<T>& a, int64_t base, T* __restrict__ lds) {
+  using D = Dims<SHAPE, P>;
+  T* s_c = lds;
+  T* s_f1 = s_c + D::E * D::M;
+  T* s_f2 = s_f1 + D::E * (D::NP + D::NX) * D::Q;
+  T* s_u = s_f2 + D::E * P * D::Q2;   // per element: u, h1, h2, h3, mass term
   const int es = threadIdx.x / D::TPE, lt = threadIdx.x % D::TPE;
-  for (int64_t base = int64_t(blockIdx.x) * D::E; base < a.nelmt; base += int64_t(gridDim.x) * D::E) {
+  {
     const int64_t ne = min(int64_t(D::E), a.nelmt - base);
     const int64_t e = base + es;
     load_block(s_c, a.in0 + base * D::M, ne * D::M);
@@ -402,7 +412,7 @@ __global__ void __launch_bounds__(256) k_helm(KArgs<T> a) {
     const T* c = s_c + es * D::M;
     T* f1 = s_f1 + es * (D::NP + D::NX) * D::Q;
     T* f2 = s_f2 + es * P * D::Q2;
-    T* u = s_u + es * 4 * D::NQ;
+    T* u = s_u + es * 5 * D::NQ;
     T* h = u + D::NQ;
     fwd_dir3<SHAPE, P>(a.tb, c, f1, lt);
     __syncthreads();
@@ -410,15 +420,13 @@ __global__ void __launch_bounds__(256) k_helm(KArgs<T> a) {
     __syncthreads();
     for (int o = lt; o < D::NQ; o += D::TPE) u[o] = fwd_dir1_point<SHAPE, P>(a.tb, c, f1, f2, o);
     __syncthreads();
-    // pointwise: G applied to the xi-gradient, mass term lambda Jw u
-    T mterm[(D::NQ + D::TPE - 1) / D::TPE];
-    T hv[3][(D::NQ + D::TPE - 1) / D::TPE];
-#pragma unroll
-    for (int it = 0; it < (D::NQ + D::TPE - 1) / D::TPE; ++it) {
-      const int o = lt + it * D::TPE;
-      mterm[it] = T(0);
-      hv[0][it] = hv[1][it] = hv[2][it] = T(0);
-      if (o < D::NQ && es < ne) {
+    // pointwise: G applied to the xi-gradient, mass term lambda Jw u; fluxes and the mass
+    // term go to LDS fields of their own, so u stays intact for the neighbours' derivatives
+    T* mt = h + 3 * D::NQ;
+#pragma unroll 1
+    for (int o = lt; o < D::NQ; o += D::TPE) {
+      T h1 = T(0), h2 = T(0), h3 = T(0), m = T(0);
+      if (es < ne) {
         T d1, d2, d3, x1, x2, x3;
         colloc_grad<SHAPE, P>(a.tb, u, o, d1, d2, d3);
         const Chain<SHAPE, T> ch = chain_at<SHAPE, P>(a.tb, o);
@@ -432,26 +440,17 @@ __global__ void __launch_bounds__(256) k_helm(KArgs<T> a) {
         const T y1 = G00 * x1 + G01 * x2 + G02 * x3;
         const T y2 = G01 * x1 + G11 * x2 + G12 * x3;
         const T y3 = G02 * x1 + G12 * x2 + G22 * x3;
-        ch.to_eta(y1, y2, y3, hv[0][it], hv[1][it], hv[2][it]);
-        mterm[it] = a.lambda * Jw * u[o];
+        ch.to_eta(y1, y2, y3, h1, h2, h3);
+        m = a.lambda * Jw * u[o];
       }
-    }
-    __syncthreads();   // every read of u is done before it is overwritten
-#pragma unroll
-    for (int it = 0; it < (D::NQ + D::TPE - 1) / D::TPE; ++it) {
-      const int o = lt + it * D::TPE;
-      if (o < D::NQ) {
-        h[o] = hv[0][it];
-        h[D::NQ + o] = hv[1][it];
-        h[2 * D::NQ + o] = hv[2][it];
-      }
+      h[o] = h1;
+      h[D::NQ + o] = h2;
+      h[2 * D::NQ + o] = h3;
+      mt[o] = m;
     }
     __syncthreads();
-#pragma unroll
-    for (int it = 0; it < (D::NQ + D::TPE - 1) / D::TPE; ++it) {
-      const int o = lt + it * D::TPE;
-      if (o < D::NQ) u[o] = mterm[it] + colloc_div_t<SHAPE, P>(a.tb, h, h + D::NQ, h + 2 * D::NQ, o);
-    }
+#pragma unroll 1
+    for (int o = lt; o < D::NQ; o += D::TPE) u[o] = mt[o] + colloc_div_t<SHAPE, P>(a.tb, h, h + D::NQ, h + 2 * D::NQ, o);
     __syncthreads();
     bwd_dir1<SHAPE, P>(a.tb, u, f2, lt);
     __syncthreads();
@@ -461,6 +460,14 @@ __global__ void __launch_bounds__(256) k_helm(KArgs<T> a) {
       for (int m = lt; m < D::M; m += D::TPE) a.out0[e * D::M + m] = bwd_dir3_mode<SHAPE, P>(a.tb, f1, m);
     __syncthreads();
   }
+}
+
+template <int SHAPE, int P, class T, bool DEF>
+__global__ void __launch_bounds__(256) k_helm(KArgs<T> a) {
+  __shared__ T lds[helm_generic_lds<SHAPE, P>()];
+  for (int64_t base = int64_t(blockIdx.x) * Dims<SHAPE, P>::E; base < a.nelmt;
+       base += int64_t(gridDim.x) * Dims<SHAPE, P>::E)
+    helm_generic_group<SHAPE, P, T, DEF>(a, base, lds);
 }
 
 // ------------------------------------------------------------------ host launcher

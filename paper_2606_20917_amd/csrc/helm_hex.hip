@@ -27,227 +27,17 @@
 // Coefficients are staged through LDS so that HBM reads and writes are
 // coalesced; the mode pencils use an odd LDS row stride.
 
-#include "helm_hex.h"
-
-#ifndef NIR_HEX_IUNROLL
-#define NIR_HEX_IUNROLL 1
-#endif
+#include "helm_hex_dev.h"
 
 namespace nir {
 
 template <int P, class T, bool DEF>
-__global__ void __launch_bounds__(256) k_helm_hex(const T* __restrict__ tabs, const T* __restrict__ x, T* __restrict__ y,
-                                                  const T* __restrict__ helm, const T* __restrict__ wq, T lambda,
-                                                  int64_t nelmt) {
-  constexpr int Q = P + 1, Q2 = Q * Q, NQ = Q2 * Q, M = P * P * P;
-  constexpr int E = 256 / Q2;
-  constexpr int PP = P | 1;                               // odd stride of a mode pencil row
-  constexpr int PQ2 = P * Q2, P2Q = P * P * Q;
-  constexpr int SLAB = (3 * PQ2 > P * P * PP) ? 3 * PQ2 : P * P * PP;
-  __shared__ T lds[E * SLAB];
-  // uniform basis operands: B[i][p] = tabs[i*P + p], B'[i][p] = tabs[Q*P + i*P + p]
-  const HexTabView<P, T> tb{tabs};
-
-  const int t = threadIdx.x;
-  const int el = t / Q2;
-  const int s = t - el * Q2;
-  const bool act = el < E;
-  T* L = lds + (act ? el : 0) * SLAB;
-
-  {
-    const int64_t base = int64_t(blockIdx.x) * E;   // one element group per block (no grid-stride
-                                                    // loop: the basis operands stay short-lived)
-    const int ne = int(min(int64_t(E), nelmt - base));
-    const int64_t e = base + el;
-    const bool valid = act && el < ne;
-
-    // ---- stage coefficients (coalesced) into padded mode pencils
-    for (int f = t; f < ne * M; f += 256) {
-      const int e2 = f / M, m = f - e2 * M, pq = m / P, r = m - pq * P;
-      lds[e2 * SLAB + pq * PP + r] = x[base * M + f];
-    }
-    __syncthreads();
-
-    // ---- A: pencils (p,q), r -> k
-    T a0[Q], a1[Q];
-    if (act && s < P * P) {
-      T c[P];
-#pragma unroll
-      for (int r = 0; r < P; ++r) c[r] = L[s * PP + r];
-#pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        T v0 = T(0), v1 = T(0);
-#pragma unroll
-        for (int r = 0; r < P; ++r) {
-          v0 += tb.B[k][r] * c[r];
-          v1 += tb.D[k][r] * c[r];
-        }
-        a0[k] = v0;
-        a1[k] = v1;
-      }
-    }
-    __syncthreads();
-    if (act && s < P * P) {
-#pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        L[s * Q + k] = a0[k];
-        L[P2Q + s * Q + k] = a1[k];
-      }
-    }
-    __syncthreads();
-
-    // ---- B: pencils (p,k), q -> j
-    T c0[Q], c1[Q], c2[Q];
-    const int pb = s / Q, kb = s - pb * Q;
-    if (act && s < P * Q) {
-      T av[P], bv[P];
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        av[q] = L[(pb * P + q) * Q + kb];
-        bv[q] = L[P2Q + (pb * P + q) * Q + kb];
-      }
-#pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        T v0 = T(0), v1 = T(0), v2 = T(0);
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-          v0 += tb.B[j][q] * av[q];
-          v1 += tb.D[j][q] * av[q];
-          v2 += tb.B[j][q] * bv[q];
-        }
-        c0[j] = v0;
-        c1[j] = v1;
-        c2[j] = v2;
-      }
-    }
-    __syncthreads();
-    if (act && s < P * Q) {
-#pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        L[pb * Q2 + j * Q + kb] = c0[j];
-        L[PQ2 + pb * Q2 + j * Q + kb] = c1[j];
-        L[2 * PQ2 + pb * Q2 + j * Q + kb] = c2[j];
-      }
-    }
-    __syncthreads();
-
-    // ---- C, pointwise, C^T fused: stream over i with pencils (j,k); the values at
-    // point (i,j,k) are formed, weighted and folded back into t0..t2 at once, so the
-    // point pencils are never held whole
-    T C0[P], C1[P], C2[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      C0[p] = L[p * Q2 + s];
-      C1[p] = L[PQ2 + p * Q2 + s];
-      C2[p] = L[2 * PQ2 + p * Q2 + s];
-    }
-    T t0[P], t1[P], t2[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) t0[p] = t1[p] = t2[p] = T(0);
-    const T* g = helm + (valid ? e : 0) * (DEF ? 7 * NQ : 7);
-#pragma unroll NIR_HEX_IUNROLL
-    for (int i = 0; i < Q; ++i) {
-      T u = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
-#pragma unroll
-      for (int p = 0; p < P; ++p) {
-        u += tb.B[i][p] * C0[p];
-        d1 += tb.D[i][p] * C0[p];
-        d2 += tb.B[i][p] * C1[p];
-        d3 += tb.B[i][p] * C2[p];
-      }
-      const int n = i * Q2 + s;
-      T G[7];
-      if (DEF) {
-#pragma unroll
-        for (int c = 0; c < 7; ++c) G[c] = valid ? g[c * NQ + n] : T(0);
-      } else {
-        const T w = wq[n];
-#pragma unroll
-        for (int c = 0; c < 7; ++c) G[c] = valid ? g[c] * w : T(0);
-      }
-      const T f1 = G[0] * d1 + G[1] * d2 + G[2] * d3;
-      const T f2 = G[1] * d1 + G[3] * d2 + G[4] * d3;
-      const T f3 = G[2] * d1 + G[4] * d2 + G[5] * d3;
-      const T m = lambda * G[6] * u;
-#pragma unroll
-      for (int p = 0; p < P; ++p) {
-        t0[p] += tb.B[i][p] * m + tb.D[i][p] * f1;
-        t1[p] += tb.B[i][p] * f2;
-        t2[p] += tb.B[i][p] * f3;
-      }
-    }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-      for (int p = 0; p < P; ++p) {
-        L[p * Q2 + s] = t0[p];
-        L[PQ2 + p * Q2 + s] = t1[p];
-        L[2 * PQ2 + p * Q2 + s] = t2[p];
-      }
-    }
-    __syncthreads();
-
-    // ---- B^T: pencils (p,k), j -> q
-    T s0[P], s1[P];
-    if (act && s < P * Q) {
-      T tv0[Q], tv1[Q], tv2[Q];
-#pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        tv0[j] = L[pb * Q2 + j * Q + kb];
-        tv1[j] = L[PQ2 + pb * Q2 + j * Q + kb];
-        tv2[j] = L[2 * PQ2 + pb * Q2 + j * Q + kb];
-      }
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        T v0 = T(0), v1 = T(0);
-#pragma unroll
-        for (int j = 0; j < Q; ++j) {
-          v0 += tb.B[j][q] * tv0[j] + tb.D[j][q] * tv1[j];
-          v1 += tb.B[j][q] * tv2[j];
-        }
-        s0[q] = v0;
-        s1[q] = v1;
-      }
-    }
-    __syncthreads();
-    if (act && s < P * Q) {
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        L[(pb * P + q) * Q + kb] = s0[q];
-        L[P2Q + (pb * P + q) * Q + kb] = s1[q];
-      }
-    }
-    __syncthreads();
-
-    // ---- A^T: pencils (p,q), k -> r
-    T yv[P];
-    if (act && s < P * P) {
-      T sv0[Q], sv1[Q];
-#pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        sv0[k] = L[s * Q + k];
-        sv1[k] = L[P2Q + s * Q + k];
-      }
-#pragma unroll
-      for (int r = 0; r < P; ++r) {
-        T v = T(0);
-#pragma unroll
-        for (int k = 0; k < Q; ++k) v += tb.B[k][r] * sv0[k] + tb.D[k][r] * sv1[k];
-        yv[r] = v;
-      }
-    }
-    __syncthreads();
-    if (act && s < P * P) {
-#pragma unroll
-      for (int r = 0; r < P; ++r) L[s * PP + r] = yv[r];
-    }
-    __syncthreads();
-    for (int f = t; f < ne * M; f += 256) {
-      const int e2 = f / M, m = f - e2 * M, pq = m / P, r = m - pq * P;
-      y[base * M + f] = lds[e2 * SLAB + pq * PP + r];
-    }
-    __syncthreads();
-  }
+__global__ void __launch_bounds__(256) k_helm_hex(const T* __restrict__ tabs, const T* __restrict__ x,
+                                                  T* __restrict__ y, const T* __restrict__ helm,
+                                                  const T* __restrict__ wq, T lambda, int64_t nelmt) {
+  // one element group per block (no grid-stride loop: the basis operands stay short-lived)
+  __shared__ T lds[HexPencilDims<P, T>::LDS];
+  helm_hex_group<P, T, DEF>(tabs, x, y, helm, wq, lambda, nelmt, int64_t(blockIdx.x) * HexPencilDims<P, T>::E, lds);
 }
 
 template <int P, class T>

@@ -1,0 +1,290 @@
+// One persistent launch of the fused Helmholtz apply over a mixed mesh: hexahedra,
+// prisms and tetrahedra at different orders, each (shape, P) class a batch of its own.
+//
+// The paper batches only alike elements (section 2.2, end: blocks of elements with the
+// same shape, quadrature and order).  Here a work list of items (batch, first element
+// of a group) is built on the host, sorted by decreasing cost (bytes moved, the bound
+// of these kernels), and workgroup b of one persistent grid of G workgroups runs items
+// b, b+G, b+2G, ... with the group function of each item's (shape, P): the register
+// pencil kernel for hexahedra, the LDS kernel for prisms and tetrahedra.  Items are
+// independent, so the result equals the per-batch launches bit for bit.  (A shared
+// atomic counter for dynamic balance was measured slower: 38k device-scope atomics on
+// one address serialise.)
+//
+// The plan tunes its launch on first use: the register budget of the kernel (2, 3 or 4
+// waves per SIMD; a tighter budget buys occupancy with spills) and the grid size (1..8
+// workgroups per CU, capped by that budget's occupancy), each pair timed on the caller's
+// operands.  It then captures [reset, persistent kernel] into a hipGraph that later
+// applies replay.
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "generic_ops.h"
+#include "helm_hex_dev.h"
+#include "nir_internal.h"
+
+#include "mixed_kernels.h"
+
+namespace nir {
+
+// host-side group size of (shape, P): must equal the device functions' E
+static int host_group_size(int shape, int P) {
+  const int Q = P + 1;
+  if (shape == kHex) return 256 / (Q * Q);
+  const int NQ = Q * Q * Q;
+  const int tpe = NQ <= 32 ? 32 : (NQ <= 128 ? 64 : (NQ <= 343 ? 128 : 256));
+  return 256 / tpe;
+}
+
+}  // namespace nir
+
+struct nir_mixed_plan {
+  int dtype = 0;
+  int nbatch = 0;
+  std::vector<nir_batch> batches;
+  std::vector<const nir_basis*> bases;
+  std::vector<nir_geom> geoms;
+  std::vector<const void*> cur_in;
+  std::vector<void*> cur_out;
+  double cur_lambda = -1.0;
+  void* dbatches = nullptr;          // MixedBatch<T>[nbatch]
+  nir::MixedItem* ditems = nullptr;
+  int nitems = 0;
+  int* counter = nullptr;
+  double* dlam = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int grid = 0;
+  int waves = 0;             // tuned register budget (waves per SIMD)
+  int ncu = 0;
+  int occ[5] = {0, 0, 0, 0, 0};   // max workgroups per CU for budgets 2..4
+  double tuned_ms = 0.0;
+  int64_t bytes = 0, dof = 0;
+};
+
+namespace nir {
+
+template <class T>
+static nir_status upload_batches(nir_mixed_plan* pl) {
+  std::vector<MixedBatch<T>> h(pl->nbatch);
+  for (int b = 0; b < pl->nbatch; ++b) {
+    MixedBatch<T>& m = h[b];
+    std::memset(&m, 0, sizeof(m));
+    m.shape = pl->batches[b].shape;
+    m.P = pl->batches[b].nmodes;
+    m.deformed = pl->batches[b].deformed;
+    m.nelmt = pl->batches[b].nelmt;
+    m.x = static_cast<const T*>(pl->cur_in[b]);
+    m.y = static_cast<T*>(pl->cur_out[b]);
+    m.helm = static_cast<const T*>(pl->geoms[b].helm);
+    if constexpr (sizeof(T) == 8) {
+      m.tb = pl->bases[b]->t64;
+      m.pencil = pl->bases[b]->pencil64;
+    } else {
+      m.tb = pl->bases[b]->t32;
+      m.pencil = pl->bases[b]->pencil32;
+    }
+  }
+  return hip_check(hipMemcpy(pl->dbatches, h.data(), h.size() * sizeof(MixedBatch<T>), hipMemcpyHostToDevice),
+                   "upload batch descriptors");
+}
+
+static nir_status enqueue(nir_mixed_plan* pl, hipStream_t s, int W, int grid) {
+  if (pl->dtype == NIR_F64)
+    return launch_mixed<double>(W, grid, s, static_cast<const MixedBatch<double>*>(pl->dbatches), pl->ditems,
+                                pl->nitems, pl->counter, pl->dlam);
+  return launch_mixed<float>(W, grid, s, static_cast<const MixedBatch<float>*>(pl->dbatches), pl->ditems,
+                             pl->nitems, pl->counter, pl->dlam);
+}
+
+// time `reps` launches with register budget W and grid g on the plan stream
+static nir_status time_grid(nir_mixed_plan* pl, int W, int g, int reps, double* ms) {
+  hipEvent_t a, b;
+  NIR_TRYS(hip_check(hipEventCreate(&a), "event"));
+  NIR_TRYS(hip_check(hipEventCreate(&b), "event"));
+  NIR_TRYS(enqueue(pl, pl->cap, W, g));   // warm-up
+  NIR_TRYS(hip_check(hipEventRecord(a, pl->cap), "event record"));
+  for (int r = 0; r < reps; ++r) NIR_TRYS(enqueue(pl, pl->cap, W, g));
+  NIR_TRYS(hip_check(hipEventRecord(b, pl->cap), "event record"));
+  NIR_TRYS(hip_check(hipEventSynchronize(b), "event sync"));
+  float t = 0.f;
+  NIR_TRYS(hip_check(hipEventElapsedTime(&t, a, b), "elapsed"));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *ms = double(t) / reps;
+  return NIR_OK;
+}
+
+}  // namespace nir
+
+using namespace nir;
+
+extern "C" {
+
+nir_status nir_mixed_plan_destroy(nir_mixed_plan* pl) {
+  if (!pl) return NIR_OK;
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  for (void* v : {pl->dbatches, (void*)pl->ditems, (void*)pl->counter, (void*)pl->dlam})
+    if (v) (void)hipFree(v);
+  if (pl->cap) (void)hipStreamDestroy(pl->cap);
+  delete pl;
+  return NIR_OK;
+}
+
+nir_status nir_mixed_plan_create(int32_t nbatch, const nir_batch* batches, const nir_basis* const* bases,
+                                 const nir_geom* geoms, nir_mixed_plan** out) {
+  if (!out) return fail(NIR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nbatch < 1 || !batches || !bases || !geoms) return fail(NIR_EINVAL, "empty or NULL batch list");
+  const int dtype = batches[0].dtype;
+  for (int b = 0; b < nbatch; ++b) {
+    NIR_TRYS(nir_validate_batch(&batches[b], bases[b]));
+    if (batches[b].dtype != dtype) return fail(NIR_EINVAL, "all batches of a mixed plan share one dtype");
+    if (batches[b].math != NIR_MATH_NATIVE) return fail(NIR_ENOTSUP, "mixed plans use native contractions");
+    if (batches[b].nmodes > kMixedMaxP)
+      return fail(NIR_ENOTSUP, "mixed plans support P <= %d (batch %d has P = %d)", kMixedMaxP, b, batches[b].nmodes);
+    if (batches[b].nelmt > 0 && !geoms[b].helm) return fail(NIR_EINVAL, "batch %d has no Helmholtz factors", b);
+  }
+  nir_mixed_plan* pl = new (std::nothrow) nir_mixed_plan();
+  if (!pl) return fail(NIR_ENOMEM, "host allocation failed");
+  pl->dtype = dtype;
+  pl->nbatch = nbatch;
+  pl->batches.assign(batches, batches + nbatch);
+  pl->bases.assign(bases, bases + nbatch);
+  pl->geoms.assign(geoms, geoms + nbatch);
+  pl->cur_in.assign(nbatch, nullptr);
+  pl->cur_out.assign(nbatch, nullptr);
+  // work list: groups of each batch, decreasing cost (algorithmic bytes of the group)
+  struct W {
+    int64_t cost;
+    MixedItem it;
+  };
+  std::vector<W> w;
+  const int s = dtype == NIR_F64 ? 8 : 4;
+  for (int b = 0; b < nbatch; ++b) {
+    const nir_batch& B = batches[b];
+    const int E = host_group_size(B.shape, B.nmodes);
+    const int64_t M = modes_of(B.shape, B.nmodes), NQ = int64_t(B.nquad) * B.nquad * B.nquad;
+    const int64_t per_elem = s * (2 * M + 7 * (B.deformed ? NQ : 1));
+    pl->bytes += per_elem * B.nelmt;
+    pl->dof += M * B.nelmt;
+    for (int64_t f = 0; f < B.nelmt; f += E) {
+      const int64_t n = std::min<int64_t>(E, B.nelmt - f);
+      w.push_back({per_elem * n, MixedItem{b, 0, f}});
+    }
+  }
+  std::stable_sort(w.begin(), w.end(), [](const W& a, const W& b) { return a.cost > b.cost; });
+  if (w.size() > 0x7fffffff) {
+    nir_mixed_plan_destroy(pl);
+    return fail(NIR_EINVAL, "too many work items");
+  }
+  pl->nitems = int(w.size());
+  std::vector<MixedItem> items(w.size());
+  for (size_t k = 0; k < w.size(); ++k) items[k] = w[k].it;
+  nir_status st = NIR_OK;
+  const size_t bsz = dtype == NIR_F64 ? sizeof(MixedBatch<double>) : sizeof(MixedBatch<float>);
+  if ((st = hip_check(hipMalloc(&pl->dbatches, bsz * nbatch), "hipMalloc")) != NIR_OK ||
+      (st = hip_check(hipMalloc((void**)&pl->ditems, sizeof(MixedItem) * std::max<size_t>(1, items.size())),
+                      "hipMalloc")) != NIR_OK ||
+      (st = hip_check(hipMalloc((void**)&pl->counter, sizeof(int)), "hipMalloc")) != NIR_OK ||
+      (st = hip_check(hipMalloc((void**)&pl->dlam, sizeof(double)), "hipMalloc")) != NIR_OK ||
+      (st = hip_check(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking), "stream")) != NIR_OK) {
+    nir_mixed_plan_destroy(pl);
+    return st;
+  }
+  if (!items.empty() &&
+      (st = hip_check(hipMemcpy(pl->ditems, items.data(), sizeof(MixedItem) * items.size(), hipMemcpyHostToDevice),
+                      "upload items")) != NIR_OK) {
+    nir_mixed_plan_destroy(pl);
+    return st;
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if ((st = hip_check(hipGetDevice(&dev), "device")) != NIR_OK ||
+      (st = hip_check(hipGetDeviceProperties(&prop, dev), "device properties")) != NIR_OK) {
+    nir_mixed_plan_destroy(pl);
+    return st;
+  }
+  pl->ncu = prop.multiProcessorCount;
+  for (int W = 2; W <= 4; ++W)
+    pl->occ[W] = std::max(1, dtype == NIR_F64 ? mixed_occupancy<double>(W) : mixed_occupancy<float>(W));
+  *out = pl;
+  return NIR_OK;
+}
+
+nir_status nir_mixed_helmholtz_apply(nir_mixed_plan* pl, double lambda, const void* const* coef_in,
+                                     void* const* coef_out, void* stream) {
+  if (!pl || !coef_in || !coef_out) return fail(NIR_EINVAL, "NULL argument");
+  if (!(lambda == lambda)) return fail(NIR_EINVAL, "lambda is NaN");
+  bool changed = false;
+  const size_t es = pl->dtype == NIR_F64 ? 8 : 4;
+  for (int b = 0; b < pl->nbatch; ++b) {
+    if (pl->batches[b].nelmt == 0) continue;
+    if (!coef_in[b] || !coef_out[b]) return fail(NIR_EINVAL, "batch %d: NULL coefficient pointer", b);
+    if ((reinterpret_cast<uintptr_t>(coef_in[b]) % es) || (reinterpret_cast<uintptr_t>(coef_out[b]) % es))
+      return fail(NIR_EINVAL, "batch %d: misaligned coefficient pointer", b);
+    const size_t nb = size_t(pl->batches[b].nelmt) * size_t(modes_of(pl->batches[b].shape, pl->batches[b].nmodes)) * es;
+    const char* i = static_cast<const char*>(coef_in[b]);
+    const char* o = static_cast<const char*>(coef_out[b]);
+    if (i < o + nb && o < i + nb) return fail(NIR_EINVAL, "batch %d: input and output overlap", b);
+    if (pl->cur_in[b] != coef_in[b] || pl->cur_out[b] != coef_out[b]) changed = true;
+  }
+  if (pl->nitems == 0) return NIR_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (changed || lambda != pl->cur_lambda) {
+    // descriptors live in device memory read by the kernel: update them in order with the caller's work
+    NIR_TRYS(hip_check(hipStreamSynchronize(s), "stream sync"));
+    for (int b = 0; b < pl->nbatch; ++b) {
+      pl->cur_in[b] = coef_in[b];
+      pl->cur_out[b] = coef_out[b];
+    }
+    NIR_TRYS(pl->dtype == NIR_F64 ? upload_batches<double>(pl) : upload_batches<float>(pl));
+    NIR_TRYS(hip_check(hipMemcpy(pl->dlam, &lambda, sizeof(double), hipMemcpyHostToDevice), "upload lambda"));
+    pl->cur_lambda = lambda;
+  }
+  if (!pl->exec) {
+    // tune the persistent grid on these operands, then capture [reset, kernel]
+    double best = 1e300;
+    int best_g = pl->ncu, best_w = 2;
+    for (int W = 2; W <= 4; ++W)
+      for (int per_cu = 1; per_cu <= std::min(8, pl->occ[W]); ++per_cu) {
+        double ms = 0;
+        NIR_TRYS(time_grid(pl, W, per_cu * pl->ncu, 3, &ms));
+        if (ms < best) {
+          best = ms;
+          best_g = per_cu * pl->ncu;
+          best_w = W;
+        }
+      }
+    pl->grid = best_g;
+    pl->waves = best_w;
+    pl->tuned_ms = best;
+    hipGraph_t g = nullptr;
+    NIR_TRYS(hip_check(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal), "begin capture"));
+    const nir_status st = enqueue(pl, pl->cap, pl->waves, pl->grid);
+    const nir_status st2 = hip_check(hipStreamEndCapture(pl->cap, &g), "end capture");
+    if (st != NIR_OK) return st;
+    if (st2 != NIR_OK) return st2;
+    const nir_status st3 = hip_check(hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0), "graph instantiate");
+    (void)hipGraphDestroy(g);
+    if (st3 != NIR_OK) return st3;
+    NIR_TRYS(hip_check(hipStreamSynchronize(pl->cap), "sync"));
+  }
+  return hip_check(hipGraphLaunch(pl->exec, s), "graph launch");
+}
+
+nir_status nir_mixed_plan_info(const nir_mixed_plan* pl, int32_t* nitems, int32_t* grid, double* tuned_ms,
+                               int64_t* bytes, int64_t* dof) {
+  if (!pl) return fail(NIR_EINVAL, "plan is NULL");
+  if (nitems) *nitems = pl->nitems;
+  if (grid) *grid = pl->grid;
+  if (tuned_ms) *tuned_ms = pl->tuned_ms;
+  if (bytes) *bytes = pl->bytes;
+  if (dof) *dof = pl->dof;
+  return NIR_OK;
+}
+
+}  // extern "C"

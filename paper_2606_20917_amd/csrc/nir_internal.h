@@ -69,9 +69,6 @@ struct DevTab {
   const int32_t* mode_pqr;
 };
 
-nir_status launch_points(const nir_basis* b, int64_t nelmt, const double* verts, double amp, double* xyz,
-                         hipStream_t s);
-
 }  // namespace nir
 
 struct nir_basis {
@@ -87,6 +84,10 @@ struct nir_basis {
   void* devpencil = nullptr;
   const double* pencil64 = nullptr;
   const float* pencil32 = nullptr;
+  // zero-padded [16][16] FP32 basis tiles for the MFMA kernels (B^T, B'^T, B, B') and their
+  // power-of-two split scales
+  float* mfma_tabs = nullptr;
+  float* mfma_scale = nullptr;
   const void* table_dev[NIR_TAB_COUNT];
 };
 
@@ -136,6 +137,7 @@ nir_status launch_geom(const nir_basis* b, int deformed, int64_t nelmt, const do
                        double amp, double* dxi_dx, double* jac, double* helm64, float* helm32,
                        hipStream_t s);
 
+nir_status launch_helm_hex_f16split(const nir_basis* b, int deformed, const OpArgs& a, hipStream_t s);
 nir_status launch_points(const nir_basis* b, int64_t nelmt, const double* verts, double amp, double* xyz,
                          hipStream_t s);
 

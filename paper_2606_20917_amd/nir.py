@@ -17,7 +17,7 @@ F64, F32 = 0, 1
 MATH_NATIVE, MATH_F16SPLIT = 0, 1
 MAP_VERTEX, MAP_VERTEX_SIN = 0, 1
 VARIANT_AUTO, VARIANT_GENERIC, VARIANT_PENCIL = 0, 1, 2
-CG_FP64, CG_MIXED_F32 = 0, 1
+CG_FP64, CG_MIXED_F32, CG_MIXED_F16SPLIT = 0, 1, 2
 
 (TAB_Z1, TAB_Z2, TAB_Z3, TAB_W1, TAB_W2, TAB_W3, TAB_T1, TAB_DT1, TAB_T2, TAB_DT2, TAB_T3, TAB_DT3,
  TAB_D1, TAB_D2, TAB_D3, TAB_WQ, TAB_XI, TAB_MODE_PQR, TAB_POINT_IJK, TAB_PAIR) = range(20)
@@ -81,6 +81,10 @@ _SIGS = {
                                   ctypes.POINTER(_vp)]),
     "nir_cg_solve": (_i32, [_vp, _i32, _vp, _vp, _dbl, _i32, _dbl, ctypes.POINTER(nir_cg_info), _vp]),
     "nir_cg_plan_destroy": (_i32, [_vp]),
+    "nir_mixed_plan_create": (_i32, [_i32, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    "nir_mixed_helmholtz_apply": (_i32, [_vp, _dbl, _vp, _vp, _vp]),
+    "nir_mixed_plan_info": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "nir_mixed_plan_destroy": (_i32, [_vp]),
     "nir_get_helmholtz_variant": (_i32, [_i32, _i32, _i32]),
 }
 
@@ -310,3 +314,44 @@ def nir_cg_solve(plan, mode, b, x, rtol=1e-10, maxit=100000, inner_rtol=1e-4, st
     if check:
         _check(st)
     return st, info
+
+
+class MixedPlan:
+    """Owner of a nir_mixed_plan: batches (list of nir_batch), bases (list of Basis), geoms (list of
+    nir_geom, helm used).  Keeps them alive with the plan."""
+
+    def __init__(self, batches, bases, geoms):
+        n = len(batches)
+        self._b = (nir_batch * n)(*batches)
+        self._h = (ctypes.c_void_p * n)(*[_basis(x).value if hasattr(_basis(x), "value") else _basis(x)
+                                          for x in bases])
+        self._g = (nir_geom * n)(*geoms)
+        h = ctypes.c_void_p()
+        _check(lib().nir_mixed_plan_create(n, ctypes.cast(self._b, _vp), ctypes.cast(self._h, _vp),
+                                           ctypes.cast(self._g, _vp), ctypes.byref(h)))
+        self.handle, self.n, self._keep = h, n, (batches, bases, geoms)
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.nir_mixed_plan_destroy(self.handle)
+            self.handle = None
+
+    def info(self):
+        ni, g = ctypes.c_int32(), ctypes.c_int32()
+        ms = ctypes.c_double()
+        by, dof = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().nir_mixed_plan_info(self.handle, ctypes.byref(ni), ctypes.byref(g), ctypes.byref(ms),
+                                         ctypes.byref(by), ctypes.byref(dof)))
+        return dict(nitems=ni.value, grid=g.value, tuned_ms=ms.value, bytes=by.value, dof=dof.value)
+
+
+def nir_mixed_plan_create(batches, bases, geoms):
+    return MixedPlan(batches, bases, geoms)
+
+
+def nir_mixed_helmholtz_apply(plan, lam, coef_in, coef_out, stream=None):
+    n = plan.n
+    ins = (ctypes.c_void_p * n)(*[_ptr(x) for x in coef_in])
+    outs = (ctypes.c_void_p * n)(*[_ptr(x) for x in coef_out])
+    _check(lib().nir_mixed_helmholtz_apply(plan.handle, lam, ctypes.cast(ins, _vp), ctypes.cast(outs, _vp),
+                                           _stream(stream)))

@@ -143,6 +143,22 @@ def test_operators_match_oracle(case, P, dtype):
     finally:
         nir.nir_set_helmholtz_variant(shape, P, dtype, nir.VARIANT_AUTO)
 
+    if dtype == nir.F32:
+        bs = nir.batch(shape, P, ne, nir.F32, s["deformed"], math=nir.MATH_F16SPLIT)
+        if shape == nir.HEX:
+            # FP16-split MFMA products, FP32 accumulation: same bar as the FP32 Helmholtz apply
+            for lam in (1.0, 0.0, 3.0):
+                nir.nir_helmholtz_apply(bs, s["basis"], g, lam, dc, cout)
+                torch.cuda.synchronize()
+                assert elem_relerr(cout.cpu().numpy(), op.helmholtz(tab, geo, lam, coef)) <= tol * 10, ("f16s", lam)
+        else:
+            with pytest.raises(nir.NirError) as e:
+                nir.nir_helmholtz_apply(bs, s["basis"], g, 1.0, dc, cout)
+            assert e.value.status == 2
+        with pytest.raises(nir.NirError) as e:
+            nir.nir_bwd_trans(bs, s["basis"], dc, out)
+        assert e.value.status == 2
+
 
 def test_config_hex_jitter64_full():
     """4x4x4 jittered trilinear hexes, P=4, Q=5: Helmholtz, BwdTrans and IProductWRTBase."""

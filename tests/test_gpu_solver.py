@@ -104,7 +104,7 @@ def _check_solution(pr, x, rtol):
     return np.linalg.norm(b - Ax) / np.linalg.norm(b), b
 
 
-@pytest.mark.parametrize("mode", [nir.CG_FP64, nir.CG_MIXED_F32])
+@pytest.mark.parametrize("mode", [nir.CG_FP64, nir.CG_MIXED_F32, nir.CG_MIXED_F16SPLIT])
 def test_cg_reaches_tolerance(mode):
     pr = _problem(4, 4)
     bg = _gpu_rhs(pr)
