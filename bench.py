@@ -247,6 +247,70 @@ def bench_mixed(args):
     print(json.dumps(out), flush=True)
 
 
+def collapsed_model(shape, P, s, deformed):
+    """Algorithmic bytes and FLOPs per element of the fused Helmholtz apply on a collapsed shape."""
+    Q = P + 1
+    M = P * P * (P + 1) // 2 if shape == 1 else P * (P + 1) * (P + 2) // 6
+    npts = Q ** 3 if deformed else 1
+    byts = s * (2 * M + 7 * npts)
+    pair_q2 = (P * P if shape == 1 else P * (P + 1) // 2) * Q * Q
+    flops = 4 * (M * Q + pair_q2 + P * Q ** 3) + 12 * Q ** 4 + (30 if shape == 1 else 40) * Q ** 3
+    return M, byts, flops
+
+
+def bench_collapsed(args):
+    """24^3 cube split into 82944 affine tets (per-element factors) or 27648 prisms (per-point
+    factors), P in {3, 5, 8}: fused Helmholtz GDoF/s against the FP64-VALU (tet) or HBM (prism) roofline."""
+    import torch
+    from paper_2606_20917_amd import inputs, nir
+    dev = torch.device("cuda")
+    out = {"metric": "collapsed-shape Helmholtz apply GDoF/s and roofline fraction", "unit": "GDoF/s",
+           "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "tet24 (82944 affine tets, per-element factors) and prism24 (27648 prisms, "
+                                  "per-point factors), 24^3 cube with +-0.03h jitter, lambda=1, Q=P+1"}}
+    for name, gen, shape in (("tet", inputs.tet24, nir.TET), ("prism", inputs.prism24, nir.PRISM)):
+        for dt_name, dt in (("f64", nir.F64), ("f32", nir.F32)):
+            s = 8 if dt == nir.F64 else 4
+            tdt = torch.float64 if dt == nir.F64 else torch.float32
+            for P in (3, 5, 8):
+                c = gen(P)
+                ne, Q, deformed = len(c["verts"]), P + 1, c["deformed"]
+                npts = Q ** 3 if deformed else 1
+                basis = nir.Basis(shape, P)
+                helm = torch.empty(ne, 7, npts, dtype=torch.float64, device=dev)
+                helm32 = torch.empty(ne, 7, npts, dtype=torch.float32, device=dev)
+                nir.nir_geom_from_vertices(nir.batch(shape, P, ne, nir.F64, deformed), basis,
+                                           torch.tensor(c["verts"], device=dev), nir.MAP_VERTEX, 0.0, None, None,
+                                           helm, helm32)
+                g = nir.geom(None, None, helm if dt == nir.F64 else helm32)
+                b = nir.batch(shape, P, ne, dt, deformed)
+                M, byts, flops = collapsed_model(shape, P, s, deformed)
+                per_set = ne * byts
+                nsets = max(1, math.ceil(ROTATE_BYTES / per_set))
+                x = torch.tensor(c["coef"], dtype=tdt, device=dev)
+                sets = [(x, torch.empty_like(x))] + [(x.clone(), torch.empty_like(x)) for _ in range(nsets - 1)]
+                for it in range(args.warmup):
+                    nir.nir_helmholtz_apply(b, basis, g, 1.0, *sets[it % nsets])
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for it in range(args.steps):
+                    nir.nir_helmholtz_apply(b, basis, g, 1.0, *sets[it % nsets])
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / args.steps
+                gbs = ne * byts / ms / 1e6
+                tfl = ne * flops / ms / 1e9
+                peak_fl = 78.6 if dt == nir.F64 else 157.3
+                out[f"{name}_P{P}_{dt_name}"] = {
+                    "nelmt": ne, "ms": round(ms, 4), "gdofs": round(ne * M / ms / 1e6, 3), "gbs": round(gbs, 1),
+                    "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "tflops": round(tfl, 2),
+                    "frac_valu": round(tfl / peak_fl, 4),
+                    "bound": "hbm" if byts * 9.8 > flops or deformed else "alu"}
+    out["value"] = out["tet_P5_f64"]["gdofs"]
+    print(json.dumps(out), flush=True)
+
+
 def bench_copy(args):
     """Plain device copy of 1 GiB (calibrates the HBM byte counters: read 1 GiB, write 1 GiB)."""
     import torch
@@ -278,7 +342,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variant", default="auto", choices=["auto", "generic", "pencil"])
     ap.add_argument("--math", default="native", choices=["native", "f16split"])
-    ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k", "copy"])
+    ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k", "collapsed", "copy"])
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -295,6 +359,8 @@ def main():
         return bench_mixed(args)
     if args.workload == "copy":
         return bench_copy(args)
+    if args.workload == "collapsed":
+        return bench_collapsed(args)
     ps = [int(p) for p in args.ps.split(",")]
     vid = {"auto": nir.VARIANT_AUTO, "generic": nir.VARIANT_GENERIC, "pencil": nir.VARIANT_PENCIL}[args.variant]
     for P in ps:

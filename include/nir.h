@@ -278,17 +278,33 @@ nir_status nir_cg_solve(nir_cg_plan* plan, int32_t mode, const double* b, double
                         double inner_rtol, nir_cg_info* info, void* stream);
 nir_status nir_cg_plan_destroy(nir_cg_plan* plan);
 
-/* ------------------------------------------------------------------ kernel variants
- * Several kernels implement the fused Helmholtz apply; the choice per (shape, P, dtype)
- * is library-global state (one int per combination, set atomically):
- *   NIR_VARIANT_AUTO     the tuned choice (from nir_autotune_helmholtz or the built-in default)
- *   NIR_VARIANT_GENERIC  LDS-staged kernel, threads over points/modes (any shape)
- *   NIR_VARIANT_PENCIL   register-pencil kernel with uniform basis operands (hex only)
+/* ------------------------------------------------------------------ kernel variants and autotuning
+ * Several kernels implement the fused Helmholtz apply (native contractions); the choice per
+ * (shape, P, dtype) is library-global state (one int per combination, set atomically), used by
+ * nir_helmholtz_apply and by the CG plans' element apply:
+ *   NIR_VARIANT_AUTO       built-in default (pencil for hexahedra, generic otherwise)
+ *   NIR_VARIANT_GENERIC    LDS-staged kernel, threads over points/modes (any shape)
+ *   NIR_VARIANT_PENCIL     register-pencil kernel with uniform basis operands (hex only)
+ *   NIR_VARIANT_PENCIL_U2  the same with the streamed point loop unrolled twice (hex only)
  * Setting a variant a shape does not support returns NIR_ENOTSUP. */
-typedef enum { NIR_VARIANT_AUTO = 0, NIR_VARIANT_GENERIC = 1, NIR_VARIANT_PENCIL = 2 } nir_variant;
+typedef enum { NIR_VARIANT_AUTO = 0, NIR_VARIANT_GENERIC = 1, NIR_VARIANT_PENCIL = 2,
+               NIR_VARIANT_PENCIL_U2 = 3 } nir_variant;
 nir_status nir_set_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype, int32_t variant);
 /* The variant a call with these parameters would run now (never NIR_VARIANT_AUTO); -1 if invalid. */
 int32_t nir_get_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype);
+/* Autotuner: times every variant applicable to the batch's shape on the caller's operands
+ * (one warm-up and `reps` timed applies each, hipEvents on `stream`; coef_out is overwritten),
+ * selects the fastest for (shape, P, dtype) and returns it in *chosen.  ms_per_variant, if not
+ * NULL, receives the average time of each variant at index variant-1 (3 doubles; untried
+ * entries untouched).  Synchronises the stream. */
+nir_status nir_autotune_helmholtz(const nir_batch* batch, const nir_basis* basis, const nir_geom* geom,
+                                  double lambda, const void* coef_in, void* coef_out, int32_t reps,
+                                  int32_t* chosen, double* ms_per_variant, void* stream);
+/* JSON cache of the variant table: save writes every non-AUTO entry; load applies the entries of
+ * a file written by save only if the whole file parses and validates (NIR_EINVAL otherwise, the
+ * table unchanged).  Host only. */
+nir_status nir_autotune_save(const char* path);
+nir_status nir_autotune_load(const char* path);
 
 #ifdef __cplusplus
 }

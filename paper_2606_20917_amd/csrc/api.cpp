@@ -7,6 +7,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "helm_hex.h"
@@ -96,6 +97,14 @@ static int resolve_variant(int shape, int P, int dtype) {
   const int v = g_variant[shape][P][dtype].load(std::memory_order_relaxed);
   if (v != NIR_VARIANT_AUTO) return v;
   return shape == kHex ? NIR_VARIANT_PENCIL : NIR_VARIANT_GENERIC;
+}
+
+// the fused Helmholtz apply with the selected kernel variant (native contractions)
+nir_status launch_helm_auto(const nir_basis* basis, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
+  const int v = resolve_variant(basis->shape, basis->P, dtype);
+  if (v == NIR_VARIANT_PENCIL) return launch_helm_hex_pencil(basis, dtype, deformed, a, s, 1);
+  if (v == NIR_VARIANT_PENCIL_U2) return launch_helm_hex_pencil(basis, dtype, deformed, a, s, 2);
+  return launch_generic(basis, kOpHelm, dtype, deformed, a, s);
 }
 
 }  // namespace nir
@@ -446,16 +455,128 @@ nir_status nir_helmholtz_apply(const nir_batch* b, const nir_basis* basis, const
     if (b->shape != kHex) return fail(NIR_ENOTSUP, "FP16-split contractions are implemented for hexahedra");
     return launch_helm_hex_f16split(basis, b->deformed, a, static_cast<hipStream_t>(stream));
   }
-  if (resolve_variant(b->shape, b->nmodes, b->dtype) == NIR_VARIANT_PENCIL)
-    return launch_helm_hex_pencil(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
-  return launch_generic(basis, kOpHelm, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+  return launch_helm_auto(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+}
+
+nir_status nir_autotune_helmholtz(const nir_batch* b, const nir_basis* basis, const nir_geom* g, double lambda,
+                                  const void* coef_in, void* coef_out, int32_t reps, int32_t* chosen,
+                                  double* ms_per_variant, void* stream) {
+  NIR_TRY(check_batch(b, basis));
+  NIR_TRY(native_only(b));
+  if (b->nelmt == 0) return fail(NIR_EINVAL, "cannot tune on an empty batch");
+  if (reps < 1 || reps > 1000) return fail(NIR_EINVAL, "reps must be in [1, 1000]");
+  NIR_TRY(check_geom(b, g, false, false, true));
+  NIR_TRY(check_ptr(b, coef_in, "coef_in"));
+  NIR_TRY(check_ptr(b, coef_out, "coef_out"));
+  const size_t es = elem_size(b), n = size_t(b->nelmt), cb = n * basis->M * es;
+  if (overlap(coef_out, cb, coef_in, cb)) return fail(NIR_EINVAL, "coef_in and coef_out overlap");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  OpArgs a{};
+  a.in0 = coef_in;
+  a.out0 = coef_out;
+  a.helm = g->helm;
+  a.lambda = lambda;
+  a.nelmt = b->nelmt;
+  std::atomic<int>& slot = g_variant[b->shape][b->nmodes][b->dtype];
+  const int before = slot.load();
+  const int cands_hex[3] = {NIR_VARIANT_GENERIC, NIR_VARIANT_PENCIL, NIR_VARIANT_PENCIL_U2};
+  const int cands_other[1] = {NIR_VARIANT_GENERIC};
+  const int* cands = b->shape == kHex ? cands_hex : cands_other;
+  const int nc = b->shape == kHex ? 3 : 1;
+  hipEvent_t e0, e1;
+  NIR_TRY(hip_check(hipEventCreate(&e0), "event"));
+  NIR_TRY(hip_check(hipEventCreate(&e1), "event"));
+  double best = 1e300;
+  int best_v = cands[0];
+  nir_status st = NIR_OK;
+  for (int c = 0; c < nc && st == NIR_OK; ++c) {
+    slot.store(cands[c]);
+    st = launch_helm_auto(basis, b->dtype, b->deformed, a, s);   // warm-up
+    if (st == NIR_OK) st = hip_check(hipEventRecord(e0, s), "event record");
+    for (int r = 0; r < reps && st == NIR_OK; ++r) st = launch_helm_auto(basis, b->dtype, b->deformed, a, s);
+    if (st == NIR_OK) st = hip_check(hipEventRecord(e1, s), "event record");
+    if (st == NIR_OK) st = hip_check(hipEventSynchronize(e1), "event sync");
+    float t = 0.f;
+    if (st == NIR_OK) st = hip_check(hipEventElapsedTime(&t, e0, e1), "elapsed");
+    const double ms = double(t) / reps;
+    if (ms_per_variant) ms_per_variant[cands[c] - 1] = ms;
+    if (st == NIR_OK && ms < best) {
+      best = ms;
+      best_v = cands[c];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != NIR_OK) {
+    slot.store(before);
+    return st;
+  }
+  slot.store(best_v);
+  if (chosen) *chosen = best_v;
+  return NIR_OK;
+}
+
+nir_status nir_autotune_save(const char* path) {
+  if (!path) return fail(NIR_EINVAL, "path is NULL");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(NIR_EINVAL, "cannot open %s for writing", path);
+  std::fprintf(f, "{\"format\": \"libnir-autotune-1\", \"entries\": [\n");
+  bool first = true;
+  for (int sh = 0; sh < 3; ++sh)
+    for (int P = kMinP; P <= kMaxP; ++P)
+      for (int dt = 0; dt < 2; ++dt) {
+        const int v = g_variant[sh][P][dt].load();
+        if (v == NIR_VARIANT_AUTO) continue;
+        std::fprintf(f, "%s{\"shape\": %d, \"P\": %d, \"dtype\": %d, \"variant\": %d}", first ? "" : ",\n", sh, P, dt, v);
+        first = false;
+      }
+  std::fprintf(f, "\n]}\n");
+  const bool ok = std::fclose(f) == 0;
+  return ok ? NIR_OK : fail(NIR_EINVAL, "write to %s failed", path);
+}
+
+nir_status nir_autotune_load(const char* path) {
+  if (!path) return fail(NIR_EINVAL, "path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(NIR_EINVAL, "cannot open %s", path);
+  std::string txt;
+  char buf[4096];
+  size_t k;
+  while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, k);
+  std::fclose(f);
+  if (txt.find("\"format\": \"libnir-autotune-1\"") == std::string::npos)
+    return fail(NIR_EINVAL, "%s is not a libnir autotune cache", path);
+  // parse every {"shape": s, "P": p, "dtype": d, "variant": v} object; apply only if all are valid
+  struct Ent { int s, P, d, v; };
+  std::vector<Ent> ents;
+  size_t pos = txt.find('[');
+  if (pos == std::string::npos || txt.find(']', pos) == std::string::npos)
+    return fail(NIR_EINVAL, "%s: malformed entry list", path);
+  const size_t end = txt.find(']', pos);
+  while (true) {
+    const size_t ob = txt.find('{', pos);
+    if (ob == std::string::npos || ob > end) break;
+    const size_t cb = txt.find('}', ob);
+    if (cb == std::string::npos || cb > end) return fail(NIR_EINVAL, "%s: unterminated entry", path);
+    Ent e{};
+    if (std::sscanf(txt.c_str() + ob, "{\"shape\": %d, \"P\": %d, \"dtype\": %d, \"variant\": %d}", &e.s, &e.P,
+                    &e.d, &e.v) != 4)
+      return fail(NIR_EINVAL, "%s: malformed entry at offset %zu", path, ob);
+    if (e.s < 0 || e.s > 2 || e.P < kMinP || e.P > kMaxP || e.d < 0 || e.d > 1 || e.v < NIR_VARIANT_AUTO ||
+        e.v > NIR_VARIANT_PENCIL_U2 || (e.s != kHex && e.v >= NIR_VARIANT_PENCIL))
+      return fail(NIR_EINVAL, "%s: invalid entry at offset %zu", path, ob);
+    ents.push_back(e);
+    pos = cb + 1;
+  }
+  for (const Ent& e : ents) g_variant[e.s][e.P][e.d].store(e.v);
+  return NIR_OK;
 }
 
 nir_status nir_set_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype, int32_t variant) {
   if (shape < kHex || shape > kTet || P < kMinP || P > kMaxP || (dtype != NIR_F64 && dtype != NIR_F32))
     return fail(NIR_EINVAL, "invalid (shape %d, P %d, dtype %d)", shape, P, dtype);
-  if (variant < NIR_VARIANT_AUTO || variant > NIR_VARIANT_PENCIL) return fail(NIR_EINVAL, "invalid variant %d", variant);
-  if (variant == NIR_VARIANT_PENCIL && shape != kHex) return fail(NIR_ENOTSUP, "the pencil kernel is hex only");
+  if (variant < NIR_VARIANT_AUTO || variant > NIR_VARIANT_PENCIL_U2) return fail(NIR_EINVAL, "invalid variant %d", variant);
+  if (variant >= NIR_VARIANT_PENCIL && shape != kHex) return fail(NIR_ENOTSUP, "the pencil kernels are hex only");
   g_variant[shape][P][dtype].store(variant, std::memory_order_relaxed);
   return NIR_OK;
 }

@@ -303,7 +303,7 @@ static nir_status apply_local(nir_cg_plan* pl, int dtype, hipStream_t s, const v
     a.in0 = pl->xl;
     a.out0 = pl->yl;
     a.helm = pl->g64.helm;
-    NIR_TRYS(launch_helm_hex_pencil(pl->basis, NIR_F64, pl->b64.deformed, a, s));
+    NIR_TRYS(launch_helm_auto(pl->basis, NIR_F64, pl->b64.deformed, a, s));
     hipLaunchKernelGGL(k_scatter<double>, grid_for(pl->ng), dim3(256), 0, s, A->off, A->idx, pl->yl,
                        static_cast<double*>(yg), pl->ng);
   } else {
@@ -315,7 +315,7 @@ static nir_status apply_local(nir_cg_plan* pl, int dtype, hipStream_t s, const v
     if (pl->f16split)
       NIR_TRYS(launch_helm_hex_f16split(pl->basis, pl->b64.deformed, a, s));
     else
-      NIR_TRYS(launch_helm_hex_pencil(pl->basis, NIR_F32, pl->b64.deformed, a, s));
+      NIR_TRYS(launch_helm_auto(pl->basis, NIR_F32, pl->b64.deformed, a, s));
     hipLaunchKernelGGL(k_scatter<float>, grid_for(pl->ng), dim3(256), 0, s, A->off, A->idx, pl->yl32,
                        static_cast<float*>(yg), pl->ng);
   }

@@ -31,6 +31,8 @@ struct HexTabView {
   __device__ __forceinline__ HexTabView(const T* __restrict__ base) : p(base), B{base}, D{base + (P + 1) * P} {}
 };
 
-nir_status launch_helm_hex_pencil(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
+// iu: unroll factor of the streamed point loop (1 or 2)
+nir_status launch_helm_hex_pencil(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s,
+                                  int iu = 1);
 
 }  // namespace nir

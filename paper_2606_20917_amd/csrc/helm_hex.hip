@@ -31,17 +31,18 @@
 
 namespace nir {
 
-template <int P, class T, bool DEF>
+template <int P, class T, bool DEF, int IU>
 __global__ void __launch_bounds__(256) k_helm_hex(const T* __restrict__ tabs, const T* __restrict__ x,
                                                   T* __restrict__ y, const T* __restrict__ helm,
                                                   const T* __restrict__ wq, T lambda, int64_t nelmt) {
   // one element group per block (no grid-stride loop: the basis operands stay short-lived)
   __shared__ T lds[HexPencilDims<P, T>::LDS];
-  helm_hex_group<P, T, DEF>(tabs, x, y, helm, wq, lambda, nelmt, int64_t(blockIdx.x) * HexPencilDims<P, T>::E, lds);
+  helm_hex_group<P, T, DEF, IU>(tabs, x, y, helm, wq, lambda, nelmt, int64_t(blockIdx.x) * HexPencilDims<P, T>::E,
+                                lds);
 }
 
 template <int P, class T>
-static nir_status launch_P(const nir_basis* b, int deformed, const OpArgs& a, hipStream_t s) {
+static nir_status launch_P(const nir_basis* b, int deformed, int iu, const OpArgs& a, hipStream_t s) {
   constexpr int Q2 = (P + 1) * (P + 1);
   constexpr int E = 256 / Q2;
   const T* tb = sizeof(T) == 8 ? reinterpret_cast<const T*>(b->pencil64) : reinterpret_cast<const T*>(b->pencil32);
@@ -49,19 +50,26 @@ static nir_status launch_P(const nir_basis* b, int deformed, const OpArgs& a, hi
   if (nb > 0x7fffffff) return fail(NIR_EINVAL, "too many elements for one launch");
   const dim3 grid(static_cast<unsigned>(nb)), block(256);
   const T* wq = sizeof(T) == 8 ? reinterpret_cast<const T*>(b->t64.wq) : reinterpret_cast<const T*>(b->t32.wq);
-  if (deformed)
-    hipLaunchKernelGGL((k_helm_hex<P, T, true>), grid, block, 0, s, tb, static_cast<const T*>(a.in0),
-                       static_cast<T*>(a.out0), static_cast<const T*>(a.helm), wq, T(a.lambda), a.nelmt);
+  const T* x = static_cast<const T*>(a.in0);
+  T* y = static_cast<T*>(a.out0);
+  const T* helm = static_cast<const T*>(a.helm);
+  const T lam = T(a.lambda);
+  if (deformed && iu == 2)
+    hipLaunchKernelGGL((k_helm_hex<P, T, true, 2>), grid, block, 0, s, tb, x, y, helm, wq, lam, a.nelmt);
+  else if (deformed)
+    hipLaunchKernelGGL((k_helm_hex<P, T, true, 1>), grid, block, 0, s, tb, x, y, helm, wq, lam, a.nelmt);
+  else if (iu == 2)
+    hipLaunchKernelGGL((k_helm_hex<P, T, false, 2>), grid, block, 0, s, tb, x, y, helm, wq, lam, a.nelmt);
   else
-    hipLaunchKernelGGL((k_helm_hex<P, T, false>), grid, block, 0, s, tb, static_cast<const T*>(a.in0),
-                       static_cast<T*>(a.out0), static_cast<const T*>(a.helm), wq, T(a.lambda), a.nelmt);
+    hipLaunchKernelGGL((k_helm_hex<P, T, false, 1>), grid, block, 0, s, tb, x, y, helm, wq, lam, a.nelmt);
   return hip_check(hipGetLastError(), "hex Helmholtz launch");
 }
 
-nir_status launch_helm_hex_pencil(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
-#define NIR_CASE(PP)                                                                    \
-  case PP:                                                                              \
-    return dtype == NIR_F64 ? launch_P<PP, double>(b, deformed, a, s) : launch_P<PP, float>(b, deformed, a, s);
+nir_status launch_helm_hex_pencil(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s,
+                                  int iu) {
+#define NIR_CASE(PP)                                                                                   \
+  case PP:                                                                                             \
+    return dtype == NIR_F64 ? launch_P<PP, double>(b, deformed, iu, a, s) : launch_P<PP, float>(b, deformed, iu, a, s);
   switch (b->P) {
     NIR_CASE(2) NIR_CASE(3) NIR_CASE(4) NIR_CASE(5) NIR_CASE(6)
     NIR_CASE(7) NIR_CASE(8) NIR_CASE(9) NIR_CASE(10)

@@ -4,10 +4,6 @@
 
 #include "helm_hex.h"
 
-#ifndef NIR_HEX_IUNROLL
-#define NIR_HEX_IUNROLL 1
-#endif
-
 namespace nir {
 
 template <int P, class T>
@@ -22,7 +18,8 @@ struct HexPencilDims {
 
 // One group of up to E elements starting at `base`, on a block of 256 threads; `lds` holds
 // HexPencilDims<P,T>::LDS values.  Every thread of the block must call it (it synchronises).
-template <int P, class T, bool DEF>
+// IU is the unroll factor of the streamed point loop (register pressure vs. loads in flight).
+template <int P, class T, bool DEF, int IU = 1>
 __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const T* __restrict__ x, T* __restrict__ y,
                                                const T* __restrict__ helm, const T* __restrict__ wq, T lambda,
                                                int64_t nelmt, int64_t base, T* __restrict__ lds) {
@@ -127,7 +124,7 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
 #pragma unroll
     for (int p = 0; p < P; ++p) t0[p] = t1[p] = t2[p] = T(0);
     const T* g = helm + (valid ? e : 0) * (DEF ? 7 * NQ : 7);
-#pragma unroll NIR_HEX_IUNROLL
+#pragma unroll IU
     for (int i = 0; i < Q; ++i) {
       T u = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
 #pragma unroll

@@ -138,6 +138,8 @@ nir_status launch_geom(const nir_basis* b, int deformed, int64_t nelmt, const do
                        hipStream_t s);
 
 nir_status launch_helm_hex_f16split(const nir_basis* b, int deformed, const OpArgs& a, hipStream_t s);
+// the fused Helmholtz apply with the currently selected kernel variant (native contractions)
+nir_status launch_helm_auto(const nir_basis* basis, int dtype, int deformed, const OpArgs& a, hipStream_t s);
 nir_status launch_points(const nir_basis* b, int64_t nelmt, const double* verts, double amp, double* xyz,
                          hipStream_t s);
 

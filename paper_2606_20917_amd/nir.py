@@ -16,7 +16,7 @@ HEX, PRISM, TET = 0, 1, 2
 F64, F32 = 0, 1
 MATH_NATIVE, MATH_F16SPLIT = 0, 1
 MAP_VERTEX, MAP_VERTEX_SIN = 0, 1
-VARIANT_AUTO, VARIANT_GENERIC, VARIANT_PENCIL = 0, 1, 2
+VARIANT_AUTO, VARIANT_GENERIC, VARIANT_PENCIL, VARIANT_PENCIL_U2 = 0, 1, 2, 3
 CG_FP64, CG_MIXED_F32, CG_MIXED_F16SPLIT = 0, 1, 2
 
 (TAB_Z1, TAB_Z2, TAB_Z3, TAB_W1, TAB_W2, TAB_W3, TAB_T1, TAB_DT1, TAB_T2, TAB_DT2, TAB_T3, TAB_DT3,
@@ -86,6 +86,10 @@ _SIGS = {
     "nir_mixed_plan_info": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "nir_mixed_plan_destroy": (_i32, [_vp]),
     "nir_get_helmholtz_variant": (_i32, [_i32, _i32, _i32]),
+    "nir_autotune_helmholtz": (_i32, [ctypes.POINTER(nir_batch), _vp, ctypes.POINTER(nir_geom), _dbl, _vp, _vp, _i32,
+                                      _vp, _vp, _vp]),
+    "nir_autotune_save": (_i32, [ctypes.c_char_p]),
+    "nir_autotune_load": (_i32, [ctypes.c_char_p]),
 }
 
 
@@ -355,3 +359,20 @@ def nir_mixed_helmholtz_apply(plan, lam, coef_in, coef_out, stream=None):
     outs = (ctypes.c_void_p * n)(*[_ptr(x) for x in coef_out])
     _check(lib().nir_mixed_helmholtz_apply(plan.handle, lam, ctypes.cast(ins, _vp), ctypes.cast(outs, _vp),
                                            _stream(stream)))
+
+
+def nir_autotune_helmholtz(b, basis, g, lam, coef_in, coef_out, reps=10, stream=None):
+    """Returns (chosen variant, {variant: ms})."""
+    ch = ctypes.c_int32()
+    ms = (ctypes.c_double * 3)(-1.0, -1.0, -1.0)
+    _check(lib().nir_autotune_helmholtz(ctypes.byref(b), _basis(basis), ctypes.byref(g), lam, _ptr(coef_in),
+                                        _ptr(coef_out), reps, ctypes.byref(ch), ctypes.cast(ms, _vp), _stream(stream)))
+    return ch.value, {v + 1: ms[v] for v in range(3) if ms[v] >= 0}
+
+
+def nir_autotune_save(path):
+    _check(lib().nir_autotune_save(path.encode()))
+
+
+def nir_autotune_load(path):
+    _check(lib().nir_autotune_load(path.encode()))

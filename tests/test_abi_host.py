@@ -152,3 +152,33 @@ def test_table_requests_validated():
     z = np.zeros(3)
     assert nir.lib().nir_quadrature_host(1, 3, 3, z.ctypes.data, z.ctypes.data) == 1
     assert nir.lib().nir_quadrature_host(0, 0, 3, None, None) == 1
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    try:
+        nir.nir_set_helmholtz_variant(nir.HEX, 6, nir.F64, nir.VARIANT_PENCIL_U2)
+        nir.nir_set_helmholtz_variant(nir.TET, 3, nir.F32, nir.VARIANT_GENERIC)
+        path = str(tmp_path / "tune.json")
+        nir.nir_autotune_save(path)
+        nir.nir_set_helmholtz_variant(nir.HEX, 6, nir.F64, nir.VARIANT_AUTO)
+        nir.nir_set_helmholtz_variant(nir.TET, 3, nir.F32, nir.VARIANT_AUTO)
+        assert nir.nir_get_helmholtz_variant(nir.HEX, 6, nir.F64) == nir.VARIANT_PENCIL
+        nir.nir_autotune_load(path)
+        assert nir.nir_get_helmholtz_variant(nir.HEX, 6, nir.F64) == nir.VARIANT_PENCIL_U2
+        assert nir.nir_get_helmholtz_variant(nir.TET, 3, nir.F32) == nir.VARIANT_GENERIC
+        # corrupt or invalid caches are rejected and leave the table unchanged
+        bad = tmp_path / "bad.json"
+        for txt in ("not json", '{"format": "libnir-autotune-1", "entries": [{"shape": 0, "P": 6}]}',
+                    '{"format": "libnir-autotune-1", "entries": [{"shape": 1, "P": 6, "dtype": 0, "variant": 2}]}',
+                    '{"format": "libnir-autotune-1", "entries": [{"shape": 0, "P": 12, "dtype": 0, "variant": 1}'):
+            bad.write_text(txt)
+            with pytest.raises(nir.NirError):
+                nir.nir_autotune_load(str(bad))
+            assert nir.nir_get_helmholtz_variant(nir.HEX, 6, nir.F64) == nir.VARIANT_PENCIL_U2
+        with pytest.raises(nir.NirError):
+            nir.nir_autotune_load(str(tmp_path / "missing.json"))
+        with pytest.raises(nir.NirError):   # pencil kernels are hex only
+            nir.nir_set_helmholtz_variant(nir.PRISM, 4, nir.F64, nir.VARIANT_PENCIL)
+    finally:
+        for s, P, d in ((nir.HEX, 6, nir.F64), (nir.TET, 3, nir.F32)):
+            nir.nir_set_helmholtz_variant(s, P, d, nir.VARIANT_AUTO)

@@ -131,7 +131,7 @@ def test_operators_match_oracle(case, P, dtype):
     torch.cuda.synchronize()
     assert elem_relerr(cout.cpu().numpy(), op.iprod_wrt_deriv_base(tab, geo, *f)) <= tol * 10
 
-    variants = [nir.VARIANT_GENERIC] + ([nir.VARIANT_PENCIL] if shape == nir.HEX else [])
+    variants = [nir.VARIANT_GENERIC] + ([nir.VARIANT_PENCIL, nir.VARIANT_PENCIL_U2] if shape == nir.HEX else [])
     try:
         for v in variants:
             nir.nir_set_helmholtz_variant(shape, P, dtype, v)
@@ -212,3 +212,23 @@ def test_empty_batch_and_pointer_validation():
         nir.nir_helmholtz_apply(nir.batch(nir.HEX, 3, 4), basis, g, 1.0, x.data_ptr() + 4, torch.empty_like(x))
     with pytest.raises(nir.NirError):   # basis of another order
         nir.nir_helmholtz_apply(nir.batch(nir.HEX, 4, 4), basis, g, 1.0, x, torch.empty_like(x))
+
+
+@pytest.mark.parametrize("shape,P", [(nir.HEX, 4), (nir.HEX, 7), (nir.TET, 5)])
+def test_autotune_selects_a_valid_variant(shape, P):
+    s = _setup((shape, 2, 0.05, 0.1 if shape == nir.HEX else 0.0, 1), P)
+    b = nir.batch(shape, P, s["ne"], nir.F64, 1)
+    g, _ = _geom(s, nir.F64)
+    x = _t(s["rng"].uniform(-1, 1, (s["ne"], s["tab"].M)), nir.F64)
+    y = torch.empty_like(x)
+    try:
+        v, ms = nir.nir_autotune_helmholtz(b, s["basis"], g, 1.0, x, y, reps=3)
+        assert v in ms and ms[v] == min(ms.values())
+        assert nir.nir_get_helmholtz_variant(shape, P, nir.F64) == v
+        assert set(ms) == ({1, 2, 3} if shape == nir.HEX else {1})
+        nir.nir_helmholtz_apply(b, s["basis"], g, 1.0, x, y)
+        torch.cuda.synchronize()
+        ref = op.helmholtz(s["tab"], s["geo"], 1.0, x.cpu().numpy())
+        assert elem_relerr(y.cpu().numpy(), ref) <= 10 * TOL64
+    finally:
+        nir.nir_set_helmholtz_variant(shape, P, nir.F64, nir.VARIANT_AUTO)
