@@ -31,8 +31,9 @@ struct HexTabView {
   __device__ __forceinline__ HexTabView(const T* __restrict__ base) : p(base), B{base}, D{base + (P + 1) * P} {}
 };
 
-// iu: unroll factor of the streamed point loop (1 or 2)
+// variant: 0 = E_max elements per 256-thread block, 1 = point loop unrolled twice,
+// 2 = one element per block, 3 = geometry prefetched into registers
 nir_status launch_helm_hex_pencil(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s,
-                                  int iu = 1);
+                                  int variant = 0);
 
 }  // namespace nir

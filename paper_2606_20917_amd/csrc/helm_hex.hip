@@ -31,45 +31,60 @@
 
 namespace nir {
 
-template <int P, class T, bool DEF, int IU>
+template <int P, class T, bool DEF, int IU, int E, bool PF>
 __global__ void __launch_bounds__(256) k_helm_hex(const T* __restrict__ tabs, const T* __restrict__ x,
                                                   T* __restrict__ y, const T* __restrict__ helm,
                                                   const T* __restrict__ wq, T lambda, int64_t nelmt) {
   // one element group per block (no grid-stride loop: the basis operands stay short-lived)
-  __shared__ T lds[HexPencilDims<P, T>::LDS];
-  helm_hex_group<P, T, DEF, IU>(tabs, x, y, helm, wq, lambda, nelmt, int64_t(blockIdx.x) * HexPencilDims<P, T>::E,
-                                lds);
+  __shared__ T lds[HexPencilDims<P, T, E>::LDS];
+  helm_hex_group<P, T, DEF, IU, E, PF>(tabs, x, y, helm, wq, lambda, nelmt, int64_t(blockIdx.x) * E, lds);
+}
+
+// variant: 0 = E_max elements per 256-thread block, 1 = same with the point loop unrolled twice,
+// 2 = one element per block (smaller LDS footprint, more blocks per CU), 3 = geometry prefetch
+template <int P, class T, bool DEF, int IU, int E, bool PF>
+static void launch_cfg(const T* tb, const T* x, T* y, const T* helm, const T* wq, T lam, int64_t nelmt,
+                       hipStream_t s) {
+  using D = HexPencilDims<P, T, E>;
+  const int64_t nb = (nelmt + E - 1) / E;
+  hipLaunchKernelGGL((k_helm_hex<P, T, DEF, IU, E, PF>), dim3(static_cast<unsigned>(nb)), dim3(D::BLOCK), 0, s, tb,
+                     x, y, helm, wq, lam, nelmt);
+}
+
+template <int P, class T, bool DEF>
+static void launch_var(int variant, const T* tb, const T* x, T* y, const T* helm, const T* wq, T lam,
+                       int64_t nelmt, hipStream_t s) {
+  constexpr int EMAX = 256 / ((P + 1) * (P + 1));
+  switch (variant) {
+    case 1: launch_cfg<P, T, DEF, 2, EMAX, false>(tb, x, y, helm, wq, lam, nelmt, s); break;
+    case 2: launch_cfg<P, T, DEF, 1, 1, false>(tb, x, y, helm, wq, lam, nelmt, s); break;
+    case 3: launch_cfg<P, T, DEF, 1, EMAX, true>(tb, x, y, helm, wq, lam, nelmt, s); break;
+    default: launch_cfg<P, T, DEF, 1, EMAX, false>(tb, x, y, helm, wq, lam, nelmt, s); break;
+  }
 }
 
 template <int P, class T>
-static nir_status launch_P(const nir_basis* b, int deformed, int iu, const OpArgs& a, hipStream_t s) {
-  constexpr int Q2 = (P + 1) * (P + 1);
-  constexpr int E = 256 / Q2;
+static nir_status launch_P(const nir_basis* b, int deformed, int variant, const OpArgs& a, hipStream_t s) {
   const T* tb = sizeof(T) == 8 ? reinterpret_cast<const T*>(b->pencil64) : reinterpret_cast<const T*>(b->pencil32);
-  const int64_t nb = (a.nelmt + E - 1) / E;
-  if (nb > 0x7fffffff) return fail(NIR_EINVAL, "too many elements for one launch");
-  const dim3 grid(static_cast<unsigned>(nb)), block(256);
+  if (a.nelmt > 0x7fffffff) return fail(NIR_EINVAL, "too many elements for one launch");
   const T* wq = sizeof(T) == 8 ? reinterpret_cast<const T*>(b->t64.wq) : reinterpret_cast<const T*>(b->t32.wq);
   const T* x = static_cast<const T*>(a.in0);
   T* y = static_cast<T*>(a.out0);
   const T* helm = static_cast<const T*>(a.helm);
   const T lam = T(a.lambda);
-  if (deformed && iu == 2)
-    hipLaunchKernelGGL((k_helm_hex<P, T, true, 2>), grid, block, 0, s, tb, x, y, helm, wq, lam, a.nelmt);
-  else if (deformed)
-    hipLaunchKernelGGL((k_helm_hex<P, T, true, 1>), grid, block, 0, s, tb, x, y, helm, wq, lam, a.nelmt);
-  else if (iu == 2)
-    hipLaunchKernelGGL((k_helm_hex<P, T, false, 2>), grid, block, 0, s, tb, x, y, helm, wq, lam, a.nelmt);
+  if (deformed)
+    launch_var<P, T, true>(variant, tb, x, y, helm, wq, lam, a.nelmt, s);
   else
-    hipLaunchKernelGGL((k_helm_hex<P, T, false, 1>), grid, block, 0, s, tb, x, y, helm, wq, lam, a.nelmt);
+    launch_var<P, T, false>(variant, tb, x, y, helm, wq, lam, a.nelmt, s);
   return hip_check(hipGetLastError(), "hex Helmholtz launch");
 }
 
 nir_status launch_helm_hex_pencil(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s,
-                                  int iu) {
+                                  int variant) {
 #define NIR_CASE(PP)                                                                                   \
   case PP:                                                                                             \
-    return dtype == NIR_F64 ? launch_P<PP, double>(b, deformed, iu, a, s) : launch_P<PP, float>(b, deformed, iu, a, s);
+    return dtype == NIR_F64 ? launch_P<PP, double>(b, deformed, variant, a, s)                         \
+                            : launch_P<PP, float>(b, deformed, variant, a, s);
   switch (b->P) {
     NIR_CASE(2) NIR_CASE(3) NIR_CASE(4) NIR_CASE(5) NIR_CASE(6)
     NIR_CASE(7) NIR_CASE(8) NIR_CASE(9) NIR_CASE(10)

@@ -6,24 +6,29 @@
 
 namespace nir {
 
-template <int P, class T>
+template <int P, class T, int E_ = 256 / ((P + 1) * (P + 1))>
 struct HexPencilDims {
   static constexpr int Q = P + 1, Q2 = Q * Q, NQ = Q2 * Q, M = P * P * P;
-  static constexpr int E = 256 / Q2;                      // elements per block of 256 threads
+  static constexpr int E = E_;                            // elements per block (Q^2 threads each)
+  static constexpr int BLOCK = (E * Q2 + 63) / 64 * 64;   // threads per block
   static constexpr int PP = P | 1;                        // odd stride of a mode pencil row
   static constexpr int PQ2 = P * Q2, P2Q = P * P * Q;
   static constexpr int SLAB = (3 * PQ2 > P * P * PP) ? 3 * PQ2 : P * P * PP;
   static constexpr int LDS = E * SLAB;                    // values of T per block
 };
 
-// One group of up to E elements starting at `base`, on a block of 256 threads; `lds` holds
-// HexPencilDims<P,T>::LDS values.  Every thread of the block must call it (it synchronises).
-// IU is the unroll factor of the streamed point loop (register pressure vs. loads in flight).
-template <int P, class T, bool DEF, int IU = 1>
+// One group of up to E elements starting at `base`, on a block of HexPencilDims<P,T,E>::BLOCK
+// threads; `lds` holds HexPencilDims<P,T,E>::LDS values.  Every thread of the block must call it (it synchronises).
+// IU is the unroll factor of the streamed point loop (register pressure vs. loads in flight);
+// E the elements per block (block of HexPencilDims<P,T,E>::BLOCK threads); PF loads the 7Q
+// geometric factors of the thread's pencil into registers before the first sweep, so their
+// HBM latency overlaps the forward sweeps (small P only: 7Q values per thread).
+template <int P, class T, bool DEF, int IU = 1, int E_ = 256 / ((P + 1) * (P + 1)), bool PF = false>
 __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const T* __restrict__ x, T* __restrict__ y,
                                                const T* __restrict__ helm, const T* __restrict__ wq, T lambda,
                                                int64_t nelmt, int64_t base, T* __restrict__ lds) {
-  using D = HexPencilDims<P, T>;
+  using D = HexPencilDims<P, T, E_>;
+  constexpr int BLOCK = D::BLOCK;
   constexpr int Q = D::Q, Q2 = D::Q2, NQ = D::NQ, M = D::M, E = D::E, PP = D::PP, PQ2 = D::PQ2, P2Q = D::P2Q,
                 SLAB = D::SLAB;
   // uniform basis operands: B[i][p] = tabs[i*P + p], B'[i][p] = tabs[Q*P + i*P + p]
@@ -40,8 +45,19 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
     const int64_t e = base + el;
     const bool valid = act && el < ne;
 
+    // ---- geometry prefetch (PF): the thread's pencil points (i, j, k), i = 0..Q-1
+    T pre[PF ? 7 * Q : 1];
+    if (PF) {
+      const T* gp = helm + (valid ? e : 0) * (DEF ? 7 * NQ : 7);
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+#pragma unroll
+        for (int c = 0; c < 7; ++c)
+          pre[i * 7 + c] = valid ? (DEF ? gp[c * NQ + i * Q2 + s] : gp[c] * wq[i * Q2 + s]) : T(0);
+    }
+
     // ---- stage coefficients (coalesced) into padded mode pencils
-    for (int f = t; f < ne * M; f += 256) {
+    for (int f = t; f < ne * M; f += BLOCK) {
       const int e2 = f / M, m = f - e2 * M, pq = m / P, r = m - pq * P;
       lds[e2 * SLAB + pq * PP + r] = x[base * M + f];
     }
@@ -124,7 +140,7 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
 #pragma unroll
     for (int p = 0; p < P; ++p) t0[p] = t1[p] = t2[p] = T(0);
     const T* g = helm + (valid ? e : 0) * (DEF ? 7 * NQ : 7);
-#pragma unroll IU
+#pragma unroll(PF ? Q : IU)
     for (int i = 0; i < Q; ++i) {
       T u = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
 #pragma unroll
@@ -136,7 +152,10 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
       }
       const int n = i * Q2 + s;
       T G[7];
-      if (DEF) {
+      if (PF) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) G[c] = pre[i * 7 + c];
+      } else if (DEF) {
 #pragma unroll
         for (int c = 0; c < 7; ++c) G[c] = valid ? g[c * NQ + n] : T(0);
       } else {
@@ -221,7 +240,7 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
       for (int r = 0; r < P; ++r) L[s * PP + r] = yv[r];
     }
     __syncthreads();
-    for (int f = t; f < ne * M; f += 256) {
+    for (int f = t; f < ne * M; f += BLOCK) {
       const int e2 = f / M, m = f - e2 * M, pq = m / P, r = m - pq * P;
       y[base * M + f] = lds[e2 * SLAB + pq * PP + r];
     }

@@ -163,6 +163,11 @@ def test_autotune_cache_roundtrip(tmp_path):
         nir.nir_set_helmholtz_variant(nir.HEX, 6, nir.F64, nir.VARIANT_AUTO)
         nir.nir_set_helmholtz_variant(nir.TET, 3, nir.F32, nir.VARIANT_AUTO)
         assert nir.nir_get_helmholtz_variant(nir.HEX, 6, nir.F64) == nir.VARIANT_PENCIL
+        # built-in per-order defaults of the hex kernel family
+        assert nir.nir_get_helmholtz_variant(nir.HEX, 2, nir.F64) == nir.VARIANT_PENCIL_PF
+        assert nir.nir_get_helmholtz_variant(nir.HEX, 10, nir.F64) == nir.VARIANT_PENCIL_U2
+        assert nir.nir_get_helmholtz_variant(nir.HEX, 10, nir.F32) == nir.VARIANT_PENCIL_E1
+        assert nir.nir_get_helmholtz_variant(nir.PRISM, 10, nir.F32) == nir.VARIANT_GENERIC
         nir.nir_autotune_load(path)
         assert nir.nir_get_helmholtz_variant(nir.HEX, 6, nir.F64) == nir.VARIANT_PENCIL_U2
         assert nir.nir_get_helmholtz_variant(nir.TET, 3, nir.F32) == nir.VARIANT_GENERIC
