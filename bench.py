@@ -94,8 +94,9 @@ def cpu_baseline(cases, budget_s):
 
 
 # HBM bytes per launch of the dominant kernel measured with FETCH_SIZE / WRITE_SIZE (calibrated
-# by a plain 1 GiB copy), valid while the kernel sources hash to `src_sha`
-TRAFFIC = {"P": 10, "dtype": "f64", "bytes": 2989844862, "src_sha": "c9bdb5e88a3400ad"}
+# by a plain 1 GiB copy: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), valid for that kernel variant while
+# the kernel sources hash to `src_sha`
+TRAFFIC = {"P": 10, "dtype": "f64", "variant": 3, "bytes": 2990406021, "src_sha": "9f3d97aea73a720b"}
 
 
 def kernel_src_sha():
@@ -180,8 +181,9 @@ def bench_cg(args):
 
 
 def bench_mixed(args):
-    """100k mixed elements (hex/prism/tet, P in 3..8, curved): one persistent graph-replayed launch
-    vs per-(shape, P) launches, FP32 and FP64."""
+    """100k mixed elements (hex/prism/tet, P in 3..8, curved), FP32 and FP64: eager per-(shape, P)
+    launches, and the mixed plan with its persistent launch, its graph of per-batch launches on
+    parallel branches, and its own choice between the two."""
     import torch
     from paper_2606_20917_amd import inputs, nir
     c = inputs.mixed100k()
@@ -201,7 +203,7 @@ def bench_mixed(args):
         x = torch.tensor(np.stack([c["coef"][i] for i in idx]), device=dev)
         bs.append(dict(shape=s, P=p, ne=ne, basis=basis, helm=helm, helm32=helm32, x64=x, x32=x.float(),
                        M=x.shape[1], Q=Q))
-    out = {"metric": "mixed-mesh Helmholtz apply GDoF/s (one persistent launch vs per-(shape,P) launches)",
+    out = {"metric": "mixed-mesh Helmholtz apply GDoF/s (mixed plan: persistent launch / per-batch graph / auto)",
            "unit": "GDoF/s", "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
            "config": {"workload": "mixed100k: 100000 independent elements, 50/30/20% hex/prism/tet, P in 3..8, "
                                   "sin deformation 0.1, per-point factors, lambda=1", "batches": len(bs)}}
@@ -219,13 +221,18 @@ def bench_mixed(args):
         def per_batch():
             for k, b in enumerate(bs):
                 nir.nir_helmholtz_apply(batches[k], b["basis"], geoms[k], 1.0, xs[k], ys[k], stream)
-        plan = nir.MixedPlan(batches, [b["basis"] for b in bs], geoms)
 
-        def persistent():
-            nir.nir_mixed_helmholtz_apply(plan, 1.0, xs, ys, stream)
+        plans = {}
+        for name, strat in (("plan_persistent", nir.MIXED_PERSISTENT), ("plan_per_batch_graph", nir.MIXED_PER_BATCH),
+                            ("plan_auto", nir.MIXED_AUTO)):
+            plans[name] = nir.MixedPlan(batches, [b["basis"] for b in bs], geoms)
+            plans[name].set_strategy(strat)
         res = {}
-        for name, fn in (("per_batch", per_batch), ("persistent", persistent)):
-            for _ in range(args.warmup):
+        fns = [("per_batch_eager", per_batch)] + [
+            (name, (lambda p: (lambda: nir.nir_mixed_helmholtz_apply(p, 1.0, xs, ys, stream)))(p))
+            for name, p in plans.items()]
+        for name, fn in fns:
+            for _ in range(max(1, args.warmup)):
                 fn()
             torch.cuda.synchronize()
             a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -237,13 +244,10 @@ def bench_mixed(args):
             ms = a.elapsed_time(e) / args.steps
             res[name] = {"ms": round(ms, 4), "gdofs": round(dof / ms / 1e6, 3),
                          "gbs": round(byts / ms / 1e6, 1), "frac_hbm": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4)}
-        ref = [y.clone() for y in ys]
-        per_batch()
-        torch.cuda.synchronize()
-        res["persistent_equals_per_batch"] = all(torch.equal(r, y) for r, y in zip(ref, ys))
-        res["plan"] = plan.info()
+            if name in plans:
+                res[name]["info"] = plans[name].info()
         out[dt_name] = res
-    out["value"] = out["f32"]["persistent"]["gdofs"]
+    out["value"] = out["f32"]["plan_auto"]["gdofs"]
     print(json.dumps(out), flush=True)
 
 
@@ -253,8 +257,11 @@ def collapsed_model(shape, P, s, deformed):
     M = P * P * (P + 1) // 2 if shape == 1 else P * (P + 1) * (P + 2) // 6
     npts = Q ** 3 if deformed else 1
     byts = s * (2 * M + 7 * npts)
-    pair_q2 = (P * P if shape == 1 else P * (P + 1) // 2) * Q * Q
-    flops = 4 * (M * Q + pair_q2 + P * Q ** 3) + 12 * Q ** 4 + (30 if shape == 1 else 40) * Q ** 3
+    # sum-factorised count (value and derivative sweeps forward, their transposes backward):
+    # A/A^T 2 tables x M x Q, B/B^T 3 x pairs x Q^2 (tet: pair (0,1) once more), C/C^T 4 x P x Q^3
+    # multiply-adds each way, plus the pointwise chain rule, factors and mass term
+    npair = (P * P if shape == 1 else P * (P + 1) // 2 + 1)
+    flops = 2 * 2 * (2 * M * Q + 3 * npair * Q * Q + 4 * P * Q ** 3) + (30 if shape == 1 else 40) * Q ** 3
     return M, byts, flops
 
 
@@ -289,16 +296,25 @@ def bench_collapsed(args):
                 nsets = max(1, math.ceil(ROTATE_BYTES / per_set))
                 x = torch.tensor(c["coef"], dtype=tdt, device=dev)
                 sets = [(x, torch.empty_like(x))] + [(x.clone(), torch.empty_like(x)) for _ in range(nsets - 1)]
-                for it in range(args.warmup):
-                    nir.nir_helmholtz_apply(b, basis, g, 1.0, *sets[it % nsets])
-                torch.cuda.synchronize()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                for it in range(args.steps):
-                    nir.nir_helmholtz_apply(b, basis, g, 1.0, *sets[it % nsets])
-                e1.record()
-                torch.cuda.synchronize()
-                ms = e0.elapsed_time(e1) / args.steps
+
+                def timed():
+                    for it in range(args.warmup):
+                        nir.nir_helmholtz_apply(b, basis, g, 1.0, *sets[it % nsets])
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for it in range(args.steps):
+                        nir.nir_helmholtz_apply(b, basis, g, 1.0, *sets[it % nsets])
+                    e1.record()
+                    torch.cuda.synchronize()
+                    return e0.elapsed_time(e1) / args.steps
+
+                try:   # the LDS-staged generic kernel beside the default (register-pencil) one
+                    nir.nir_set_helmholtz_variant(shape, P, dt, nir.VARIANT_GENERIC)
+                    ms_generic = timed()
+                finally:
+                    nir.nir_set_helmholtz_variant(shape, P, dt, nir.VARIANT_AUTO)
+                ms = timed()
                 gbs = ne * byts / ms / 1e6
                 tfl = ne * flops / ms / 1e9
                 peak_fl = 78.6 if dt == nir.F64 else 157.3
@@ -306,7 +322,9 @@ def bench_collapsed(args):
                     "nelmt": ne, "ms": round(ms, 4), "gdofs": round(ne * M / ms / 1e6, 3), "gbs": round(gbs, 1),
                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "tflops": round(tfl, 2),
                     "frac_valu": round(tfl / peak_fl, 4),
-                    "bound": "hbm" if byts * 9.8 > flops or deformed else "alu"}
+                    "bound": "hbm" if byts * 9.8 > flops or deformed else "alu",
+                    "variant": nir.nir_get_helmholtz_variant(shape, P, dt),
+                    "generic_gdofs": round(ne * M / ms_generic / 1e6, 3)}
     out["value"] = out["tet_P5_f64"]["gdofs"]
     print(json.dumps(out), flush=True)
 
@@ -422,7 +440,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": (TRAFFIC["bytes"] if (TRAFFIC["P"] == dom["P"] and TRAFFIC["dtype"] == args.dtype
-                                                      and args.math == "native" and args.variant != "generic"
+                                                      and args.math == "native"
+                                                      and nir.nir_get_helmholtz_variant(
+                                                          nir.HEX, dom["P"], nir.F64 if args.dtype == "f64" else nir.F32)
+                                                      == TRAFFIC["variant"]
                                                       and kernel_src_sha() == TRAFFIC["src_sha"]) else None),
                      "kernel": f"hex Helmholtz P={dom['P']}",
                      "bytes_per_launch": hex_bytes(dom["P"], s) * dom["ne"]},

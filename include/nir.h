@@ -193,26 +193,42 @@ nir_status nir_helmholtz_apply(const nir_batch* batch, const nir_basis* basis, c
                                double lambda, const void* coef_in, void* coef_out, void* stream);
 
 /* ------------------------------------------------------------------ mixed batches
- * One persistent launch of the fused Helmholtz apply over several batches of different shape
- * and order (a mixed mesh grouped by (shape, P)).  The plan builds a work list of element
- * groups sorted by decreasing cost; workgroup b of the persistent grid of G runs items b,
- * b+G, b+2G, ...  Results equal the per-batch nir_helmholtz_apply launches bit for bit (same device
- * code per item).  All batches share one dtype and NIR_MATH_NATIVE and have P <= 8 (the orders
- * compiled into the persistent kernel; NIR_ENOTSUP above); the arrays batches[],
- * bases[], geoms[] (geoms[b].helm used) are copied, the objects they point to must outlive the
- * plan.  The first apply tunes the kernel's register budget (2..4 waves per SIMD) and the grid
- * size (1..8 workgroups per CU), timed on the caller's operands, and captures the launch into a
- * hipGraph that later applies replay.
- * Changing the coefficient pointers or lambda between applies re-uploads the descriptors
- * (synchronising the stream).  Not thread-safe per plan. */
+ * The fused Helmholtz apply over several batches of different shape and order (a mixed mesh
+ * grouped by (shape, P)), replayed from one hipGraph.  Two strategies:
+ *   NIR_MIXED_PERSISTENT  one persistent launch over a work list of element groups sorted by
+ *                         decreasing cost; workgroup b of the grid of G runs items b, b+G, ...
+ *                         with the group function of each item's (shape, P) (P <= 8: the
+ *                         orders compiled into the persistent kernel);
+ *   NIR_MIXED_PER_BATCH   one launch per batch with its standalone kernel (the variant selected
+ *                         for its (shape, P, dtype) when the graph is captured), spread over
+ *                         four parallel graph branches balanced by bytes;
+ *   NIR_MIXED_AUTO        (default) the first apply times both and keeps the faster; plans
+ *                         with a batch of P > 8 use NIR_MIXED_PER_BATCH.
+ * Results of both equal the per-batch nir_helmholtz_apply launches (the same device code per
+ * element group; bit for bit with the same kernel variant).  All batches share one dtype and
+ * NIR_MATH_NATIVE; the arrays batches[], bases[], geoms[] (geoms[b].helm used) are copied, the
+ * objects they point to must outlive the plan.  Tuning the persistent launch covers the
+ * kernel's register budget (2..4 waves per SIMD) and the grid size (1..8 workgroups per CU),
+ * timed on the caller's operands.  Changing the coefficient pointers or lambda between applies
+ * re-uploads the descriptors (synchronising the stream) and re-captures a per-batch graph.
+ * Not thread-safe per plan. */
+typedef enum { NIR_MIXED_AUTO = 0, NIR_MIXED_PERSISTENT = 1, NIR_MIXED_PER_BATCH = 2 } nir_mixed_strategy;
 typedef struct nir_mixed_plan nir_mixed_plan;
 nir_status nir_mixed_plan_create(int32_t nbatch, const nir_batch* batches, const nir_basis* const* bases,
                                  const nir_geom* geoms, nir_mixed_plan** out);
 /* coef_in[b], coef_out[b]: device arrays [nelmt_b][M_b] of batch b */
 nir_status nir_mixed_helmholtz_apply(nir_mixed_plan* plan, double lambda, const void* const* coef_in,
                                      void* const* coef_out, void* stream);
-/* work items, tuned grid size (0 before the first apply), its measured time per apply (ms),
- * algorithmic bytes and DoF of one apply; any pointer may be NULL */
+/* Requests a strategy (nir_mixed_strategy); takes effect, with tuning, at the next apply.
+ * NIR_ENOTSUP for NIR_MIXED_PERSISTENT on a plan with a batch of P > 8. */
+nir_status nir_mixed_plan_set_strategy(nir_mixed_plan* plan, int32_t strategy);
+/* Strategy in use (0 before the first apply) and the tuning times per apply (ms) of the two
+ * strategies at the last tuning (-1 where not timed); any pointer may be NULL. */
+nir_status nir_mixed_plan_timings(const nir_mixed_plan* plan, int32_t* strategy, double* ms_persistent,
+                                  double* ms_per_batch);
+/* work items of the persistent list, tuned grid size (0 before the first apply), the measured
+ * time per apply (ms) of the strategy in use, algorithmic bytes and DoF of one apply; any
+ * pointer may be NULL */
 nir_status nir_mixed_plan_info(const nir_mixed_plan* plan, int32_t* nitems, int32_t* grid, double* tuned_ms,
                                int64_t* bytes, int64_t* dof);
 nir_status nir_mixed_plan_destroy(nir_mixed_plan* plan);
@@ -282,13 +298,16 @@ nir_status nir_cg_plan_destroy(nir_cg_plan* plan);
  * Several kernels implement the fused Helmholtz apply (native contractions); the choice per
  * (shape, P, dtype) is library-global state (one int per combination, set atomically), used by
  * nir_helmholtz_apply and by the CG plans' element apply:
- *   NIR_VARIANT_AUTO       built-in default (pencil for hexahedra, generic otherwise)
+ *   NIR_VARIANT_AUTO       built-in default (a pencil kernel per shape; for hexahedra the
+ *                          per-order choice measured fastest on MI355X)
  *   NIR_VARIANT_GENERIC    LDS-staged kernel, threads over points/modes (any shape)
- *   NIR_VARIANT_PENCIL     register-pencil kernel with uniform basis operands (hex only)
- *   NIR_VARIANT_PENCIL_U2  the same with the streamed point loop unrolled twice (hex only)
- *   NIR_VARIANT_PENCIL_E1  the same with one element per block (smaller LDS footprint per block)
- *   NIR_VARIANT_PENCIL_PF  the same with each pencil's geometric factors loaded into registers
- *                          before the forward sweeps (latency overlap; for small P)
+ *   NIR_VARIANT_PENCIL     register-pencil kernel with uniform basis operands (any shape; on
+ *                          prisms and tetrahedra the contractions whose 1-D factor depends on
+ *                          p or p+q run one such index per wavefront)
+ *   NIR_VARIANT_PENCIL_U2  hex pencil kernel with the streamed point loop unrolled twice
+ *   NIR_VARIANT_PENCIL_E1  hex pencil kernel with one element per block (smaller LDS per block)
+ *   NIR_VARIANT_PENCIL_PF  hex pencil kernel with each pencil's geometric factors loaded into
+ *                          registers before the forward sweeps (latency overlap; for small P)
  * Setting a variant a shape does not support returns NIR_ENOTSUP. */
 typedef enum { NIR_VARIANT_AUTO = 0, NIR_VARIANT_GENERIC = 1, NIR_VARIANT_PENCIL = 2,
                NIR_VARIANT_PENCIL_U2 = 3, NIR_VARIANT_PENCIL_E1 = 4, NIR_VARIANT_PENCIL_PF = 5 } nir_variant;

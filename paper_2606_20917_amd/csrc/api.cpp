@@ -96,7 +96,7 @@ static std::atomic<int> g_variant[3][kMaxP + 1][2];
 static int resolve_variant(int shape, int P, int dtype) {
   const int v = g_variant[shape][P][dtype].load(std::memory_order_relaxed);
   if (v != NIR_VARIANT_AUTO) return v;
-  if (shape != kHex) return NIR_VARIANT_GENERIC;
+  if (shape != kHex) return NIR_VARIANT_PENCIL;
   // defaults from a sweep of all variants on MI355X (32^3 curved hexes, per-point factors):
   // geometry prefetch wins for P <= 4, the plain pencil kernel in between, and at P >= 8 the
   // two-fold point-loop unroll (FP64) or one element per block (FP32, P = 10)
@@ -109,6 +109,9 @@ static int resolve_variant(int shape, int P, int dtype) {
 // the fused Helmholtz apply with the selected kernel variant (native contractions)
 nir_status launch_helm_auto(const nir_basis* basis, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
   const int v = resolve_variant(basis->shape, basis->P, dtype);
+  if (basis->shape == kPrism && v == NIR_VARIANT_PENCIL) return launch_helm_col_prism(basis, dtype, deformed, a, s);
+  if (basis->shape == kTet && v == NIR_VARIANT_PENCIL) return launch_helm_col_tet(basis, dtype, deformed, a, s);
+  if (basis->shape != kHex) return launch_generic(basis, kOpHelm, dtype, deformed, a, s);
   if (v == NIR_VARIANT_PENCIL) return launch_helm_hex_pencil(basis, dtype, deformed, a, s, 0);
   if (v == NIR_VARIANT_PENCIL_U2) return launch_helm_hex_pencil(basis, dtype, deformed, a, s, 1);
   if (v == NIR_VARIANT_PENCIL_E1) return launch_helm_hex_pencil(basis, dtype, deformed, a, s, 2);
@@ -490,9 +493,9 @@ nir_status nir_autotune_helmholtz(const nir_batch* b, const nir_basis* basis, co
   const int before = slot.load();
   const int cands_hex[5] = {NIR_VARIANT_GENERIC, NIR_VARIANT_PENCIL, NIR_VARIANT_PENCIL_U2, NIR_VARIANT_PENCIL_E1,
                             NIR_VARIANT_PENCIL_PF};
-  const int cands_other[1] = {NIR_VARIANT_GENERIC};
+  const int cands_other[2] = {NIR_VARIANT_GENERIC, NIR_VARIANT_PENCIL};
   const int* cands = b->shape == kHex ? cands_hex : cands_other;
-  const int nc = b->shape == kHex ? 5 : 1;
+  const int nc = b->shape == kHex ? 5 : 2;
   hipEvent_t e0, e1;
   NIR_TRY(hip_check(hipEventCreate(&e0), "event"));
   NIR_TRY(hip_check(hipEventCreate(&e1), "event"));
@@ -573,7 +576,7 @@ nir_status nir_autotune_load(const char* path) {
                     &e.d, &e.v) != 4)
       return fail(NIR_EINVAL, "%s: malformed entry at offset %zu", path, ob);
     if (e.s < 0 || e.s > 2 || e.P < kMinP || e.P > kMaxP || e.d < 0 || e.d > 1 || e.v < NIR_VARIANT_AUTO ||
-        e.v > NIR_VARIANT_PENCIL_PF || (e.s != kHex && e.v >= NIR_VARIANT_PENCIL))
+        e.v > NIR_VARIANT_PENCIL_PF || (e.s != kHex && e.v > NIR_VARIANT_PENCIL))
       return fail(NIR_EINVAL, "%s: invalid entry at offset %zu", path, ob);
     ents.push_back(e);
     pos = cb + 1;
@@ -586,7 +589,8 @@ nir_status nir_set_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype, in
   if (shape < kHex || shape > kTet || P < kMinP || P > kMaxP || (dtype != NIR_F64 && dtype != NIR_F32))
     return fail(NIR_EINVAL, "invalid (shape %d, P %d, dtype %d)", shape, P, dtype);
   if (variant < NIR_VARIANT_AUTO || variant > NIR_VARIANT_PENCIL_PF) return fail(NIR_EINVAL, "invalid variant %d", variant);
-  if (variant >= NIR_VARIANT_PENCIL && shape != kHex) return fail(NIR_ENOTSUP, "the pencil kernels are hex only");
+  if (variant > NIR_VARIANT_PENCIL && shape != kHex)
+    return fail(NIR_ENOTSUP, "variant %d is a hex kernel (prism and tet have GENERIC and PENCIL)", variant);
   g_variant[shape][P][dtype].store(variant, std::memory_order_relaxed);
   return NIR_OK;
 }

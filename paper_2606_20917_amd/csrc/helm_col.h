@@ -1,0 +1,52 @@
+// Host launcher of the collapsed-shape register-pencil Helmholtz kernel, instantiated once
+// per shape (helm_col_prism.hip, helm_col_tet.hip).
+#pragma once
+
+#include "helm_col_dev.h"
+
+namespace nir {
+
+template <int SHAPE, int P, class T, bool DEF>
+__global__ void __launch_bounds__((ColDims<SHAPE, P, T>::BLOCK))
+    k_helm_col(DevTab<T> tb, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ helm, T lambda,
+               int64_t nelmt) {
+  using D = ColDims<SHAPE, P, T>;
+  __shared__ T lds[D::LDS];
+  helm_col_group<SHAPE, P, T, DEF>(tb, x, y, helm, lambda, nelmt, int64_t(blockIdx.x) * D::E, lds);
+}
+
+template <int SHAPE, int P, class T>
+nir_status launch_col_PT(const nir_basis* b, int deformed, const OpArgs& a, hipStream_t s) {
+  using D = ColDims<SHAPE, P, T>;
+  static_assert(D::LDS * sizeof(T) <= 65536, "LDS budget");
+  DevTab<T> tb;
+  if constexpr (sizeof(T) == 8) tb = b->t64; else tb = b->t32;
+  const int64_t nb = (a.nelmt + D::E - 1) / D::E;
+  if (nb > 0x7fffffff) return fail(NIR_EINVAL, "too many elements for one launch");
+  if (nb == 0) return ok();
+  const T* x = static_cast<const T*>(a.in0);
+  T* y = static_cast<T*>(a.out0);
+  const T* helm = static_cast<const T*>(a.helm);
+  const dim3 grid(static_cast<unsigned>(nb)), block(D::BLOCK);
+  if (deformed)
+    hipLaunchKernelGGL((k_helm_col<SHAPE, P, T, true>), grid, block, 0, s, tb, x, y, helm, T(a.lambda), a.nelmt);
+  else
+    hipLaunchKernelGGL((k_helm_col<SHAPE, P, T, false>), grid, block, 0, s, tb, x, y, helm, T(a.lambda), a.nelmt);
+  return hip_check(hipGetLastError(), "collapsed Helmholtz launch");
+}
+
+template <int SHAPE>
+nir_status launch_col_shape(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
+#define NIR_CASE(PP)                                                                   \
+  case PP:                                                                             \
+    return dtype == NIR_F64 ? launch_col_PT<SHAPE, PP, double>(b, deformed, a, s)      \
+                            : launch_col_PT<SHAPE, PP, float>(b, deformed, a, s);
+  switch (b->P) {
+    NIR_CASE(2) NIR_CASE(3) NIR_CASE(4) NIR_CASE(5) NIR_CASE(6)
+    NIR_CASE(7) NIR_CASE(8) NIR_CASE(9) NIR_CASE(10)
+    default: return fail(NIR_ENOTSUP, "P=%d not compiled", b->P);
+  }
+#undef NIR_CASE
+}
+
+}  // namespace nir

@@ -1,0 +1,511 @@
+// Register-pencil fused Helmholtz apply for the collapsed shapes (prism and tetrahedron),
+// device body of one element group.
+//
+// The operator is the one of the generic kernel (sum factorisation of section 2.2 with the
+// modified C0 basis, eqs. (16)/(17) forward and (20)/(21) transposed), but the derivatives
+// come from the derivative tables of the 1-D factors instead of collocation matrices, and
+// every contraction runs as a register pencil whose 1-D factor values are the same for all
+// lanes of a wavefront, so they are scalar loads:
+//
+//   A   r -> k  a0[pq][k] = sum_r c_pqr phi3_r(k), a1 with phi3'      (phi3 depends on p or p+q)
+//   B   q -> j  b0[p][j][k] = sum_q phi2_pq(j) a0[pq][k], b1 (phi2', a0), b2 (phi2, a1)
+//   C   p -> i  u, du/deta1, du/deta2, du/deta3 at (i,j,k), streamed over i per (j,k) pencil,
+//               with the eta -> xi chain rule (eq. (23)), the geometric factors and the mass
+//               term applied point by point and the transposed sweep C^T folded in
+//   B^T, A^T    the transposed contractions back to the modes
+//
+// The two coupled contractions (B of the tetrahedron, whose factor psi^b_pq depends on p,
+// and A of both shapes, whose factor depends on p or on p+q) give every wavefront one value
+// of the coupling index ("slice"): lanes are (element, free index) and the slice index is a
+// compile-time constant inside a uniform switch.  A group of E elements therefore holds at
+// least P wavefronts, one per slice.
+//
+// Collapsed-vertex modes of the modified basis (section 2.1):
+//  tet   modes (0,1,r) add psi^a_1(eta1) psi^b_01(eta2) psi^c_01r(eta3): an extra q-term of
+//        pair (0,1) in the p = 1 plane of B (and of B^T);
+//        mode (0,0,1) is the vertex function (1+eta3)/2 = psi^c_001(eta3) on its own; it is
+//        left out of A and added point by point in C; its transposed value is the sum over
+//        all points of psi^c_001 times the mass term plus psi^c_001' times the eta3 flux;
+//  prism modes (0,q,1) add psi^a_1(eta1) psi^a_q(xi2) psi^b_01(xi3): an extra r-term in the
+//        p = 1 rows of A (and of A^T).
+//
+// LDS per element (values of T): one region of 3 P Q^2 values that holds, in turn, the
+// coefficients, the A rows, the B planes, the C^T planes, the B^T rows and the results;
+// every stage reads its inputs into registers, synchronises, then writes its outputs.  The
+// tetrahedron adds a plane of Q^2 vertex partials and three rows of Q values.
+#pragma once
+
+#include <type_traits>
+
+#include "nir_internal.h"
+
+namespace nir {
+
+template <int SHAPE, int P>
+struct ColModes {
+  static constexpr int pair(int p, int q) { return SHAPE == kTet ? p * P - p * (p - 1) / 2 + q : p * P + q; }
+  static constexpr int nq(int p) { return SHAPE == kTet ? P - p : P; }
+  // first mode of pair (p,q) in the p-outer, q, r-inner order
+  static constexpr int m0(int p, int q) {
+    int m = 0;
+    for (int pp = 0; pp < p; ++pp) m += SHAPE == kTet ? (P - pp) * (P - pp + 1) / 2 : P * (P - pp);
+    return m + (SHAPE == kTet ? q * (P - p) - q * (q - 1) / 2 : q * (P - p));
+  }
+};
+
+// E_ = 0: the default group size (full slice wavefronts within 64 KiB of LDS)
+template <int SHAPE, int P, class T, int E_ = 0>
+struct ColDims {
+  static constexpr int Q = P + 1, Q2 = Q * Q, NQ = Q2 * Q;
+  static constexpr int M = SHAPE == kPrism ? P * P * (P + 1) / 2 : P * (P + 1) * (P + 2) / 6;
+  static constexpr int NP = SHAPE == kTet ? P * (P + 1) / 2 : P * P;
+  static constexpr int MAIN = 3 * P * Q2;
+  static constexpr int XTRA = SHAPE == kTet ? Q2 + 3 * Q : 0;   // vertex partials, x0, x1, vertex row
+  static constexpr int SLAB = MAIN + XTRA;
+  static constexpr int EW = 64 / Q;                              // elements whose Q lanes fill a wavefront
+  static constexpr int EL = (65536 / int(sizeof(T))) / SLAB;     // elements within 64 KiB of LDS
+  static constexpr int E = E_ > 0 ? E_ : (EW < EL ? EW : (EL > 0 ? EL : 1));
+  static constexpr int NT = E * Q2;                              // pencil threads
+  static constexpr int NWP = (NT + 63) / 64;
+  static constexpr int NW = NWP > P ? NWP : P;                   // at least one wavefront per slice
+  static constexpr int BLOCK = 64 * NW;
+  static constexpr int LDS = E * SLAB;
+};
+
+// calls f(integral_constant<I>) for the I == v (v uniform across the wavefront)
+template <int I, int N, class F>
+__device__ __forceinline__ void col_dispatch(int v, F& f) {
+  if constexpr (I < N) {
+    if (v == I)
+      f(std::integral_constant<int, I>{});
+    else
+      col_dispatch<I + 1, N>(v, f);
+  }
+}
+
+// One call processes NSUB independent groups of E elements, group g starting at element
+// base + g E, on a block of at least NSUB * ColDims::BLOCK threads (g = wavefront / NW; the
+// wavefronts past the last group only take part in the barriers); `lds` holds NSUB * LDS
+// values.  Every thread of the block must call it (it synchronises).
+template <int SHAPE, int P, class T, bool DEF, int E_ = 0, int NSUB = 1>
+__device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __restrict__ x, T* __restrict__ y,
+                                               const T* __restrict__ helm, T lambda, int64_t nelmt, int64_t base0,
+                                               T* __restrict__ lds0) {
+  using D = ColDims<SHAPE, P, T, E_>;
+  using MO = ColModes<SHAPE, P>;
+  constexpr int Q = D::Q, Q2 = D::Q2, NQ = D::NQ, M = D::M, NP = D::NP, E = D::E, SLAB = D::SLAB,
+                MAIN = D::MAIN, BLOCK = D::BLOCK;
+  constexpr int PQ2 = P * Q2;
+  constexpr bool TET = SHAPE == kTet;
+
+  static_assert(E * Q <= 64, "a slice wavefront holds E elements x Q lanes");
+  const int wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int sub = wave0 / D::NW;                       // group of this wavefront
+  const bool in = sub < NSUB;
+  const int t = int(threadIdx.x) - sub * BLOCK;        // thread within the group
+  const int wave = in ? wave0 - sub * D::NW : P;       // slice index (P: none)
+  const int lane = t & 63;
+  const int64_t base = base0 + int64_t(sub) * E;
+  T* __restrict__ lds = lds0 + (in ? sub : 0) * D::LDS;
+  const int ne = in ? int(max(int64_t(0), min(int64_t(E), nelmt - base))) : 0;
+
+  // pencil role: element el, point pencil s = (j,k)
+  const int el = t / Q2;
+  const int s = t - el * Q2;
+  const int jj = s / Q, kk = s - jj * Q;
+  const bool act = in && el < E;
+  const bool valid = act && el < ne;
+  T* L = lds + (act ? el : 0) * SLAB;
+
+  // ---- stage the coefficients (coalesced)
+  for (int f = t; f < ne * M; f += BLOCK) {
+    const int e2 = f / M;
+    lds[e2 * SLAB + (f - e2 * M)] = x[base * M + f];
+  }
+  __syncthreads();
+
+  // ---- A: r -> k, one slice (tet: s = p+q, prism: p) per wavefront
+  T c001 = T(0);
+  if (TET && act) c001 = L[1];
+  {
+    T a0[Q], a1[Q];
+    int dst = -1;   // pair row written by this lane
+    T* Ls = lds;
+    auto stageA = [&](auto ic) {
+      constexpr int sl = decltype(ic)::value;
+      if constexpr (TET) {
+        // lanes (element, p), q = sl - p; factor psi^c_{sl,r}
+        constexpr int np = sl + 1, nr = P - sl;
+        const int e2 = lane / np, p = lane - e2 * np, q = sl - p;
+        if (e2 < E) {
+          Ls = lds + e2 * SLAB;
+          const int m0 = MO::m0(p, q);
+          T c[nr];
+#pragma unroll
+          for (int r = 0; r < nr; ++r) c[r] = (sl == 0 && r == 1) ? T(0) : Ls[m0 + r];   // vertex mode apart
+#pragma unroll
+          for (int k = 0; k < Q; ++k) {
+            T v0 = T(0), v1 = T(0);
+#pragma unroll
+            for (int r = 0; r < nr; ++r) {
+              v0 += tb.T3[(MO::m0(0, sl) + r) * Q + k] * c[r];
+              v1 += tb.dT3[(MO::m0(0, sl) + r) * Q + k] * c[r];
+            }
+            a0[k] = v0;
+            a1[k] = v1;
+          }
+          dst = MO::pair(p, q);
+        }
+      } else {
+        // lanes (element, q); factor psi^b_{sl,r}; p = 1 adds the (0,q,1) vertex modes
+        constexpr int p = sl, nr = P - p;
+        const int e2 = lane / P, q = lane - e2 * P;
+        if (e2 < E) {
+          Ls = lds + e2 * SLAB;
+          const int m0 = MO::m0(p, 0) + q * nr;
+          T c[nr];
+#pragma unroll
+          for (int r = 0; r < nr; ++r) c[r] = Ls[m0 + r];
+          T cx = T(0);
+          if (p == 1) cx = Ls[MO::m0(0, 0) + q * P + 1];
+#pragma unroll
+          for (int k = 0; k < Q; ++k) {
+            T v0 = T(0), v1 = T(0);
+#pragma unroll
+            for (int r = 0; r < nr; ++r) {
+              v0 += tb.T3[(MO::m0(p, 0) + r) * Q + k] * c[r];
+              v1 += tb.dT3[(MO::m0(p, 0) + r) * Q + k] * c[r];
+            }
+            if (p == 1) {
+              v0 += tb.T3[1 * Q + k] * cx;
+              v1 += tb.dT3[1 * Q + k] * cx;
+            }
+            a0[k] = v0;
+            a1[k] = v1;
+          }
+          dst = MO::pair(p, q);
+        }
+      }
+    };
+    col_dispatch<0, P>(wave, stageA);
+    __syncthreads();
+    if (dst >= 0) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        Ls[dst * Q + k] = a0[k];
+        Ls[NP * Q + dst * Q + k] = a1[k];
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- B: q -> j, one p per wavefront, lanes (element, k)
+  {
+    T b0[Q], b1[Q], b2[Q];
+    const int e2 = lane / Q, k = lane - e2 * Q;
+    T* Ls = lds + (e2 < E ? e2 : 0) * SLAB;
+    int pw = -1;
+    auto stageB = [&](auto ic) {
+      constexpr int p = decltype(ic)::value, nq = MO::nq(p);
+      constexpr bool X = TET && p == 1;   // pair (0,1) enters the p = 1 plane
+      if (e2 < E) {
+        T av[nq + 1], bv[nq + 1];
+#pragma unroll
+        for (int q = 0; q < nq; ++q) {
+          av[q] = Ls[MO::pair(p, q) * Q + k];
+          bv[q] = Ls[NP * Q + MO::pair(p, q) * Q + k];
+        }
+        if (X) {
+          av[nq] = Ls[MO::pair(0, 1) * Q + k];
+          bv[nq] = Ls[NP * Q + MO::pair(0, 1) * Q + k];
+        }
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          T v0 = T(0), v1 = T(0), v2 = T(0);
+#pragma unroll
+          for (int q = 0; q < nq; ++q) {
+            const T f = tb.T2[MO::pair(p, q) * Q + j], df = tb.dT2[MO::pair(p, q) * Q + j];
+            v0 += f * av[q];
+            v1 += df * av[q];
+            v2 += f * bv[q];
+          }
+          if (X) {
+            const T f = tb.T2[MO::pair(0, 1) * Q + j], df = tb.dT2[MO::pair(0, 1) * Q + j];
+            v0 += f * av[nq];
+            v1 += df * av[nq];
+            v2 += f * bv[nq];
+          }
+          b0[j] = v0;
+          b1[j] = v1;
+          b2[j] = v2;
+        }
+        pw = p;
+      }
+    };
+    col_dispatch<0, P>(wave, stageB);
+    __syncthreads();
+    if (pw >= 0) {
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        Ls[pw * Q2 + j * Q + k] = b0[j];
+        Ls[PQ2 + pw * Q2 + j * Q + k] = b1[j];
+        Ls[2 * PQ2 + pw * Q2 + j * Q + k] = b2[j];
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- C, pointwise, C^T fused over the (j,k) pencils, streamed over i
+  {
+    T C0[P], C1[P], C2[P];
+    T t0[P], t1[P], t2[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      C0[p] = act ? L[p * Q2 + s] : T(0);
+      C1[p] = act ? L[PQ2 + p * Q2 + s] : T(0);
+      C2[p] = act ? L[2 * PQ2 + p * Q2 + s] : T(0);
+      t0[p] = t1[p] = t2[p] = T(0);
+    }
+    // chain-rule factors of the pencil: d eta / d xi (eq. (23))
+    const T e2v = tb.z[1][act ? jj : 0], e3v = tb.z[2][act ? kk : 0];
+    T c00, c1k, c11, c12;   // c01 = c02 = c1k (1 + eta1) for the tet, c02 = c1k (1 + eta1) for the prism
+    if (TET) {
+      const T r3 = T(1) / (T(1) - e3v);
+      const T ra = r3 / (T(1) - e2v);
+      c00 = T(4) * ra;
+      c1k = T(2) * ra;
+      c11 = T(2) * r3;
+      c12 = (T(1) + e2v) * r3;
+    } else {
+      const T r3 = T(1) / (T(1) - e3v);
+      c00 = T(2) * r3;
+      c1k = r3;
+      c11 = T(1);
+      c12 = T(0);
+    }
+    T vc = T(0), vd = T(0);   // tet vertex mode: value and eta3-derivative factor at k
+    if (TET) {
+      vc = tb.T3[1 * Q + (act ? kk : 0)];
+      vd = tb.dT3[1 * Q + (act ? kk : 0)];
+    }
+    const T uv = c001 * vc, dv = c001 * vd;
+    T vm = T(0), v3 = T(0);
+    const T* g = helm + (valid ? int64_t(base + el) : 0) * (DEF ? 7 * NQ : 7);
+    const T* wq = tb.wq;
+#pragma unroll 1
+    for (int i = 0; i < Q; ++i) {
+      T u = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const T f = tb.T1[p * Q + i], df = tb.dT1[p * Q + i];
+        u += f * C0[p];
+        d1 += df * C0[p];
+        d2 += f * C1[p];
+        d3 += f * C2[p];
+      }
+      if (TET) {
+        u += uv;
+        d3 += dv;
+      }
+      const int n = i * Q2 + s;
+      T G[7];
+      if (DEF) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) G[c] = valid ? g[c * NQ + n] : T(0);
+      } else {
+        const T w = valid ? wq[n] : T(0);
+#pragma unroll
+        for (int c = 0; c < 7; ++c) G[c] = valid ? g[c] * w : T(0);
+      }
+      const T c1 = c1k * (T(1) + tb.z[0][i]);
+      T x1, x2, x3;
+      if (TET) {
+        x1 = c00 * d1;
+        x2 = c1 * d1 + c11 * d2;
+        x3 = c1 * d1 + c12 * d2 + d3;
+      } else {
+        x1 = c00 * d1;
+        x2 = d2;
+        x3 = c1 * d1 + d3;
+      }
+      const T y1 = G[0] * x1 + G[1] * x2 + G[2] * x3;
+      const T y2 = G[1] * x1 + G[3] * x2 + G[4] * x3;
+      const T y3 = G[2] * x1 + G[4] * x2 + G[5] * x3;
+      const T m = lambda * G[6] * u;
+      T h1, h2;
+      if (TET) {
+        h1 = c00 * y1 + c1 * (y2 + y3);
+        h2 = c11 * y2 + c12 * y3;
+        vm += m;
+        v3 += y3;
+      } else {
+        h1 = c00 * y1 + c1 * y3;
+        h2 = y2;
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const T f = tb.T1[p * Q + i], df = tb.dT1[p * Q + i];
+        t0[p] += f * m + df * h1;
+        t1[p] += f * h2;
+        t2[p] += f * y3;
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        L[p * Q2 + s] = t0[p];
+        L[PQ2 + p * Q2 + s] = t1[p];
+        L[2 * PQ2 + p * Q2 + s] = t2[p];
+      }
+      if (TET) L[MAIN + s] = vc * vm + vd * v3;
+    }
+    __syncthreads();
+  }
+
+  // ---- B^T: j -> q, one p per wavefront, lanes (element, k)
+  {
+    T s0[P + 1], s1[P + 1];
+    T sx = T(0);
+    const int e2 = lane / Q, k = lane - e2 * Q;
+    T* Ls = lds + (e2 < E ? e2 : 0) * SLAB;
+    int pw = -1;
+    auto stageBT = [&](auto ic) {
+      constexpr int p = decltype(ic)::value, nq = MO::nq(p);
+      constexpr bool X = TET && p == 1;
+      if (e2 < E) {
+        T tv0[Q], tv1[Q], tv2[Q];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          tv0[j] = Ls[p * Q2 + j * Q + k];
+          tv1[j] = Ls[PQ2 + p * Q2 + j * Q + k];
+          tv2[j] = Ls[2 * PQ2 + p * Q2 + j * Q + k];
+        }
+        if (TET && p == 0) {
+#pragma unroll
+          for (int j = 0; j < Q; ++j) sx += Ls[MAIN + j * Q + k];
+        }
+#pragma unroll
+        for (int q = 0; q < nq + (X ? 1 : 0); ++q) {
+          const int pr = q < nq ? MO::pair(p, q) : MO::pair(0, 1);
+          T v0 = T(0), v1 = T(0);
+#pragma unroll
+          for (int j = 0; j < Q; ++j) {
+            v0 += tb.T2[pr * Q + j] * tv0[j] + tb.dT2[pr * Q + j] * tv1[j];
+            v1 += tb.T2[pr * Q + j] * tv2[j];
+          }
+          s0[q] = v0;
+          s1[q] = v1;
+        }
+        pw = p;
+      }
+    };
+    col_dispatch<0, P>(wave, stageBT);
+    __syncthreads();
+    if (pw >= 0) {
+      // rows of pair (pw, q); the tet's p = 1 wavefront also writes the (0,1) extra rows, the
+      // p = 0 wavefront the vertex row
+      auto writeBT = [&](auto ic) {
+        constexpr int p = decltype(ic)::value, nq = MO::nq(p);
+#pragma unroll
+        for (int q = 0; q < nq; ++q) {
+          Ls[MO::pair(p, q) * Q + k] = s0[q];
+          Ls[NP * Q + MO::pair(p, q) * Q + k] = s1[q];
+        }
+        if (TET && p == 1) {
+          Ls[MAIN + Q2 + k] = s0[nq];
+          Ls[MAIN + Q2 + Q + k] = s1[nq];
+        }
+        if (TET && p == 0) Ls[MAIN + Q2 + 2 * Q + k] = sx;
+      };
+      col_dispatch<0, P>(pw, writeBT);
+    }
+    __syncthreads();
+  }
+
+  // ---- A^T: k -> r, one slice per wavefront
+  {
+    T yv[P];
+    int dst = -1, cnt = 0;
+    T* Ls = lds;
+    auto stageAT = [&](auto ic) {
+      constexpr int sl = decltype(ic)::value;
+      if constexpr (TET) {
+        constexpr int np = sl + 1, nr = P - sl;
+        const int e2 = lane / np, p = lane - e2 * np, q = sl - p;
+        if (e2 < E) {
+          Ls = lds + e2 * SLAB;
+          const int pr = MO::pair(p, q);
+          const bool x01 = sl == 1 && p == 0;   // pair (0,1): plus its p = 1 plane part
+          T sv0[Q], sv1[Q];
+#pragma unroll
+          for (int k = 0; k < Q; ++k) {
+            sv0[k] = Ls[pr * Q + k] + (x01 ? Ls[MAIN + Q2 + k] : T(0));
+            sv1[k] = Ls[NP * Q + pr * Q + k] + (x01 ? Ls[MAIN + Q2 + Q + k] : T(0));
+          }
+#pragma unroll
+          for (int r = 0; r < nr; ++r) {
+            T v = T(0);
+            if (sl == 0 && r == 1) {
+#pragma unroll
+              for (int k = 0; k < Q; ++k) v += Ls[MAIN + Q2 + 2 * Q + k];
+            } else {
+#pragma unroll
+              for (int k = 0; k < Q; ++k)
+                v += tb.T3[(MO::m0(0, sl) + r) * Q + k] * sv0[k] + tb.dT3[(MO::m0(0, sl) + r) * Q + k] * sv1[k];
+            }
+            yv[r] = v;
+          }
+          dst = MO::m0(p, q);
+          cnt = nr;
+        }
+      } else {
+        constexpr int p = sl, nr = P - p;
+        const int e2 = lane / P, q = lane - e2 * P;
+        if (e2 < E) {
+          Ls = lds + e2 * SLAB;
+          const int pr = MO::pair(p, q);
+          T sv0[Q], sv1[Q], xv0[Q], xv1[Q];
+#pragma unroll
+          for (int k = 0; k < Q; ++k) {
+            sv0[k] = Ls[pr * Q + k];
+            sv1[k] = Ls[NP * Q + pr * Q + k];
+            // (0,q,1) modes also see the p = 1 rows
+            xv0[k] = p == 0 ? Ls[MO::pair(1, q) * Q + k] : T(0);
+            xv1[k] = p == 0 ? Ls[NP * Q + MO::pair(1, q) * Q + k] : T(0);
+          }
+#pragma unroll
+          for (int r = 0; r < nr; ++r) {
+            T v = T(0);
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+              const T f = tb.T3[(MO::m0(p, 0) + r) * Q + k], df = tb.dT3[(MO::m0(p, 0) + r) * Q + k];
+              if (p == 0 && r == 1)
+                v += f * (sv0[k] + xv0[k]) + df * (sv1[k] + xv1[k]);
+              else
+                v += f * sv0[k] + df * sv1[k];
+            }
+            yv[r] = v;
+          }
+          dst = MO::m0(p, 0) + q * nr;
+          cnt = nr;
+        }
+      }
+    };
+    col_dispatch<0, P>(wave, stageAT);
+    __syncthreads();
+    if (dst >= 0) {
+#pragma unroll
+      for (int r = 0; r < P; ++r)
+        if (r < cnt) Ls[dst + r] = yv[r];
+    }
+    __syncthreads();
+  }
+
+  for (int f = t; f < ne * M; f += BLOCK) {
+    const int e2 = f / M;
+    y[base * M + f] = lds[e2 * SLAB + (f - e2 * M)];
+  }
+}
+
+}  // namespace nir

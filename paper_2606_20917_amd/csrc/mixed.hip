@@ -6,16 +6,23 @@
 // of a group) is built on the host, sorted by decreasing cost (bytes moved, the bound
 // of these kernels), and workgroup b of one persistent grid of G workgroups runs items
 // b, b+G, b+2G, ... with the group function of each item's (shape, P): the register
-// pencil kernel for hexahedra, the LDS kernel for prisms and tetrahedra.  Items are
-// independent, so the result equals the per-batch launches bit for bit.  The static
+// pencil kernel of each shape (hexahedra; prisms and tetrahedra).  Items are independent,
+// so the result equals the per-batch launches of the same kernels bit for bit.  The static
 // schedule needs no shared counter (a dynamic atomic counter measured the same time on
 // the 100k-element mixed mesh).
 //
 // The plan tunes its launch on first use: the register budget of the kernel (2, 3 or 4
 // waves per SIMD; a tighter budget buys occupancy with spills) and the grid size (1..8
 // workgroups per CU, capped by that budget's occupancy), each pair timed on the caller's
-// operands.  It then captures [reset, persistent kernel] into a hipGraph that later
-// applies replay.
+// operands.  It then captures the persistent kernel into a hipGraph that later applies
+// replay.
+//
+// A second strategy is kept beside it: one hipGraph of per-batch launches, each with the
+// standalone kernel of its (shape, P) (own block size, LDS and register budget), spread over
+// up to four parallel graph branches balanced by bytes, so the launches overlap and fill each
+// other's tails.  The persistent kernel pays for its single launch with the union of the
+// item types' resources (LDS and registers of the largest); with the strategy left to the
+// plan (the default), the first apply times both and keeps the faster.
 
 #include <algorithm>
 #include <chrono>
@@ -29,15 +36,6 @@
 #include "mixed_kernels.h"
 
 namespace nir {
-
-// host-side group size of (shape, P): must equal the device functions' E
-static int host_group_size(int shape, int P) {
-  const int Q = P + 1;
-  if (shape == kHex) return 256 / (Q * Q);
-  const int NQ = Q * Q * Q;
-  const int tpe = NQ <= 32 ? 32 : (NQ <= 128 ? 64 : (NQ <= 343 ? 128 : 256));
-  return 256 / tpe;
-}
 
 }  // namespace nir
 
@@ -63,6 +61,14 @@ struct nir_mixed_plan {
   int occ[5] = {0, 0, 0, 0, 0};   // max workgroups per CU for budgets 2..4
   double tuned_ms = 0.0;
   int64_t bytes = 0, dof = 0;
+  int strategy_req = NIR_MIXED_AUTO;   // requested strategy
+  int strategy = 0;                    // strategy of the captured graph (0 before the first apply)
+  bool persistent_ok = true;           // every batch has P <= kMixedMaxP
+  static constexpr int kBranches = 4;
+  hipStream_t aux[kBranches] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[kBranches] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<int> branch_of;          // per-batch strategy: branch of each batch
+  double ms_persistent = -1.0, ms_per_batch = -1.0;
 };
 
 namespace nir {
@@ -100,6 +106,71 @@ static nir_status enqueue(nir_mixed_plan* pl, hipStream_t s, int W, int grid) {
                              pl->nitems, pl->counter, pl->dlam);
 }
 
+// per-batch strategy: every non-empty batch launched with its own standalone kernel; batches
+// spread over the plan's parallel branches (fork/join events on the capture stream)
+static nir_status enqueue_per_batch(nir_mixed_plan* pl, hipStream_t s) {
+  NIR_TRYS(hip_check(hipEventRecord(pl->fork, s), "fork event"));
+  for (int k = 0; k < nir_mixed_plan::kBranches; ++k)
+    NIR_TRYS(hip_check(hipStreamWaitEvent(pl->aux[k], pl->fork, 0), "fork wait"));
+  for (int b = 0; b < pl->nbatch; ++b) {
+    const nir_batch& B = pl->batches[b];
+    if (B.nelmt == 0) continue;
+    OpArgs a{};
+    a.in0 = pl->cur_in[b];
+    a.out0 = pl->cur_out[b];
+    a.helm = pl->geoms[b].helm;
+    a.lambda = pl->cur_lambda;
+    a.nelmt = B.nelmt;
+    NIR_TRYS(launch_helm_auto(pl->bases[b], B.dtype, B.deformed, a, pl->aux[pl->branch_of[b]]));
+  }
+  for (int k = 0; k < nir_mixed_plan::kBranches; ++k) {
+    NIR_TRYS(hip_check(hipEventRecord(pl->join[k], pl->aux[k]), "join event"));
+    NIR_TRYS(hip_check(hipStreamWaitEvent(s, pl->join[k], 0), "join wait"));
+  }
+  return NIR_OK;
+}
+
+// capture the chosen strategy into the plan's graph (replacing any previous one)
+static nir_status capture(nir_mixed_plan* pl, int strategy) {
+  if (pl->exec) {
+    (void)hipGraphExecDestroy(pl->exec);
+    pl->exec = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  NIR_TRYS(hip_check(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal), "begin capture"));
+  const nir_status st = strategy == NIR_MIXED_PERSISTENT ? enqueue(pl, pl->cap, pl->waves, pl->grid)
+                                                         : enqueue_per_batch(pl, pl->cap);
+  const nir_status st2 = hip_check(hipStreamEndCapture(pl->cap, &g), "end capture");
+  if (st != NIR_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (st2 != NIR_OK) return st2;
+  const nir_status st3 = hip_check(hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0), "graph instantiate");
+  (void)hipGraphDestroy(g);
+  if (st3 != NIR_OK) return st3;
+  pl->strategy = strategy;
+  return NIR_OK;
+}
+
+// average time of `reps` replays of the captured graph on the plan stream
+static nir_status time_graph(nir_mixed_plan* pl, int reps, double* ms) {
+  hipEvent_t a, b;
+  NIR_TRYS(hip_check(hipEventCreate(&a), "event"));
+  NIR_TRYS(hip_check(hipEventCreate(&b), "event"));
+  NIR_TRYS(hip_check(hipGraphLaunch(pl->exec, pl->cap), "graph launch"));   // warm-up
+  NIR_TRYS(hip_check(hipEventRecord(a, pl->cap), "event record"));
+  for (int r = 0; r < reps; ++r) NIR_TRYS(hip_check(hipGraphLaunch(pl->exec, pl->cap), "graph launch"));
+  NIR_TRYS(hip_check(hipEventRecord(b, pl->cap), "event record"));
+  NIR_TRYS(hip_check(hipEventSynchronize(b), "event sync"));
+  float t = 0.f;
+  NIR_TRYS(hip_check(hipEventElapsedTime(&t, a, b), "elapsed"));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *ms = double(t) / reps;
+  return NIR_OK;
+}
+
 // time `reps` launches with register budget W and grid g on the plan stream
 static nir_status time_grid(nir_mixed_plan* pl, int W, int g, int reps, double* ms) {
   hipEvent_t a, b;
@@ -129,6 +200,11 @@ nir_status nir_mixed_plan_destroy(nir_mixed_plan* pl) {
   if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
   for (void* v : {pl->dbatches, (void*)pl->ditems, (void*)pl->counter, (void*)pl->dlam})
     if (v) (void)hipFree(v);
+  for (int k = 0; k < nir_mixed_plan::kBranches; ++k) {
+    if (pl->aux[k]) (void)hipStreamDestroy(pl->aux[k]);
+    if (pl->join[k]) (void)hipEventDestroy(pl->join[k]);
+  }
+  if (pl->fork) (void)hipEventDestroy(pl->fork);
   if (pl->cap) (void)hipStreamDestroy(pl->cap);
   delete pl;
   return NIR_OK;
@@ -144,8 +220,6 @@ nir_status nir_mixed_plan_create(int32_t nbatch, const nir_batch* batches, const
     NIR_TRYS(nir_validate_batch(&batches[b], bases[b]));
     if (batches[b].dtype != dtype) return fail(NIR_EINVAL, "all batches of a mixed plan share one dtype");
     if (batches[b].math != NIR_MATH_NATIVE) return fail(NIR_ENOTSUP, "mixed plans use native contractions");
-    if (batches[b].nmodes > kMixedMaxP)
-      return fail(NIR_ENOTSUP, "mixed plans support P <= %d (batch %d has P = %d)", kMixedMaxP, b, batches[b].nmodes);
     if (batches[b].nelmt > 0 && !geoms[b].helm) return fail(NIR_EINVAL, "batch %d has no Helmholtz factors", b);
   }
   nir_mixed_plan* pl = new (std::nothrow) nir_mixed_plan();
@@ -157,6 +231,8 @@ nir_status nir_mixed_plan_create(int32_t nbatch, const nir_batch* batches, const
   pl->geoms.assign(geoms, geoms + nbatch);
   pl->cur_in.assign(nbatch, nullptr);
   pl->cur_out.assign(nbatch, nullptr);
+  for (int b = 0; b < nbatch; ++b)
+    if (batches[b].nmodes > kMixedMaxP && batches[b].nelmt > 0) pl->persistent_ok = false;
   // work list: groups of each batch, decreasing cost (algorithmic bytes of the group)
   struct W {
     int64_t cost;
@@ -164,19 +240,37 @@ nir_status nir_mixed_plan_create(int32_t nbatch, const nir_batch* batches, const
   };
   std::vector<W> w;
   const int s = dtype == NIR_F64 ? 8 : 4;
-  for (int b = 0; b < nbatch; ++b) {
+  for (int b = 0; b < nbatch && pl->persistent_ok; ++b) {
     const nir_batch& B = batches[b];
-    const int E = host_group_size(B.shape, B.nmodes);
+    const int E = dtype == NIR_F64 ? mixed_group_elems<double>(B.shape, B.nmodes)
+                                   : mixed_group_elems<float>(B.shape, B.nmodes);
     const int64_t M = modes_of(B.shape, B.nmodes), NQ = int64_t(B.nquad) * B.nquad * B.nquad;
     const int64_t per_elem = s * (2 * M + 7 * (B.deformed ? NQ : 1));
-    pl->bytes += per_elem * B.nelmt;
-    pl->dof += M * B.nelmt;
     for (int64_t f = 0; f < B.nelmt; f += E) {
       const int64_t n = std::min<int64_t>(E, B.nelmt - f);
       w.push_back({per_elem * n, MixedItem{b, 0, f}});
     }
   }
   std::stable_sort(w.begin(), w.end(), [](const W& a, const W& b) { return a.cost > b.cost; });
+  // bytes / DoF of one apply, and the per-batch strategy's branches (largest batch first onto
+  // the least loaded branch)
+  std::vector<std::pair<int64_t, int>> order;
+  for (int b = 0; b < nbatch; ++b) {
+    const nir_batch& B = batches[b];
+    const int64_t M = modes_of(B.shape, B.nmodes), NQ = int64_t(B.nquad) * B.nquad * B.nquad;
+    const int64_t bb = s * (2 * M + 7 * (B.deformed ? NQ : 1)) * B.nelmt;
+    pl->bytes += bb;
+    pl->dof += M * B.nelmt;
+    order.push_back({bb, b});
+  }
+  std::stable_sort(order.begin(), order.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+  pl->branch_of.assign(nbatch, 0);
+  int64_t load[nir_mixed_plan::kBranches] = {0, 0, 0, 0};
+  for (const auto& o : order) {
+    int k = int(std::min_element(load, load + nir_mixed_plan::kBranches) - load);
+    pl->branch_of[o.second] = k;
+    load[k] += o.first;
+  }
   if (w.size() > 0x7fffffff) {
     nir_mixed_plan_destroy(pl);
     return fail(NIR_EINVAL, "too many work items");
@@ -191,10 +285,17 @@ nir_status nir_mixed_plan_create(int32_t nbatch, const nir_batch* batches, const
                       "hipMalloc")) != NIR_OK ||
       (st = hip_check(hipMalloc((void**)&pl->counter, sizeof(int)), "hipMalloc")) != NIR_OK ||
       (st = hip_check(hipMalloc((void**)&pl->dlam, sizeof(double)), "hipMalloc")) != NIR_OK ||
-      (st = hip_check(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking), "stream")) != NIR_OK) {
+      (st = hip_check(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking), "stream")) != NIR_OK ||
+      (st = hip_check(hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming), "event")) != NIR_OK) {
     nir_mixed_plan_destroy(pl);
     return st;
   }
+  for (int k = 0; k < nir_mixed_plan::kBranches; ++k)
+    if ((st = hip_check(hipStreamCreateWithFlags(&pl->aux[k], hipStreamNonBlocking), "stream")) != NIR_OK ||
+        (st = hip_check(hipEventCreateWithFlags(&pl->join[k], hipEventDisableTiming), "event")) != NIR_OK) {
+      nir_mixed_plan_destroy(pl);
+      return st;
+    }
   if (!items.empty() &&
       (st = hip_check(hipMemcpy(pl->ditems, items.data(), sizeof(MixedItem) * items.size(), hipMemcpyHostToDevice),
                       "upload items")) != NIR_OK) {
@@ -232,7 +333,7 @@ nir_status nir_mixed_helmholtz_apply(nir_mixed_plan* pl, double lambda, const vo
     if (i < o + nb && o < i + nb) return fail(NIR_EINVAL, "batch %d: input and output overlap", b);
     if (pl->cur_in[b] != coef_in[b] || pl->cur_out[b] != coef_out[b]) changed = true;
   }
-  if (pl->nitems == 0) return NIR_OK;
+  if (pl->dof == 0) return NIR_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (changed || lambda != pl->cur_lambda) {
     // descriptors live in device memory read by the kernel: update them in order with the caller's work
@@ -244,36 +345,64 @@ nir_status nir_mixed_helmholtz_apply(nir_mixed_plan* pl, double lambda, const vo
     NIR_TRYS(pl->dtype == NIR_F64 ? upload_batches<double>(pl) : upload_batches<float>(pl));
     NIR_TRYS(hip_check(hipMemcpy(pl->dlam, &lambda, sizeof(double), hipMemcpyHostToDevice), "upload lambda"));
     pl->cur_lambda = lambda;
+    // the per-batch graph holds pointers and lambda in its kernel nodes: capture it again
+    if (pl->exec && pl->strategy == NIR_MIXED_PER_BATCH) NIR_TRYS(capture(pl, NIR_MIXED_PER_BATCH));
   }
   if (!pl->exec) {
-    // tune the persistent grid on these operands, then capture [reset, kernel]
-    double best = 1e300;
-    int best_g = pl->ncu, best_w = 2;
-    for (int W = 2; W <= 4; ++W)
-      for (int per_cu = 1; per_cu <= std::min(8, pl->occ[W]); ++per_cu) {
-        double ms = 0;
-        NIR_TRYS(time_grid(pl, W, per_cu * pl->ncu, 3, &ms));
-        if (ms < best) {
-          best = ms;
-          best_g = per_cu * pl->ncu;
-          best_w = W;
+    const int req = pl->persistent_ok ? pl->strategy_req : NIR_MIXED_PER_BATCH;
+    pl->ms_persistent = pl->ms_per_batch = -1.0;
+    if (req != NIR_MIXED_PER_BATCH) {
+      // tune the persistent grid and register budget on these operands
+      double best = 1e300;
+      int best_g = pl->ncu, best_w = 2;
+      for (int W = 2; W <= 4; ++W)
+        for (int per_cu = 1; per_cu <= std::min(8, pl->occ[W]); ++per_cu) {
+          double ms = 0;
+          NIR_TRYS(time_grid(pl, W, per_cu * pl->ncu, 3, &ms));
+          if (ms < best) {
+            best = ms;
+            best_g = per_cu * pl->ncu;
+            best_w = W;
+          }
         }
-      }
-    pl->grid = best_g;
-    pl->waves = best_w;
-    pl->tuned_ms = best;
-    hipGraph_t g = nullptr;
-    NIR_TRYS(hip_check(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal), "begin capture"));
-    const nir_status st = enqueue(pl, pl->cap, pl->waves, pl->grid);
-    const nir_status st2 = hip_check(hipStreamEndCapture(pl->cap, &g), "end capture");
-    if (st != NIR_OK) return st;
-    if (st2 != NIR_OK) return st2;
-    const nir_status st3 = hip_check(hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0), "graph instantiate");
-    (void)hipGraphDestroy(g);
-    if (st3 != NIR_OK) return st3;
+      pl->grid = best_g;
+      pl->waves = best_w;
+      NIR_TRYS(capture(pl, NIR_MIXED_PERSISTENT));
+      NIR_TRYS(time_graph(pl, 5, &pl->ms_persistent));
+    }
+    if (req != NIR_MIXED_PERSISTENT) {
+      NIR_TRYS(capture(pl, NIR_MIXED_PER_BATCH));
+      NIR_TRYS(time_graph(pl, 5, &pl->ms_per_batch));
+    }
+    if (req == NIR_MIXED_AUTO && pl->ms_persistent <= pl->ms_per_batch) NIR_TRYS(capture(pl, NIR_MIXED_PERSISTENT));
+    pl->tuned_ms = pl->strategy == NIR_MIXED_PERSISTENT ? pl->ms_persistent : pl->ms_per_batch;
     NIR_TRYS(hip_check(hipStreamSynchronize(pl->cap), "sync"));
   }
   return hip_check(hipGraphLaunch(pl->exec, s), "graph launch");
+}
+
+nir_status nir_mixed_plan_set_strategy(nir_mixed_plan* pl, int32_t strategy) {
+  if (!pl) return fail(NIR_EINVAL, "plan is NULL");
+  if (strategy < NIR_MIXED_AUTO || strategy > NIR_MIXED_PER_BATCH) return fail(NIR_EINVAL, "invalid strategy %d", strategy);
+  if (strategy == NIR_MIXED_PERSISTENT && !pl->persistent_ok)
+    return fail(NIR_ENOTSUP, "the persistent kernel covers P <= %d; this plan has a batch above", kMixedMaxP);
+  pl->strategy_req = strategy;
+  if (pl->exec) {   // re-tuned and re-captured at the next apply
+    NIR_TRYS(hip_check(hipStreamSynchronize(pl->cap), "sync"));
+    (void)hipGraphExecDestroy(pl->exec);
+    pl->exec = nullptr;
+  }
+  pl->strategy = 0;
+  return NIR_OK;
+}
+
+nir_status nir_mixed_plan_timings(const nir_mixed_plan* pl, int32_t* strategy, double* ms_persistent,
+                                  double* ms_per_batch) {
+  if (!pl) return fail(NIR_EINVAL, "plan is NULL");
+  if (strategy) *strategy = pl->strategy;
+  if (ms_persistent) *ms_persistent = pl->ms_persistent;
+  if (ms_per_batch) *ms_per_batch = pl->ms_per_batch;
+  return NIR_OK;
 }
 
 nir_status nir_mixed_plan_info(const nir_mixed_plan* pl, int32_t* nitems, int32_t* grid, double* tuned_ms,

@@ -137,6 +137,10 @@ nir_status launch_geom(const nir_basis* b, int deformed, int64_t nelmt, const do
                        double amp, double* dxi_dx, double* jac, double* helm64, float* helm32,
                        hipStream_t s);
 
+// register-pencil fused Helmholtz apply of the collapsed shapes (helm_col_{prism,tet}.hip)
+nir_status launch_helm_col_prism(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
+nir_status launch_helm_col_tet(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
+
 nir_status launch_helm_hex_f16split(const nir_basis* b, int deformed, const OpArgs& a, hipStream_t s);
 // the fused Helmholtz apply with the currently selected kernel variant (native contractions)
 nir_status launch_helm_auto(const nir_basis* basis, int dtype, int deformed, const OpArgs& a, hipStream_t s);

@@ -16,6 +16,7 @@ HEX, PRISM, TET = 0, 1, 2
 F64, F32 = 0, 1
 MATH_NATIVE, MATH_F16SPLIT = 0, 1
 MAP_VERTEX, MAP_VERTEX_SIN = 0, 1
+MIXED_AUTO, MIXED_PERSISTENT, MIXED_PER_BATCH = range(3)
 VARIANT_AUTO, VARIANT_GENERIC, VARIANT_PENCIL, VARIANT_PENCIL_U2, VARIANT_PENCIL_E1, VARIANT_PENCIL_PF = range(6)
 CG_FP64, CG_MIXED_F32, CG_MIXED_F16SPLIT = 0, 1, 2
 
@@ -84,6 +85,8 @@ _SIGS = {
     "nir_mixed_plan_create": (_i32, [_i32, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
     "nir_mixed_helmholtz_apply": (_i32, [_vp, _dbl, _vp, _vp, _vp]),
     "nir_mixed_plan_info": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "nir_mixed_plan_set_strategy": (_i32, [_vp, _i32]),
+    "nir_mixed_plan_timings": (_i32, [_vp, _vp, _vp, _vp]),
     "nir_mixed_plan_destroy": (_i32, [_vp]),
     "nir_get_helmholtz_variant": (_i32, [_i32, _i32, _i32]),
     "nir_autotune_helmholtz": (_i32, [ctypes.POINTER(nir_batch), _vp, ctypes.POINTER(nir_geom), _dbl, _vp, _vp, _i32,
@@ -346,7 +349,13 @@ class MixedPlan:
         by, dof = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().nir_mixed_plan_info(self.handle, ctypes.byref(ni), ctypes.byref(g), ctypes.byref(ms),
                                          ctypes.byref(by), ctypes.byref(dof)))
-        return dict(nitems=ni.value, grid=g.value, tuned_ms=ms.value, bytes=by.value, dof=dof.value)
+        st, mp, mb = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().nir_mixed_plan_timings(self.handle, ctypes.byref(st), ctypes.byref(mp), ctypes.byref(mb)))
+        return dict(nitems=ni.value, grid=g.value, tuned_ms=ms.value, bytes=by.value, dof=dof.value,
+                    strategy=st.value, ms_persistent=mp.value, ms_per_batch=mb.value)
+
+    def set_strategy(self, strategy):
+        _check(lib().nir_mixed_plan_set_strategy(self.handle, strategy))
 
 
 def nir_mixed_plan_create(batches, bases, geoms):

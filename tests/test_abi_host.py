@@ -167,14 +167,14 @@ def test_autotune_cache_roundtrip(tmp_path):
         assert nir.nir_get_helmholtz_variant(nir.HEX, 2, nir.F64) == nir.VARIANT_PENCIL_PF
         assert nir.nir_get_helmholtz_variant(nir.HEX, 10, nir.F64) == nir.VARIANT_PENCIL_U2
         assert nir.nir_get_helmholtz_variant(nir.HEX, 10, nir.F32) == nir.VARIANT_PENCIL_E1
-        assert nir.nir_get_helmholtz_variant(nir.PRISM, 10, nir.F32) == nir.VARIANT_GENERIC
+        assert nir.nir_get_helmholtz_variant(nir.PRISM, 10, nir.F32) == nir.VARIANT_PENCIL
         nir.nir_autotune_load(path)
         assert nir.nir_get_helmholtz_variant(nir.HEX, 6, nir.F64) == nir.VARIANT_PENCIL_U2
         assert nir.nir_get_helmholtz_variant(nir.TET, 3, nir.F32) == nir.VARIANT_GENERIC
         # corrupt or invalid caches are rejected and leave the table unchanged
         bad = tmp_path / "bad.json"
         for txt in ("not json", '{"format": "libnir-autotune-1", "entries": [{"shape": 0, "P": 6}]}',
-                    '{"format": "libnir-autotune-1", "entries": [{"shape": 1, "P": 6, "dtype": 0, "variant": 2}]}',
+                    '{"format": "libnir-autotune-1", "entries": [{"shape": 1, "P": 6, "dtype": 0, "variant": 3}]}',
                     '{"format": "libnir-autotune-1", "entries": [{"shape": 0, "P": 12, "dtype": 0, "variant": 1}'):
             bad.write_text(txt)
             with pytest.raises(nir.NirError):
@@ -182,8 +182,9 @@ def test_autotune_cache_roundtrip(tmp_path):
             assert nir.nir_get_helmholtz_variant(nir.HEX, 6, nir.F64) == nir.VARIANT_PENCIL_U2
         with pytest.raises(nir.NirError):
             nir.nir_autotune_load(str(tmp_path / "missing.json"))
-        with pytest.raises(nir.NirError):   # pencil kernels are hex only
-            nir.nir_set_helmholtz_variant(nir.PRISM, 4, nir.F64, nir.VARIANT_PENCIL)
+        with pytest.raises(nir.NirError):   # the unrolled/E1/prefetch pencil kernels are hex only
+            nir.nir_set_helmholtz_variant(nir.PRISM, 4, nir.F64, nir.VARIANT_PENCIL_U2)
+        nir.nir_set_helmholtz_variant(nir.PRISM, 4, nir.F64, nir.VARIANT_PENCIL)
     finally:
-        for s, P, d in ((nir.HEX, 6, nir.F64), (nir.TET, 3, nir.F32)):
+        for s, P, d in ((nir.HEX, 6, nir.F64), (nir.TET, 3, nir.F32), (nir.PRISM, 4, nir.F64)):
             nir.nir_set_helmholtz_variant(s, P, d, nir.VARIANT_AUTO)
