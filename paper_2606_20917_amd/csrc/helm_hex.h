@@ -32,7 +32,8 @@ struct HexTabView {
 };
 
 // variant: 0 = E_max elements per 256-thread block, 1 = point loop unrolled twice,
-// 2 = one element per block, 3 = geometry prefetched into registers
+// 2 = one element per block, 3 = geometry prefetched into registers, 4 = planes exchanged two
+// at a time
 nir_status launch_helm_hex_pencil(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s,
                                   int variant = 0);
 

@@ -6,9 +6,9 @@
 // Every thread owns one "pencil" of an element: a line of Q (or P) values along
 // the direction being contracted, held in registers.  A contraction along the
 // pencil is pure VALU work whose basis operands are the same for every lane;
-// they come from the kernel-argument segment, so the compiler feeds them
-// through scalar registers and no LDS traffic is spent on them.  Between two
-// sweeps the pencils are transposed through LDS.
+// they come from a read-only table in global memory read at uniform addresses,
+// so the compiler issues scalar loads and no LDS traffic is spent on them.
+// Between two sweeps the pencils are transposed through LDS.
 //
 // Forward (x -> u and its three reference derivatives at the points), the
 // derivatives taken directly with the derivative tables B' = d psi/d xi
@@ -31,24 +31,38 @@
 
 namespace nir {
 
-template <int P, class T, bool DEF, int IU, int E, bool PF>
-__global__ void __launch_bounds__(256) k_helm_hex(const T* __restrict__ tabs, const T* __restrict__ x,
+// Register budget of the two-plane variant: the waves per SIMD that its LDS footprint allows
+// (160 KiB per CU, four SIMDs), capped at 3 (512 / 3 VGPRs), so that registers do not hold the
+// occupancy below what the smaller slab allows.  The other variants keep the compiler's own
+// choice (measured faster: at P >= 8 forcing the budget lowered their throughput).
+template <int P, class T, int E, bool TP>
+constexpr int hex_waves_target() {
+  using D = HexPencilDims<P, T, E, TP>;
+  const int blocks = (160 * 1024) / (D::LDS * int(sizeof(T)));
+  const int waves = blocks * (D::BLOCK / 64) / 4;
+  return !TP ? 1 : (waves < 1 ? 1 : (waves > 3 ? 3 : waves));
+}
+
+template <int P, class T, bool DEF, int IU, int E, bool PF, bool TP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(hex_waves_target<P, T, E, TP>())))
+k_helm_hex(const T* __restrict__ tabs, const T* __restrict__ x,
                                                   T* __restrict__ y, const T* __restrict__ helm,
                                                   const T* __restrict__ wq, T lambda, int64_t nelmt) {
   // one element group per block (no grid-stride loop: the basis operands stay short-lived)
-  __shared__ T lds[HexPencilDims<P, T, E>::LDS];
-  helm_hex_group<P, T, DEF, IU, E, PF>(tabs, x, y, helm, wq, lambda, nelmt, int64_t(blockIdx.x) * E, lds);
+  __shared__ T lds[HexPencilDims<P, T, E, TP>::LDS];
+  helm_hex_group<P, T, DEF, IU, E, PF, TP>(tabs, x, y, helm, wq, lambda, nelmt, int64_t(blockIdx.x) * E, lds);
 }
 
 // variant: 0 = E_max elements per 256-thread block, 1 = same with the point loop unrolled twice,
-// 2 = one element per block (smaller LDS footprint, more blocks per CU), 3 = geometry prefetch
-template <int P, class T, bool DEF, int IU, int E, bool PF>
+// 2 = one element per block (smaller LDS footprint, more blocks per CU), 3 = geometry prefetch,
+// 4 = planes exchanged two at a time
+template <int P, class T, bool DEF, int IU, int E, bool PF, bool TP = false>
 static void launch_cfg(const T* tb, const T* x, T* y, const T* helm, const T* wq, T lam, int64_t nelmt,
                        hipStream_t s) {
-  using D = HexPencilDims<P, T, E>;
+  using D = HexPencilDims<P, T, E, TP>;
   const int64_t nb = (nelmt + E - 1) / E;
-  hipLaunchKernelGGL((k_helm_hex<P, T, DEF, IU, E, PF>), dim3(static_cast<unsigned>(nb)), dim3(D::BLOCK), 0, s, tb,
-                     x, y, helm, wq, lam, nelmt);
+  hipLaunchKernelGGL((k_helm_hex<P, T, DEF, IU, E, PF, TP>), dim3(static_cast<unsigned>(nb)), dim3(D::BLOCK), 0, s,
+                     tb, x, y, helm, wq, lam, nelmt);
 }
 
 template <int P, class T, bool DEF>
@@ -59,6 +73,7 @@ static void launch_var(int variant, const T* tb, const T* x, T* y, const T* helm
     case 1: launch_cfg<P, T, DEF, 2, EMAX, false>(tb, x, y, helm, wq, lam, nelmt, s); break;
     case 2: launch_cfg<P, T, DEF, 1, 1, false>(tb, x, y, helm, wq, lam, nelmt, s); break;
     case 3: launch_cfg<P, T, DEF, 1, EMAX, true>(tb, x, y, helm, wq, lam, nelmt, s); break;
+    case 4: launch_cfg<P, T, DEF, 1, EMAX, false, true>(tb, x, y, helm, wq, lam, nelmt, s); break;
     default: launch_cfg<P, T, DEF, 1, EMAX, false>(tb, x, y, helm, wq, lam, nelmt, s); break;
   }
 }

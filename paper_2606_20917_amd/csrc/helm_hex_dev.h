@@ -6,14 +6,18 @@
 
 namespace nir {
 
-template <int P, class T, int E_ = 256 / ((P + 1) * (P + 1))>
+// TP: the three planes exchanged between sweeps B and C (and C^T and B^T) pass through LDS
+// two at a time, so the slab holds two planes instead of three
+template <int P, class T, int E_ = 256 / ((P + 1) * (P + 1)), bool TP = false>
 struct HexPencilDims {
   static constexpr int Q = P + 1, Q2 = Q * Q, NQ = Q2 * Q, M = P * P * P;
   static constexpr int E = E_;                            // elements per block (Q^2 threads each)
   static constexpr int BLOCK = (E * Q2 + 63) / 64 * 64;   // threads per block
   static constexpr int PP = P | 1;                        // odd stride of a mode pencil row
   static constexpr int PQ2 = P * Q2, P2Q = P * P * Q;
-  static constexpr int SLAB = (3 * PQ2 > P * P * PP) ? 3 * PQ2 : P * P * PP;
+  static constexpr int NPL = TP ? 2 : 3;                  // planes resident at once
+  static constexpr int S1 = NPL * PQ2 > P * P * PP ? NPL * PQ2 : P * P * PP;
+  static constexpr int SLAB = S1 > 2 * P2Q ? S1 : 2 * P2Q;
   static constexpr int LDS = E * SLAB;                    // values of T per block
 };
 
@@ -22,12 +26,15 @@ struct HexPencilDims {
 // IU is the unroll factor of the streamed point loop (register pressure vs. loads in flight);
 // E the elements per block (block of HexPencilDims<P,T,E>::BLOCK threads); PF loads the 7Q
 // geometric factors of the thread's pencil into registers before the first sweep, so their
-// HBM latency overlaps the forward sweeps (small P only: 7Q values per thread).
-template <int P, class T, bool DEF, int IU = 1, int E_ = 256 / ((P + 1) * (P + 1)), bool PF = false>
+// HBM latency overlaps the forward sweeps (small P only: 7Q values per thread).  TP exchanges
+// the planes of the direction-2/direction-1 sweeps two at a time (two more barriers each way,
+// a third less LDS per element: more blocks per CU at large P).
+template <int P, class T, bool DEF, int IU = 1, int E_ = 256 / ((P + 1) * (P + 1)), bool PF = false,
+          bool TP = false>
 __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const T* __restrict__ x, T* __restrict__ y,
                                                const T* __restrict__ helm, const T* __restrict__ wq, T lambda,
                                                int64_t nelmt, int64_t base, T* __restrict__ lds) {
-  using D = HexPencilDims<P, T, E_>;
+  using D = HexPencilDims<P, T, E_, TP>;
   constexpr int BLOCK = D::BLOCK;
   constexpr int Q = D::Q, Q2 = D::Q2, NQ = D::NQ, M = D::M, E = D::E, PP = D::PP, PQ2 = D::PQ2, P2Q = D::P2Q,
                 SLAB = D::SLAB;
@@ -121,7 +128,7 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
       for (int j = 0; j < Q; ++j) {
         L[pb * Q2 + j * Q + kb] = c0[j];
         L[PQ2 + pb * Q2 + j * Q + kb] = c1[j];
-        L[2 * PQ2 + pb * Q2 + j * Q + kb] = c2[j];
+        if (!TP) L[2 * PQ2 + pb * Q2 + j * Q + kb] = c2[j];
       }
     }
     __syncthreads();
@@ -134,7 +141,17 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
     for (int p = 0; p < P; ++p) {
       C0[p] = L[p * Q2 + s];
       C1[p] = L[PQ2 + p * Q2 + s];
-      C2[p] = L[2 * PQ2 + p * Q2 + s];
+      if (!TP) C2[p] = L[2 * PQ2 + p * Q2 + s];
+    }
+    if (TP) {   // third plane through the space of the first
+      __syncthreads();
+      if (act && s < P * Q) {
+#pragma unroll
+        for (int j = 0; j < Q; ++j) L[pb * Q2 + j * Q + kb] = c2[j];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < P; ++p) C2[p] = L[p * Q2 + s];
     }
     T t0[P], t1[P], t2[P];
 #pragma unroll
@@ -180,31 +197,68 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
       for (int p = 0; p < P; ++p) {
         L[p * Q2 + s] = t0[p];
         L[PQ2 + p * Q2 + s] = t1[p];
-        L[2 * PQ2 + p * Q2 + s] = t2[p];
+        if (!TP) L[2 * PQ2 + p * Q2 + s] = t2[p];
       }
     }
     __syncthreads();
 
     // ---- B^T: pencils (p,k), j -> q
     T s0[P], s1[P];
-    if (act && s < P * Q) {
-      T tv0[Q], tv1[Q], tv2[Q];
-#pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        tv0[j] = L[pb * Q2 + j * Q + kb];
-        tv1[j] = L[PQ2 + pb * Q2 + j * Q + kb];
-        tv2[j] = L[2 * PQ2 + pb * Q2 + j * Q + kb];
-      }
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        T v0 = T(0), v1 = T(0);
+    if constexpr (!TP) {
+      if (act && s < P * Q) {
+        T tv0[Q], tv1[Q], tv2[Q];
 #pragma unroll
         for (int j = 0; j < Q; ++j) {
-          v0 += tb.B[j][q] * tv0[j] + tb.D[j][q] * tv1[j];
-          v1 += tb.B[j][q] * tv2[j];
+          tv0[j] = L[pb * Q2 + j * Q + kb];
+          tv1[j] = L[PQ2 + pb * Q2 + j * Q + kb];
+          tv2[j] = L[2 * PQ2 + pb * Q2 + j * Q + kb];
         }
-        s0[q] = v0;
-        s1[q] = v1;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          T v0 = T(0), v1 = T(0);
+#pragma unroll
+          for (int j = 0; j < Q; ++j) {
+            v0 += tb.B[j][q] * tv0[j] + tb.D[j][q] * tv1[j];
+            v1 += tb.B[j][q] * tv2[j];
+          }
+          s0[q] = v0;
+          s1[q] = v1;
+        }
+      }
+    } else {
+      // first two planes, then the third through the space of the first
+      if (act && s < P * Q) {
+        T tv0[Q], tv1[Q];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          tv0[j] = L[pb * Q2 + j * Q + kb];
+          tv1[j] = L[PQ2 + pb * Q2 + j * Q + kb];
+        }
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          T v0 = T(0);
+#pragma unroll
+          for (int j = 0; j < Q; ++j) v0 += tb.B[j][q] * tv0[j] + tb.D[j][q] * tv1[j];
+          s0[q] = v0;
+        }
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) L[p * Q2 + s] = t2[p];
+      }
+      __syncthreads();
+      if (act && s < P * Q) {
+        T tv2[Q];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) tv2[j] = L[pb * Q2 + j * Q + kb];
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          T v1 = T(0);
+#pragma unroll
+          for (int j = 0; j < Q; ++j) v1 += tb.B[j][q] * tv2[j];
+          s1[q] = v1;
+        }
       }
     }
     __syncthreads();
