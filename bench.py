@@ -96,13 +96,13 @@ def cpu_baseline(cases, budget_s):
 # HBM bytes per launch of the dominant kernel measured with FETCH_SIZE / WRITE_SIZE (calibrated
 # by a plain 1 GiB copy: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), valid for that kernel variant while
 # the kernel sources hash to `src_sha`
-TRAFFIC = {"P": 10, "dtype": "f64", "variant": 3, "bytes": 2990406021, "src_sha": "9f3d97aea73a720b"}
+TRAFFIC = {"P": 10, "dtype": "f64", "variant": 6, "bytes": 2994028428, "src_sha": "84af3440bdb7be5d"}
 
 
 def kernel_src_sha():
     import hashlib
     h = hashlib.sha256()
-    for f in ("helm_hex_dev.h", "helm_hex.hip", "helm_hex.h"):
+    for f in ("helm_hex_dev.h", "helm_hex.hip", "helm_hex.h", "uniform_table.h"):
         h.update(open(os.path.join(ROOT, "paper_2606_20917_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -358,7 +358,7 @@ def main():
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--variant", default="auto", choices=["auto", "generic", "pencil"])
+    ap.add_argument("--variant", default="auto", choices=["auto", "generic", "pencil", "u2", "e1", "pf", "split"])
     ap.add_argument("--math", default="native", choices=["native", "f16split"])
     ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k", "collapsed", "copy"])
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
@@ -380,7 +380,9 @@ def main():
     if args.workload == "collapsed":
         return bench_collapsed(args)
     ps = [int(p) for p in args.ps.split(",")]
-    vid = {"auto": nir.VARIANT_AUTO, "generic": nir.VARIANT_GENERIC, "pencil": nir.VARIANT_PENCIL}[args.variant]
+    vid = {"auto": nir.VARIANT_AUTO, "generic": nir.VARIANT_GENERIC, "pencil": nir.VARIANT_PENCIL,
+           "u2": nir.VARIANT_PENCIL_U2, "e1": nir.VARIANT_PENCIL_E1, "pf": nir.VARIANT_PENCIL_PF,
+           "split": nir.VARIANT_PENCIL_SPLIT}[args.variant]
     for P in ps:
         nir.nir_set_helmholtz_variant(nir.HEX, P, nir.F64 if args.dtype == "f64" else nir.F32, vid)
     if args.math == "f16split" and args.dtype != "f32":

@@ -99,12 +99,11 @@ static int resolve_variant(int shape, int P, int dtype) {
   if (shape != kHex) return NIR_VARIANT_PENCIL;
   // defaults from a sweep of all variants on MI355X (32^3 curved hexes, per-point factors):
   // geometry prefetch wins for P <= 4, the plain pencil kernel in between, the two-plane
-  // exchange at P = 8, 9, and at P = 10 the two-fold point-loop unroll (FP64) or one element per
-  // block (FP32)
+  // exchange at P = 8 and 10 (and P = 9 in FP32), the two-fold point-loop unroll at P = 9 in FP64
   if (P <= 4) return NIR_VARIANT_PENCIL_PF;
   if (P <= 7) return NIR_VARIANT_PENCIL;
-  if (P <= 9) return NIR_VARIANT_PENCIL_SPLIT;
-  return dtype == NIR_F64 ? NIR_VARIANT_PENCIL_U2 : NIR_VARIANT_PENCIL_E1;
+  if (P == 9 && dtype == NIR_F64) return NIR_VARIANT_PENCIL_U2;
+  return NIR_VARIANT_PENCIL_SPLIT;
 }
 
 // the fused Helmholtz apply with the selected kernel variant (native contractions)

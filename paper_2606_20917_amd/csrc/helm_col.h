@@ -8,11 +8,11 @@ namespace nir {
 
 template <int SHAPE, int P, class T, bool DEF>
 __global__ void __launch_bounds__((ColDims<SHAPE, P, T>::BLOCK))
-    k_helm_col(DevTab<T> tb, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ helm, T lambda,
-               int64_t nelmt) {
+    k_helm_col(DevTab<T> tb, const T* __restrict__ pen, const T* __restrict__ x, T* __restrict__ y,
+               const T* __restrict__ helm, T lambda, int64_t nelmt) {
   using D = ColDims<SHAPE, P, T>;
   __shared__ T lds[D::LDS];
-  helm_col_group<SHAPE, P, T, DEF>(tb, x, y, helm, lambda, nelmt, int64_t(blockIdx.x) * D::E, lds);
+  helm_col_group<SHAPE, P, T, DEF>(tb, pen, x, y, helm, lambda, nelmt, int64_t(blockIdx.x) * D::E, lds);
 }
 
 template <int SHAPE, int P, class T>
@@ -20,7 +20,14 @@ nir_status launch_col_PT(const nir_basis* b, int deformed, const OpArgs& a, hipS
   using D = ColDims<SHAPE, P, T>;
   static_assert(D::LDS * sizeof(T) <= 65536, "LDS budget");
   DevTab<T> tb;
-  if constexpr (sizeof(T) == 8) tb = b->t64; else tb = b->t32;
+  const T* pen;
+  if constexpr (sizeof(T) == 8) {
+    tb = b->t64;
+    pen = b->pencil64;
+  } else {
+    tb = b->t32;
+    pen = b->pencil32;
+  }
   const int64_t nb = (a.nelmt + D::E - 1) / D::E;
   if (nb > 0x7fffffff) return fail(NIR_EINVAL, "too many elements for one launch");
   if (nb == 0) return ok();
@@ -29,9 +36,11 @@ nir_status launch_col_PT(const nir_basis* b, int deformed, const OpArgs& a, hipS
   const T* helm = static_cast<const T*>(a.helm);
   const dim3 grid(static_cast<unsigned>(nb)), block(D::BLOCK);
   if (deformed)
-    hipLaunchKernelGGL((k_helm_col<SHAPE, P, T, true>), grid, block, 0, s, tb, x, y, helm, T(a.lambda), a.nelmt);
+    hipLaunchKernelGGL((k_helm_col<SHAPE, P, T, true>), grid, block, 0, s, tb, pen, x, y, helm, T(a.lambda),
+                       a.nelmt);
   else
-    hipLaunchKernelGGL((k_helm_col<SHAPE, P, T, false>), grid, block, 0, s, tb, x, y, helm, T(a.lambda), a.nelmt);
+    hipLaunchKernelGGL((k_helm_col<SHAPE, P, T, false>), grid, block, 0, s, tb, pen, x, y, helm, T(a.lambda),
+                       a.nelmt);
   return hip_check(hipGetLastError(), "collapsed Helmholtz launch");
 }
 

@@ -38,6 +38,7 @@
 #include <type_traits>
 
 #include "nir_internal.h"
+#include "uniform_table.h"
 
 namespace nir {
 
@@ -87,10 +88,11 @@ __device__ __forceinline__ void col_dispatch(int v, F& f) {
 // base + g E, on a block of at least NSUB * ColDims::BLOCK threads (g = wavefront / NW; the
 // wavefronts past the last group only take part in the barriers); `lds` holds NSUB * LDS
 // values.  Every thread of the block must call it (it synchronises).
+// pen: the direction-1 factor and its derivative in [point][mode] layout (B then B').
 template <int SHAPE, int P, class T, bool DEF, int E_ = 0, int NSUB = 1>
-__device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __restrict__ x, T* __restrict__ y,
-                                               const T* __restrict__ helm, T lambda, int64_t nelmt, int64_t base0,
-                                               T* __restrict__ lds0) {
+__device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __restrict__ pen, const T* __restrict__ x,
+                                               T* __restrict__ y, const T* __restrict__ helm, T lambda, int64_t nelmt,
+                                               int64_t base0, T* __restrict__ lds0) {
   using D = ColDims<SHAPE, P, T, E_>;
   using MO = ColModes<SHAPE, P>;
   constexpr int Q = D::Q, Q2 = D::Q2, NQ = D::NQ, M = D::M, NP = D::NP, E = D::E, SLAB = D::SLAB,
@@ -144,15 +146,16 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 #pragma unroll
           for (int r = 0; r < nr; ++r) c[r] = (sl == 0 && r == 1) ? T(0) : Ls[m0 + r];   // vertex mode apart
 #pragma unroll
-          for (int k = 0; k < Q; ++k) {
-            T v0 = T(0), v1 = T(0);
+          for (int k = 0; k < Q; ++k) a0[k] = a1[k] = T(0);
 #pragma unroll
-            for (int r = 0; r < nr; ++r) {
-              v0 += tb.T3[(MO::m0(0, sl) + r) * Q + k] * c[r];
-              v1 += tb.dT3[(MO::m0(0, sl) + r) * Q + k] * c[r];
+          for (int r = 0; r < nr; ++r) {
+            const const_ptr<T> f = fresh_table(tb.T3) + (MO::m0(0, sl) + r) * Q;
+            const const_ptr<T> df = fresh_table(tb.dT3) + (MO::m0(0, sl) + r) * Q;
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+              a0[k] += f[k] * c[r];
+              a1[k] += df[k] * c[r];
             }
-            a0[k] = v0;
-            a1[k] = v1;
           }
           dst = MO::pair(p, q);
         }
@@ -169,19 +172,19 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
           T cx = T(0);
           if (p == 1) cx = Ls[MO::m0(0, 0) + q * P + 1];
 #pragma unroll
-          for (int k = 0; k < Q; ++k) {
-            T v0 = T(0), v1 = T(0);
+          for (int k = 0; k < Q; ++k) a0[k] = a1[k] = T(0);
 #pragma unroll
-            for (int r = 0; r < nr; ++r) {
-              v0 += tb.T3[(MO::m0(p, 0) + r) * Q + k] * c[r];
-              v1 += tb.dT3[(MO::m0(p, 0) + r) * Q + k] * c[r];
+          for (int r = 0; r < nr + (p == 1 ? 1 : 0); ++r) {
+            // r = nr (p = 1 only): the (0,q,1) vertex modes with psi^b_01
+            const int row = r < nr ? MO::m0(p, 0) + r : 1;
+            const T cr = r < nr ? c[r] : cx;
+            const const_ptr<T> f = fresh_table(tb.T3) + row * Q;
+            const const_ptr<T> df = fresh_table(tb.dT3) + row * Q;
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+              a0[k] += f[k] * cr;
+              a1[k] += df[k] * cr;
             }
-            if (p == 1) {
-              v0 += tb.T3[1 * Q + k] * cx;
-              v1 += tb.dT3[1 * Q + k] * cx;
-            }
-            a0[k] = v0;
-            a1[k] = v1;
           }
           dst = MO::pair(p, q);
         }
@@ -220,24 +223,18 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
           bv[nq] = Ls[NP * Q + MO::pair(0, 1) * Q + k];
         }
 #pragma unroll
-        for (int j = 0; j < Q; ++j) {
-          T v0 = T(0), v1 = T(0), v2 = T(0);
+        for (int j = 0; j < Q; ++j) b0[j] = b1[j] = b2[j] = T(0);
 #pragma unroll
-          for (int q = 0; q < nq; ++q) {
-            const T f = tb.T2[MO::pair(p, q) * Q + j], df = tb.dT2[MO::pair(p, q) * Q + j];
-            v0 += f * av[q];
-            v1 += df * av[q];
-            v2 += f * bv[q];
+        for (int q = 0; q < nq + (X ? 1 : 0); ++q) {
+          const int pr = q < nq ? MO::pair(p, q) : MO::pair(0, 1);
+          const const_ptr<T> f = fresh_table(tb.T2) + pr * Q;
+          const const_ptr<T> df = fresh_table(tb.dT2) + pr * Q;
+#pragma unroll
+          for (int j = 0; j < Q; ++j) {
+            b0[j] += f[j] * av[q];
+            b1[j] += df[j] * av[q];
+            b2[j] += f[j] * bv[q];
           }
-          if (X) {
-            const T f = tb.T2[MO::pair(0, 1) * Q + j], df = tb.dT2[MO::pair(0, 1) * Q + j];
-            v0 += f * av[nq];
-            v1 += df * av[nq];
-            v2 += f * bv[nq];
-          }
-          b0[j] = v0;
-          b1[j] = v1;
-          b2[j] = v2;
         }
         pw = p;
       }
@@ -294,10 +291,11 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
     const T* wq = tb.wq;
 #pragma unroll 1
     for (int i = 0; i < Q; ++i) {
+      const HexTabC<P, T> tk{fresh_table(pen)};
       T u = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        const T f = tb.T1[p * Q + i], df = tb.dT1[p * Q + i];
+        const T f = tk.B(i, p), df = tk.D(i, p);
         u += f * C0[p];
         d1 += df * C0[p];
         d2 += f * C1[p];
@@ -344,8 +342,9 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
       }
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        const T f = tb.T1[p * Q + i], df = tb.dT1[p * Q + i];
-        t0[p] += f * m + df * h1;
+        const T f = tk.B(i, p), df = tk.D(i, p);
+        t0[p] += f * m;
+        t0[p] += df * h1;
         t1[p] += f * h2;
         t2[p] += f * y3;
       }
@@ -388,11 +387,20 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 #pragma unroll
         for (int q = 0; q < nq + (X ? 1 : 0); ++q) {
           const int pr = q < nq ? MO::pair(p, q) : MO::pair(0, 1);
+          // one table row live at a time: psi^b_pq first, then its derivative
           T v0 = T(0), v1 = T(0);
+          {
+            const const_ptr<T> f = fresh_table(tb.T2) + pr * Q;
 #pragma unroll
-          for (int j = 0; j < Q; ++j) {
-            v0 += tb.T2[pr * Q + j] * tv0[j] + tb.dT2[pr * Q + j] * tv1[j];
-            v1 += tb.T2[pr * Q + j] * tv2[j];
+            for (int j = 0; j < Q; ++j) {
+              v0 += f[j] * tv0[j];
+              v1 += f[j] * tv2[j];
+            }
+          }
+          {
+            const const_ptr<T> df = fresh_table(tb.dT2) + pr * Q;
+#pragma unroll
+            for (int j = 0; j < Q; ++j) v0 += df[j] * tv1[j];
           }
           s0[q] = v0;
           s1[q] = v1;
@@ -450,9 +458,12 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 #pragma unroll
               for (int k = 0; k < Q; ++k) v += Ls[MAIN + Q2 + 2 * Q + k];
             } else {
+              const const_ptr<T> f = fresh_table(tb.T3) + (MO::m0(0, sl) + r) * Q;
 #pragma unroll
-              for (int k = 0; k < Q; ++k)
-                v += tb.T3[(MO::m0(0, sl) + r) * Q + k] * sv0[k] + tb.dT3[(MO::m0(0, sl) + r) * Q + k] * sv1[k];
+              for (int k = 0; k < Q; ++k) v += f[k] * sv0[k];
+              const const_ptr<T> df = fresh_table(tb.dT3) + (MO::m0(0, sl) + r) * Q;
+#pragma unroll
+              for (int k = 0; k < Q; ++k) v += df[k] * sv1[k];
             }
             yv[r] = v;
           }
@@ -476,14 +487,18 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
           }
 #pragma unroll
           for (int r = 0; r < nr; ++r) {
+            const const_ptr<T> f = fresh_table(tb.T3) + (MO::m0(p, 0) + r) * Q;
+            const const_ptr<T> df = fresh_table(tb.dT3) + (MO::m0(p, 0) + r) * Q;
             T v = T(0);
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
-              const T f = tb.T3[(MO::m0(p, 0) + r) * Q + k], df = tb.dT3[(MO::m0(p, 0) + r) * Q + k];
-              if (p == 0 && r == 1)
-                v += f * (sv0[k] + xv0[k]) + df * (sv1[k] + xv1[k]);
-              else
-                v += f * sv0[k] + df * sv1[k];
+              if (p == 0 && r == 1) {
+                v += f[k] * (sv0[k] + xv0[k]);
+                v += df[k] * (sv1[k] + xv1[k]);
+              } else {
+                v += f[k] * sv0[k];
+                v += df[k] * sv1[k];
+              }
             }
             yv[r] = v;
           }

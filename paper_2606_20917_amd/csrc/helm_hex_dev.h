@@ -3,6 +3,7 @@
 #pragma once
 
 #include "helm_hex.h"
+#include "uniform_table.h"
 
 namespace nir {
 
@@ -38,8 +39,8 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
   constexpr int BLOCK = D::BLOCK;
   constexpr int Q = D::Q, Q2 = D::Q2, NQ = D::NQ, M = D::M, E = D::E, PP = D::PP, PQ2 = D::PQ2, P2Q = D::P2Q,
                 SLAB = D::SLAB;
-  // uniform basis operands: B[i][p] = tabs[i*P + p], B'[i][p] = tabs[Q*P + i*P + p]
-  const HexTabView<P, T> tb{tabs};
+  // uniform basis operands: B[i][p] = tabs[i*P + p], B'[i][p] = tabs[Q*P + i*P + p], read
+  // one row per outer iteration through fresh_table
 
   const int t = threadIdx.x;
   const int el = t / Q2;
@@ -78,11 +79,12 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
       for (int r = 0; r < P; ++r) c[r] = L[s * PP + r];
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
+        const HexTabC<P, T> tk{fresh_table(tabs)};
         T v0 = T(0), v1 = T(0);
 #pragma unroll
         for (int r = 0; r < P; ++r) {
-          v0 += tb.B[k][r] * c[r];
-          v1 += tb.D[k][r] * c[r];
+          v0 += tk.B(k, r) * c[r];
+          v1 += tk.D(k, r) * c[r];
         }
         a0[k] = v0;
         a1[k] = v1;
@@ -110,12 +112,13 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
       }
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
+        const HexTabC<P, T> tk{fresh_table(tabs)};
         T v0 = T(0), v1 = T(0), v2 = T(0);
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-          v0 += tb.B[j][q] * av[q];
-          v1 += tb.D[j][q] * av[q];
-          v2 += tb.B[j][q] * bv[q];
+          v0 += tk.B(j, q) * av[q];
+          v1 += tk.D(j, q) * av[q];
+          v2 += tk.B(j, q) * bv[q];
         }
         c0[j] = v0;
         c1[j] = v1;
@@ -159,13 +162,14 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
     const T* g = helm + (valid ? e : 0) * (DEF ? 7 * NQ : 7);
 #pragma unroll(PF ? Q : IU)
     for (int i = 0; i < Q; ++i) {
+      const HexTabC<P, T> tk{fresh_table(tabs)};
       T u = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        u += tb.B[i][p] * C0[p];
-        d1 += tb.D[i][p] * C0[p];
-        d2 += tb.B[i][p] * C1[p];
-        d3 += tb.B[i][p] * C2[p];
+        u += tk.B(i, p) * C0[p];
+        d1 += tk.D(i, p) * C0[p];
+        d2 += tk.B(i, p) * C1[p];
+        d3 += tk.B(i, p) * C2[p];
       }
       const int n = i * Q2 + s;
       T G[7];
@@ -186,9 +190,10 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
       const T m = lambda * G[6] * u;
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        t0[p] += tb.B[i][p] * m + tb.D[i][p] * f1;
-        t1[p] += tb.B[i][p] * f2;
-        t2[p] += tb.B[i][p] * f3;
+        t0[p] += tk.B(i, p) * m;
+        t0[p] += tk.D(i, p) * f1;
+        t1[p] += tk.B(i, p) * f2;
+        t2[p] += tk.B(i, p) * f3;
       }
     }
     __syncthreads();
@@ -214,15 +219,16 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
           tv2[j] = L[2 * PQ2 + pb * Q2 + j * Q + kb];
         }
 #pragma unroll
-        for (int q = 0; q < P; ++q) {
-          T v0 = T(0), v1 = T(0);
+        for (int q = 0; q < P; ++q) s0[q] = s1[q] = T(0);
 #pragma unroll
-          for (int j = 0; j < Q; ++j) {
-            v0 += tb.B[j][q] * tv0[j] + tb.D[j][q] * tv1[j];
-            v1 += tb.B[j][q] * tv2[j];
+        for (int j = 0; j < Q; ++j) {
+          const HexTabC<P, T> tk{fresh_table(tabs)};
+#pragma unroll
+          for (int q = 0; q < P; ++q) {
+            s0[q] += tk.B(j, q) * tv0[j];
+            s0[q] += tk.D(j, q) * tv1[j];
+            s1[q] += tk.B(j, q) * tv2[j];
           }
-          s0[q] = v0;
-          s1[q] = v1;
         }
       }
     } else {
@@ -235,11 +241,15 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
           tv1[j] = L[PQ2 + pb * Q2 + j * Q + kb];
         }
 #pragma unroll
-        for (int q = 0; q < P; ++q) {
-          T v0 = T(0);
+        for (int q = 0; q < P; ++q) s0[q] = T(0);
 #pragma unroll
-          for (int j = 0; j < Q; ++j) v0 += tb.B[j][q] * tv0[j] + tb.D[j][q] * tv1[j];
-          s0[q] = v0;
+        for (int j = 0; j < Q; ++j) {
+          const HexTabC<P, T> tk{fresh_table(tabs)};
+#pragma unroll
+          for (int q = 0; q < P; ++q) {
+            s0[q] += tk.B(j, q) * tv0[j];
+            s0[q] += tk.D(j, q) * tv1[j];
+          }
         }
       }
       __syncthreads();
@@ -253,11 +263,12 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
 #pragma unroll
         for (int j = 0; j < Q; ++j) tv2[j] = L[pb * Q2 + j * Q + kb];
 #pragma unroll
-        for (int q = 0; q < P; ++q) {
-          T v1 = T(0);
+        for (int q = 0; q < P; ++q) s1[q] = T(0);
 #pragma unroll
-          for (int j = 0; j < Q; ++j) v1 += tb.B[j][q] * tv2[j];
-          s1[q] = v1;
+        for (int j = 0; j < Q; ++j) {
+          const HexTabC<P, T> tk{fresh_table(tabs)};
+#pragma unroll
+          for (int q = 0; q < P; ++q) s1[q] += tk.B(j, q) * tv2[j];
         }
       }
     }
@@ -281,11 +292,15 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
         sv1[k] = L[P2Q + s * Q + k];
       }
 #pragma unroll
-      for (int r = 0; r < P; ++r) {
-        T v = T(0);
+      for (int r = 0; r < P; ++r) yv[r] = T(0);
 #pragma unroll
-        for (int k = 0; k < Q; ++k) v += tb.B[k][r] * sv0[k] + tb.D[k][r] * sv1[k];
-        yv[r] = v;
+      for (int k = 0; k < Q; ++k) {
+        const HexTabC<P, T> tk{fresh_table(tabs)};
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+          yv[r] += tk.B(k, r) * sv0[k];
+          yv[r] += tk.D(k, r) * sv1[k];
+        }
       }
     }
     __syncthreads();

@@ -103,9 +103,11 @@ template <class T, int S, int P>
 __device__ __noinline__ void item_col(const MixedBatch<T>* __restrict__ B, int64_t first, T lambda, T* lds) {
   using C = MixedCol<S, P, T>;
   if (B->deformed)
-    helm_col_group<S, P, T, true, C::E, C::NSUB>(B->tb, B->x, B->y, B->helm, lambda, B->nelmt, first, lds);
+    helm_col_group<S, P, T, true, C::E, C::NSUB>(B->tb, B->pencil, B->x, B->y, B->helm, lambda, B->nelmt, first,
+                                                 lds);
   else
-    helm_col_group<S, P, T, false, C::E, C::NSUB>(B->tb, B->x, B->y, B->helm, lambda, B->nelmt, first, lds);
+    helm_col_group<S, P, T, false, C::E, C::NSUB>(B->tb, B->pencil, B->x, B->y, B->helm, lambda, B->nelmt, first,
+                                                  lds);
 }
 
 template <class T>

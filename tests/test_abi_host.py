@@ -165,8 +165,9 @@ def test_autotune_cache_roundtrip(tmp_path):
         assert nir.nir_get_helmholtz_variant(nir.HEX, 6, nir.F64) == nir.VARIANT_PENCIL
         # built-in per-order defaults of the hex kernel family
         assert nir.nir_get_helmholtz_variant(nir.HEX, 2, nir.F64) == nir.VARIANT_PENCIL_PF
-        assert nir.nir_get_helmholtz_variant(nir.HEX, 10, nir.F64) == nir.VARIANT_PENCIL_U2
-        assert nir.nir_get_helmholtz_variant(nir.HEX, 10, nir.F32) == nir.VARIANT_PENCIL_E1
+        assert nir.nir_get_helmholtz_variant(nir.HEX, 10, nir.F64) == nir.VARIANT_PENCIL_SPLIT
+        assert nir.nir_get_helmholtz_variant(nir.HEX, 9, nir.F64) == nir.VARIANT_PENCIL_U2
+        assert nir.nir_get_helmholtz_variant(nir.HEX, 9, nir.F32) == nir.VARIANT_PENCIL_SPLIT
         assert nir.nir_get_helmholtz_variant(nir.HEX, 8, nir.F64) == nir.VARIANT_PENCIL_SPLIT
         assert nir.nir_get_helmholtz_variant(nir.PRISM, 10, nir.F32) == nir.VARIANT_PENCIL
         nir.nir_autotune_load(path)
