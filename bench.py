@@ -329,6 +329,62 @@ def bench_collapsed(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_ops(args):
+    """The four elemental operators alone on hex_sin32 (32^3 curved hexes, per-point geometry), FP64,
+    P in {2,4,6,8,10}: GDoF/s and fraction of 8 TB/s against each operator's algorithmic bytes."""
+    import torch
+    from paper_2606_20917_amd import nir
+    dev = torch.device("cuda")
+    out = {"metric": "elemental operators GDoF/s and HBM roofline fraction", "unit": "GDoF/s",
+           "higher_is_better": True, "n_gpus": 1, "data": "synthetic", "dtype": "f64",
+           "config": {"workload": "hex_sin32: 32^3 = 32768 curved hexes (sin deformation 0.1), per-point geometry, "
+                                  "Q=P+1"}}
+    ps = [int(p) for p in args.ps.split(",")]
+    for P in ps:
+        from paper_2606_20917_amd import inputs
+        c = inputs.hex_sin32(P)
+        Q, ne = P + 1, len(c["verts"])
+        M, NQ = P ** 3, Q ** 3
+        basis = nir.Basis(nir.HEX, P)
+        b = nir.batch(nir.HEX, P, ne, nir.F64, 1)
+        dxi = torch.empty(ne, 9, NQ, dtype=torch.float64, device=dev)
+        jac = torch.empty(ne, NQ, dtype=torch.float64, device=dev)
+        nir.nir_geom_from_vertices(b, basis, torch.tensor(c["verts"], device=dev), nir.MAP_VERTEX_SIN, c["amp"],
+                                   dxi, jac, None, None)
+        g = nir.geom(dxi, jac, None)
+        coef = torch.tensor(c["coef"], device=dev)
+        phys = torch.empty(ne, NQ, dtype=torch.float64, device=dev)
+        nir.nir_bwd_trans(b, basis, coef, phys)
+        d = [torch.empty_like(phys) for _ in range(3)]
+        cout = torch.empty_like(coef)
+        ops = {
+            "bwd_trans": (lambda: nir.nir_bwd_trans(b, basis, coef, phys), 8 * (M + NQ)),
+            "iprod_wrt_base": (lambda: nir.nir_iprod_wrt_base(b, basis, g, phys, cout), 8 * (M + 2 * NQ)),
+            "phys_deriv": (lambda: nir.nir_phys_deriv(b, basis, g, phys, *d), 8 * 13 * NQ),
+            "iprod_wrt_deriv_base": (lambda: nir.nir_iprod_wrt_deriv_base(b, basis, g, *d, cout),
+                                     8 * (13 * NQ + M)),
+        }
+        res = {}
+        for name, (fn, byts) in ops.items():
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            res[name] = {"ms": round(ms, 4), "gdofs": round(ne * M / ms / 1e6, 3),
+                         "frac_hbm": round(ne * byts / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        out[f"P{P}"] = res
+        del dxi, jac, phys, d, coef, cout
+        torch.cuda.empty_cache()
+    out["value"] = out[f"P{ps[-1]}"]["bwd_trans"]["gdofs"]
+    print(json.dumps(out), flush=True)
+
+
 def bench_copy(args):
     """Plain device copy of 1 GiB (calibrates the HBM byte counters: read 1 GiB, write 1 GiB)."""
     import torch
@@ -360,7 +416,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variant", default="auto", choices=["auto", "generic", "pencil", "u2", "e1", "pf", "split"])
     ap.add_argument("--math", default="native", choices=["native", "f16split"])
-    ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k", "collapsed", "copy"])
+    ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k", "collapsed", "copy", "ops"])
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -379,6 +435,8 @@ def main():
         return bench_copy(args)
     if args.workload == "collapsed":
         return bench_collapsed(args)
+    if args.workload == "ops":
+        return bench_ops(args)
     ps = [int(p) for p in args.ps.split(",")]
     vid = {"auto": nir.VARIANT_AUTO, "generic": nir.VARIANT_GENERIC, "pencil": nir.VARIANT_PENCIL,
            "u2": nir.VARIANT_PENCIL_U2, "e1": nir.VARIANT_PENCIL_E1, "pf": nir.VARIANT_PENCIL_PF,

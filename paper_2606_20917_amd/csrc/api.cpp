@@ -365,6 +365,8 @@ nir_status nir_bwd_trans(const nir_batch* b, const nir_basis* basis, const void*
   a.in0 = coef;
   a.out0 = phys;
   a.nelmt = b->nelmt;
+  if (basis->shape == kHex)
+    return launch_ops_hex_pencil(basis, kOpBwd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
   return launch_generic(basis, kOpBwd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
 }
 
@@ -385,6 +387,8 @@ nir_status nir_iprod_wrt_base(const nir_batch* b, const nir_basis* basis, const 
   a.out0 = coef;
   a.jac = g->jac;
   a.nelmt = b->nelmt;
+  if (basis->shape == kHex)
+    return launch_ops_hex_pencil(basis, kOpIProd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
   return launch_generic(basis, kOpIProd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
 }
 
