@@ -418,6 +418,9 @@ nir_status nir_phys_deriv(const nir_batch* b, const nir_basis* basis, const nir_
   a.out2 = d2;
   a.dxi_dx = g->dxi_dx;
   a.nelmt = b->nelmt;
+  // hex pencils from P = 3 (at P = 2 the generic layout, 32 threads over 27 points, measured faster)
+  if (basis->shape == kHex && basis->P >= 3)
+    return launch_ops_hex_pencil(basis, kOpPhysDeriv, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
   return launch_generic(basis, kOpPhysDeriv, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
 }
 
@@ -446,6 +449,9 @@ nir_status nir_iprod_wrt_deriv_base(const nir_batch* b, const nir_basis* basis, 
   a.dxi_dx = g->dxi_dx;
   a.jac = g->jac;
   a.nelmt = b->nelmt;
+  // hex pencils from P = 3 (at P = 2 the generic layout, 32 threads over 27 points, measured faster)
+  if (basis->shape == kHex && basis->P >= 3)
+    return launch_ops_hex_pencil(basis, kOpIProdDeriv, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
   return launch_generic(basis, kOpIProdDeriv, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
 }
 

@@ -137,7 +137,7 @@ nir_status launch_geom(const nir_basis* b, int deformed, int64_t nelmt, const do
                        double amp, double* dxi_dx, double* jac, double* helm64, float* helm32,
                        hipStream_t s);
 
-// BwdTrans / IProductWRTBase on hexahedra with register pencils (ops_hex_pencil.hip)
+// the four elemental operators on hexahedra with register pencils (ops_hex_pencil.hip)
 nir_status launch_ops_hex_pencil(const nir_basis* b, int op, int dtype, int deformed, const OpArgs& a,
                                  hipStream_t s);
 // register-pencil fused Helmholtz apply of the collapsed shapes (helm_col_{prism,tet}.hip)
