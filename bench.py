@@ -232,7 +232,7 @@ def bench_mixed(args):
             (name, (lambda p: (lambda: nir.nir_mixed_helmholtz_apply(p, 1.0, xs, ys, stream)))(p))
             for name, p in plans.items()]
         for name, fn in fns:
-            for _ in range(max(1, args.warmup)):
+            for _ in range(max(10, args.warmup)):   # the plans tune on their first apply
                 fn()
             torch.cuda.synchronize()
             a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
