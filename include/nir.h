@@ -237,7 +237,9 @@ nir_status nir_mixed_plan_destroy(nir_mixed_plan* plan);
  * Structured n x n x n hex mesh on a cube, element e = ix + n*(iy + n*iz), every element with
  * the same orientation (the paper leaves assembly out of scope, section 2.1).  The 1-D global
  * index of mode p of element i is i(P-1) + {0 if p = 0; P-1 if p = 1; p-1 if p >= 2}, and
- * the 3-D index is gx + ng*(gy + ng*gz), ng = n(P-1)+1; shared modes need no sign change.
+ * the 3-D index is gz + ng*(gy + ng*gx), ng = n(P-1)+1 (z fastest, like r in the local mode
+ * order, so gather and scatter read and write mostly contiguous runs); shared modes need no
+ * sign change.
  * Number of global unknowns (n(P-1)+1)^3; -1 if invalid. */
 int64_t nir_c0_nglobal_hex(int32_t n, int32_t P);
 /* l2g [n^3][P^3] int32 local-to-global map: host version (host array) and device version

@@ -8,7 +8,8 @@ operator evaluations (section 4).  Reading used here:
   the same orientation, so shared modes match with no sign change;
 * 1-D global index of mode p in element ix:
       g = ix*(P-1) + (0 if p == 0, P-1 if p == 1, p-1 if p >= 2),
-  3-D index G = gx + ng*(gy + ng*gz), ng = n*(P-1) + 1;
+  3-D index G = gz + ng*(gy + ng*gx), ng = n*(P-1) + 1 (z fastest, like r in the
+  local mode order; any bijective numbering gives the same solution);
 * A = sum_e P_e^T H_e P_e (homogeneous Neumann problem, eq. (3) of the paper
   with the sign of eq. (5)), b = B^T W (3 pi^2 + lambda) u for the
   manufactured u = sin(pi x) cos(pi y) sin(pi z), i.e. -B^T W f with
@@ -38,7 +39,7 @@ def c0_map_closed_form(n, P):
                 for p in range(P):
                     for q in range(P):
                         for r in range(P):
-                            l2g[e, m] = g1(ix, p) + ng * (g1(iy, q) + ng * g1(iz, r))
+                            l2g[e, m] = g1(iz, r) + ng * (g1(iy, q) + ng * g1(ix, p))
                             m += 1
     return l2g, ng ** 3
 
@@ -52,7 +53,7 @@ def c0_map_closed_form_vec(n, P):
     m = np.arange(P ** 3)[None, :]
     ix, iy, iz = e % n, (e // n) % n, e // (n * n)
     p, q, r = m // (P * P), (m // P) % P, m % P
-    return (g1(ix, p) + ng * (g1(iy, q) + ng * g1(iz, r))).astype(np.int64), ng ** 3
+    return (g1(iz, r) + ng * (g1(iy, q) + ng * g1(ix, p))).astype(np.int64), ng ** 3
 
 
 def c0_map_by_matching(n, P):

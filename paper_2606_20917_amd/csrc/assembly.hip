@@ -34,7 +34,7 @@ __global__ void k_c0_map_hex(int n, int P, int32_t* __restrict__ l2g) {
     const int m = int(t - e * M);
     const int p = m / (P * P), q = (m / P) % P, r = m % P;
     const int64_t ix = e % n, iy = (e / n) % n, iz = e / (int64_t(n) * n);
-    l2g[t] = int32_t(c0_g1(ix, p, P) + ng * (c0_g1(iy, q, P) + ng * c0_g1(iz, r, P)));
+    l2g[t] = int32_t(c0_g1(iz, r, P) + ng * (c0_g1(iy, q, P) + ng * c0_g1(ix, p, P)));
   }
 }
 
@@ -46,11 +46,11 @@ __global__ void k_gather(const int32_t* __restrict__ l2g, const T* __restrict__ 
 
 // yg[G] = sum over the local entries of G in ascending (element, mode) order
 template <class T>
-__global__ void k_scatter(const int64_t* __restrict__ off, const int64_t* __restrict__ idx, const T* __restrict__ yl,
+__global__ void k_scatter(const int32_t* __restrict__ off, const int32_t* __restrict__ idx, const T* __restrict__ yl,
                           T* __restrict__ yg, int64_t ng) {
   for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < ng; g += int64_t(gridDim.x) * blockDim.x) {
     T s = T(0);
-    for (int64_t k = off[g]; k < off[g + 1]; ++k) s += yl[idx[k]];
+    for (int32_t k = off[g]; k < off[g + 1]; ++k) s += yl[idx[k]];
     yg[g] = s;
   }
 }
@@ -261,8 +261,8 @@ struct nir_assembly {
   int64_t nelmt = 0, nglobal = 0;
   int32_t M = 0;
   int32_t* l2g = nullptr;    // device [nelmt][M]
-  int64_t* off = nullptr;    // device [nglobal+1]
-  int64_t* idx = nullptr;    // device [nelmt*M]
+  int32_t* off = nullptr;    // device [nglobal+1]
+  int32_t* idx = nullptr;    // device [nelmt*M]
 };
 
 struct nir_cg_plan {
@@ -388,7 +388,7 @@ nir_status nir_c0_map_hex_host(int32_t n, int32_t P, int32_t* l2g) {
     const int64_t ix = e % n, iy = (e / n) % n, iz = e / (int64_t(n) * n);
     for (int m = 0; m < M; ++m) {
       const int p = m / (P * P), q = (m / P) % P, r = m % P;
-      l2g[e * M + m] = int32_t(c0_g1(ix, p, P) + ng * (c0_g1(iy, q, P) + ng * c0_g1(iz, r, P)));
+      l2g[e * M + m] = int32_t(c0_g1(iz, r, P) + ng * (c0_g1(iy, q, P) + ng * c0_g1(ix, p, P)));
     }
   }
   return NIR_OK;
@@ -409,10 +409,11 @@ nir_status nir_assembly_create(const int32_t* l2g, int64_t nelmt, int32_t M, int
   if (!l2g || nelmt < 1 || M < 1 || nglobal < 1 || nglobal > INT32_MAX)
     return fail(NIR_EINVAL, "invalid assembly arguments");
   const int64_t nl = nelmt * M;
+  if (nl > INT32_MAX) return fail(NIR_EINVAL, "%lld local entries exceed the int32 index range", (long long)nl);
   std::vector<int32_t> h(nl);
   NIR_TRYS(hip_check(hipMemcpy(h.data(), l2g, nl * 4, hipMemcpyDeviceToHost), "copy l2g"));
   // CSR of the inverse map by counting sort (stable: entries of a row in (element, mode) order)
-  std::vector<int64_t> off(nglobal + 1, 0), idx(nl);
+  std::vector<int32_t> off(nglobal + 1, 0), idx(nl);
   for (int64_t k = 0; k < nl; ++k) {
     if (h[k] < 0 || h[k] >= nglobal) return fail(NIR_EINVAL, "l2g entry %lld = %d outside [0, %lld)", (long long)k, h[k], (long long)nglobal);
     ++off[h[k] + 1];
@@ -422,8 +423,8 @@ nir_status nir_assembly_create(const int32_t* l2g, int64_t nelmt, int32_t M, int
     off[g + 1] += off[g];
   }
   {
-    std::vector<int64_t> pos(off.begin(), off.end() - 1);
-    for (int64_t k = 0; k < nl; ++k) idx[pos[h[k]]++] = k;
+    std::vector<int32_t> pos(off.begin(), off.end() - 1);
+    for (int64_t k = 0; k < nl; ++k) idx[pos[h[k]]++] = int32_t(k);
   }
   nir_assembly* a = new (std::nothrow) nir_assembly();
   if (!a) return fail(NIR_ENOMEM, "host allocation failed");
@@ -432,11 +433,11 @@ nir_status nir_assembly_create(const int32_t* l2g, int64_t nelmt, int32_t M, int
   a->nglobal = nglobal;
   nir_status st;
   if ((st = hip_check(hipMalloc(&a->l2g, nl * 4), "hipMalloc")) != NIR_OK ||
-      (st = hip_check(hipMalloc(&a->off, (nglobal + 1) * 8), "hipMalloc")) != NIR_OK ||
-      (st = hip_check(hipMalloc(&a->idx, nl * 8), "hipMalloc")) != NIR_OK ||
+      (st = hip_check(hipMalloc(&a->off, (nglobal + 1) * 4), "hipMalloc")) != NIR_OK ||
+      (st = hip_check(hipMalloc(&a->idx, nl * 4), "hipMalloc")) != NIR_OK ||
       (st = hip_check(hipMemcpy(a->l2g, l2g, nl * 4, hipMemcpyDeviceToDevice), "copy")) != NIR_OK ||
-      (st = hip_check(hipMemcpy(a->off, off.data(), (nglobal + 1) * 8, hipMemcpyHostToDevice), "copy")) != NIR_OK ||
-      (st = hip_check(hipMemcpy(a->idx, idx.data(), nl * 8, hipMemcpyHostToDevice), "copy")) != NIR_OK) {
+      (st = hip_check(hipMemcpy(a->off, off.data(), (nglobal + 1) * 4, hipMemcpyHostToDevice), "copy")) != NIR_OK ||
+      (st = hip_check(hipMemcpy(a->idx, idx.data(), nl * 4, hipMemcpyHostToDevice), "copy")) != NIR_OK) {
     nir_assembly_destroy(a);
     return st;
   }
