@@ -96,7 +96,7 @@ def cpu_baseline(cases, budget_s):
 # HBM bytes per launch of the dominant kernel measured with FETCH_SIZE / WRITE_SIZE (calibrated
 # by a plain 1 GiB copy: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), valid for that kernel variant while
 # the kernel sources hash to `src_sha`
-TRAFFIC = {"P": 10, "dtype": "f64", "variant": 6, "bytes": 2994028428, "src_sha": "84af3440bdb7be5d"}
+TRAFFIC = {"P": 10, "dtype": "f64", "variant": 8, "bytes": 3005361355, "src_sha": "92b9cb60f922239b"}
 
 
 def kernel_src_sha():
@@ -414,7 +414,8 @@ def main():
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--variant", default="auto", choices=["auto", "generic", "pencil", "u2", "e1", "pf", "split"])
+    ap.add_argument("--variant", default="auto",
+                    choices=["auto", "generic", "pencil", "u2", "e1", "pf", "split", "gp", "split_gp"])
     ap.add_argument("--math", default="native", choices=["native", "f16split"])
     ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k", "collapsed", "copy", "ops"])
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
@@ -440,7 +441,8 @@ def main():
     ps = [int(p) for p in args.ps.split(",")]
     vid = {"auto": nir.VARIANT_AUTO, "generic": nir.VARIANT_GENERIC, "pencil": nir.VARIANT_PENCIL,
            "u2": nir.VARIANT_PENCIL_U2, "e1": nir.VARIANT_PENCIL_E1, "pf": nir.VARIANT_PENCIL_PF,
-           "split": nir.VARIANT_PENCIL_SPLIT}[args.variant]
+           "split": nir.VARIANT_PENCIL_SPLIT, "gp": nir.VARIANT_PENCIL_GP,
+           "split_gp": nir.VARIANT_PENCIL_SPLIT_GP}[args.variant]
     for P in ps:
         nir.nir_set_helmholtz_variant(nir.HEX, P, nir.F64 if args.dtype == "f64" else nir.F32, vid)
     if args.math == "f16split" and args.dtype != "f32":

@@ -313,17 +313,23 @@ nir_status nir_cg_plan_destroy(nir_cg_plan* plan);
  *   NIR_VARIANT_PENCIL_SPLIT  hex pencil kernel whose planes between the direction-2 and
  *                          direction-1 sweeps pass through LDS two at a time (a third less LDS
  *                          per element, more blocks per CU at large P)
+ *   NIR_VARIANT_PENCIL_GP  hex pencil kernel whose point loop requests the next point plane's
+ *                          geometric factors while it computes the current one, the first plane
+ *                          during the forward sweeps (deeper HBM latency overlap; per-point
+ *                          factors only, otherwise the same as NIR_VARIANT_PENCIL)
+ *   NIR_VARIANT_PENCIL_SPLIT_GP  the same on NIR_VARIANT_PENCIL_SPLIT (whose third plane then
+ *                          stays in LDS during the point loop)
  * Setting a variant a shape does not support returns NIR_ENOTSUP. */
 typedef enum { NIR_VARIANT_AUTO = 0, NIR_VARIANT_GENERIC = 1, NIR_VARIANT_PENCIL = 2,
                NIR_VARIANT_PENCIL_U2 = 3, NIR_VARIANT_PENCIL_E1 = 4, NIR_VARIANT_PENCIL_PF = 5,
-               NIR_VARIANT_PENCIL_SPLIT = 6 } nir_variant;
+               NIR_VARIANT_PENCIL_SPLIT = 6, NIR_VARIANT_PENCIL_GP = 7, NIR_VARIANT_PENCIL_SPLIT_GP = 8 } nir_variant;
 nir_status nir_set_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype, int32_t variant);
 /* The variant a call with these parameters would run now (never NIR_VARIANT_AUTO); -1 if invalid. */
 int32_t nir_get_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype);
 /* Autotuner: times every variant applicable to the batch's shape on the caller's operands
  * (one warm-up and `reps` timed applies each, hipEvents on `stream`; coef_out is overwritten),
  * selects the fastest for (shape, P, dtype) and returns it in *chosen.  ms_per_variant, if not
- * NULL, receives the average time of each variant at index variant-1 (6 doubles; untried
+ * NULL, receives the average time of each variant at index variant-1 (8 doubles; untried
  * entries untouched).  Synchronises the stream. */
 nir_status nir_autotune_helmholtz(const nir_batch* batch, const nir_basis* basis, const nir_geom* geom,
                                   double lambda, const void* coef_in, void* coef_out, int32_t reps,

@@ -97,13 +97,21 @@ static int resolve_variant(int shape, int P, int dtype) {
   const int v = g_variant[shape][P][dtype].load(std::memory_order_relaxed);
   if (v != NIR_VARIANT_AUTO) return v;
   if (shape != kHex) return NIR_VARIANT_PENCIL;
-  // defaults from a sweep of all variants on MI355X (32^3 curved hexes, per-point factors):
-  // geometry prefetch wins for P <= 4, the plain pencil kernel in between, the two-plane
-  // exchange at P = 8 and 10 (and P = 9 in FP32), the two-fold point-loop unroll at P = 9 in FP64
-  if (P <= 4) return NIR_VARIANT_PENCIL_PF;
-  if (P <= 7) return NIR_VARIANT_PENCIL;
-  if (P == 9 && dtype == NIR_F64) return NIR_VARIANT_PENCIL_U2;
-  return NIR_VARIANT_PENCIL_SPLIT;
+  // defaults from a sweep of all variants on MI355X (32^3 curved hexes, per-point factors, the
+  // fastest of four interleaved rounds per variant): whole-pencil geometry prefetch for small P,
+  // the point loop one plane ahead on its factors (with the two-plane exchange where that frees
+  // the registers) for medium and large P, the twice-unrolled point loop at P=9 FP64 and P=3 FP32
+  static const int8_t def64[kMaxP + 1] = {0, 0, NIR_VARIANT_PENCIL_PF, NIR_VARIANT_PENCIL_PF,
+                                          NIR_VARIANT_PENCIL_PF, NIR_VARIANT_PENCIL_PF,
+                                          NIR_VARIANT_PENCIL_GP, NIR_VARIANT_PENCIL_SPLIT_GP,
+                                          NIR_VARIANT_PENCIL_GP, NIR_VARIANT_PENCIL_U2,
+                                          NIR_VARIANT_PENCIL_SPLIT_GP};
+  static const int8_t def32[kMaxP + 1] = {0, 0, NIR_VARIANT_PENCIL_PF, NIR_VARIANT_PENCIL_U2,
+                                          NIR_VARIANT_PENCIL_PF, NIR_VARIANT_PENCIL_PF,
+                                          NIR_VARIANT_PENCIL_SPLIT_GP, NIR_VARIANT_PENCIL_SPLIT_GP,
+                                          NIR_VARIANT_PENCIL_SPLIT, NIR_VARIANT_PENCIL_SPLIT,
+                                          NIR_VARIANT_PENCIL_SPLIT};
+  return dtype == NIR_F64 ? def64[P] : def32[P];
 }
 
 // the fused Helmholtz apply with the selected kernel variant (native contractions)
@@ -117,6 +125,8 @@ nir_status launch_helm_auto(const nir_basis* basis, int dtype, int deformed, con
   if (v == NIR_VARIANT_PENCIL_E1) return launch_helm_hex_pencil(basis, dtype, deformed, a, s, 2);
   if (v == NIR_VARIANT_PENCIL_PF) return launch_helm_hex_pencil(basis, dtype, deformed, a, s, 3);
   if (v == NIR_VARIANT_PENCIL_SPLIT) return launch_helm_hex_pencil(basis, dtype, deformed, a, s, 4);
+  if (v == NIR_VARIANT_PENCIL_GP) return launch_helm_hex_pencil(basis, dtype, deformed, a, s, 5);
+  if (v == NIR_VARIANT_PENCIL_SPLIT_GP) return launch_helm_hex_pencil(basis, dtype, deformed, a, s, 6);
   return launch_generic(basis, kOpHelm, dtype, deformed, a, s);
 }
 
@@ -502,11 +512,12 @@ nir_status nir_autotune_helmholtz(const nir_batch* b, const nir_basis* basis, co
   a.nelmt = b->nelmt;
   std::atomic<int>& slot = g_variant[b->shape][b->nmodes][b->dtype];
   const int before = slot.load();
-  const int cands_hex[6] = {NIR_VARIANT_GENERIC, NIR_VARIANT_PENCIL, NIR_VARIANT_PENCIL_U2, NIR_VARIANT_PENCIL_E1,
-                            NIR_VARIANT_PENCIL_PF, NIR_VARIANT_PENCIL_SPLIT};
+  const int cands_hex[8] = {NIR_VARIANT_GENERIC, NIR_VARIANT_PENCIL,    NIR_VARIANT_PENCIL_U2,
+                            NIR_VARIANT_PENCIL_E1, NIR_VARIANT_PENCIL_PF, NIR_VARIANT_PENCIL_SPLIT,
+                            NIR_VARIANT_PENCIL_GP, NIR_VARIANT_PENCIL_SPLIT_GP};
   const int cands_other[2] = {NIR_VARIANT_GENERIC, NIR_VARIANT_PENCIL};
   const int* cands = b->shape == kHex ? cands_hex : cands_other;
-  const int nc = b->shape == kHex ? 6 : 2;
+  const int nc = b->shape == kHex ? 8 : 2;
   hipEvent_t e0, e1;
   NIR_TRY(hip_check(hipEventCreate(&e0), "event"));
   NIR_TRY(hip_check(hipEventCreate(&e1), "event"));
@@ -587,7 +598,7 @@ nir_status nir_autotune_load(const char* path) {
                     &e.d, &e.v) != 4)
       return fail(NIR_EINVAL, "%s: malformed entry at offset %zu", path, ob);
     if (e.s < 0 || e.s > 2 || e.P < kMinP || e.P > kMaxP || e.d < 0 || e.d > 1 || e.v < NIR_VARIANT_AUTO ||
-        e.v > NIR_VARIANT_PENCIL_SPLIT || (e.s != kHex && e.v > NIR_VARIANT_PENCIL))
+        e.v > NIR_VARIANT_PENCIL_SPLIT_GP || (e.s != kHex && e.v > NIR_VARIANT_PENCIL))
       return fail(NIR_EINVAL, "%s: invalid entry at offset %zu", path, ob);
     ents.push_back(e);
     pos = cb + 1;
@@ -599,7 +610,8 @@ nir_status nir_autotune_load(const char* path) {
 nir_status nir_set_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype, int32_t variant) {
   if (shape < kHex || shape > kTet || P < kMinP || P > kMaxP || (dtype != NIR_F64 && dtype != NIR_F32))
     return fail(NIR_EINVAL, "invalid (shape %d, P %d, dtype %d)", shape, P, dtype);
-  if (variant < NIR_VARIANT_AUTO || variant > NIR_VARIANT_PENCIL_SPLIT) return fail(NIR_EINVAL, "invalid variant %d", variant);
+  if (variant < NIR_VARIANT_AUTO || variant > NIR_VARIANT_PENCIL_SPLIT_GP)
+    return fail(NIR_EINVAL, "invalid variant %d", variant);
   if (variant > NIR_VARIANT_PENCIL && shape != kHex)
     return fail(NIR_ENOTSUP, "variant %d is a hex kernel (prism and tet have GENERIC and PENCIL)", variant);
   g_variant[shape][P][dtype].store(variant, std::memory_order_relaxed);

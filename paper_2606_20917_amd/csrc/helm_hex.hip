@@ -43,25 +43,26 @@ constexpr int hex_waves_target() {
   return !TP ? 1 : (waves < 1 ? 1 : (waves > 3 ? 3 : waves));
 }
 
-template <int P, class T, bool DEF, int IU, int E, bool PF, bool TP>
+template <int P, class T, bool DEF, int IU, int E, bool PF, bool TP, bool GP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(hex_waves_target<P, T, E, TP>())))
 k_helm_hex(const T* __restrict__ tabs, const T* __restrict__ x,
                                                   T* __restrict__ y, const T* __restrict__ helm,
                                                   const T* __restrict__ wq, T lambda, int64_t nelmt) {
   // one element group per block (no grid-stride loop: the basis operands stay short-lived)
   __shared__ T lds[HexPencilDims<P, T, E, TP>::LDS];
-  helm_hex_group<P, T, DEF, IU, E, PF, TP>(tabs, x, y, helm, wq, lambda, nelmt, int64_t(blockIdx.x) * E, lds);
+  helm_hex_group<P, T, DEF, IU, E, PF, TP, GP>(tabs, x, y, helm, wq, lambda, nelmt, int64_t(blockIdx.x) * E, lds);
 }
 
 // variant: 0 = E_max elements per 256-thread block, 1 = same with the point loop unrolled twice,
 // 2 = one element per block (smaller LDS footprint, more blocks per CU), 3 = geometry prefetch,
-// 4 = planes exchanged two at a time
-template <int P, class T, bool DEF, int IU, int E, bool PF, bool TP = false>
+// 4 = planes exchanged two at a time, 5 = 0 with the point planes' factors requested one plane
+// ahead, 6 = 4 with the same (both are 0 and 4 for affine elements, which stream no factors)
+template <int P, class T, bool DEF, int IU, int E, bool PF, bool TP = false, bool GP = false>
 static void launch_cfg(const T* tb, const T* x, T* y, const T* helm, const T* wq, T lam, int64_t nelmt,
                        hipStream_t s) {
   using D = HexPencilDims<P, T, E, TP>;
   const int64_t nb = (nelmt + E - 1) / E;
-  hipLaunchKernelGGL((k_helm_hex<P, T, DEF, IU, E, PF, TP>), dim3(static_cast<unsigned>(nb)), dim3(D::BLOCK), 0, s,
+  hipLaunchKernelGGL((k_helm_hex<P, T, DEF, IU, E, PF, TP, GP>), dim3(static_cast<unsigned>(nb)), dim3(D::BLOCK), 0, s,
                      tb, x, y, helm, wq, lam, nelmt);
 }
 
@@ -74,6 +75,14 @@ static void launch_var(int variant, const T* tb, const T* x, T* y, const T* helm
     case 2: launch_cfg<P, T, DEF, 1, 1, false>(tb, x, y, helm, wq, lam, nelmt, s); break;
     case 3: launch_cfg<P, T, DEF, 1, EMAX, true>(tb, x, y, helm, wq, lam, nelmt, s); break;
     case 4: launch_cfg<P, T, DEF, 1, EMAX, false, true>(tb, x, y, helm, wq, lam, nelmt, s); break;
+    case 5:
+      if constexpr (DEF) launch_cfg<P, T, DEF, 1, EMAX, false, false, true>(tb, x, y, helm, wq, lam, nelmt, s);
+      else launch_cfg<P, T, DEF, 1, EMAX, false>(tb, x, y, helm, wq, lam, nelmt, s);
+      break;
+    case 6:
+      if constexpr (DEF) launch_cfg<P, T, DEF, 1, EMAX, false, true, true>(tb, x, y, helm, wq, lam, nelmt, s);
+      else launch_cfg<P, T, DEF, 1, EMAX, false, true>(tb, x, y, helm, wq, lam, nelmt, s);
+      break;
     default: launch_cfg<P, T, DEF, 1, EMAX, false>(tb, x, y, helm, wq, lam, nelmt, s); break;
   }
 }

@@ -29,9 +29,13 @@ struct HexPencilDims {
 // geometric factors of the thread's pencil into registers before the first sweep, so their
 // HBM latency overlaps the forward sweeps (small P only: 7Q values per thread).  TP exchanges
 // the planes of the direction-2/direction-1 sweeps two at a time (two more barriers each way,
-// a third less LDS per element: more blocks per CU at large P).
+// a third less LDS per element: more blocks per CU at large P).  GP (deformed geometry, point
+// loop not unrolled) requests the factors of point plane i+1 when plane i is consumed, so each
+// plane's loads are in flight for a whole iteration of the point loop instead of being waited
+// for at once; plane 0 is requested after the coefficients are staged and stays in flight
+// through the forward sweeps (barriers do not wait for outstanding loads).
 template <int P, class T, bool DEF, int IU = 1, int E_ = 256 / ((P + 1) * (P + 1)), bool PF = false,
-          bool TP = false>
+          bool TP = false, bool GP = false>
 __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const T* __restrict__ x, T* __restrict__ y,
                                                const T* __restrict__ helm, const T* __restrict__ wq, T lambda,
                                                int64_t nelmt, int64_t base, T* __restrict__ lds) {
@@ -70,6 +74,17 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
       lds[e2 * SLAB + pq * PP + r] = x[base * M + f];
     }
     __syncthreads();
+
+    // ---- GP: the factors of point plane 0, in flight through the forward sweeps.  Lanes of
+    // an element past the end read element 0's factors (in bounds, finite) unmasked: a mask
+    // would wait for the loads where it is applied, and those lanes' results are never stored
+    constexpr bool G1 = GP && DEF && !PF && IU == 1;
+    const T* g = helm + (valid ? e : 0) * (DEF ? 7 * NQ : 7);
+    T gn[G1 ? 7 : 1];
+    if constexpr (G1) {
+#pragma unroll
+      for (int c = 0; c < 7; ++c) gn[c] = g[c * NQ + s];
+    }
 
     // ---- A: pencils (p,q), r -> k
     T a0[Q], a1[Q];
@@ -146,6 +161,9 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
       C1[p] = L[PQ2 + p * Q2 + s];
       if (!TP) C2[p] = L[2 * PQ2 + p * Q2 + s];
     }
+    // with GP, the two-plane variant leaves the third plane in LDS through the point loop and
+    // reads it there (P values per point plane), which frees 2P registers for the prefetch
+    constexpr bool C2L = TP && G1;
     if (TP) {   // third plane through the space of the first
       __syncthreads();
       if (act && s < P * Q) {
@@ -153,47 +171,92 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
         for (int j = 0; j < Q; ++j) L[pb * Q2 + j * Q + kb] = c2[j];
       }
       __syncthreads();
+      if constexpr (!C2L) {
 #pragma unroll
-      for (int p = 0; p < P; ++p) C2[p] = L[p * Q2 + s];
+        for (int p = 0; p < P; ++p) C2[p] = L[p * Q2 + s];
+      }
     }
     T t0[P], t1[P], t2[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) t0[p] = t1[p] = t2[p] = T(0);
-    const T* g = helm + (valid ? e : 0) * (DEF ? 7 * NQ : 7);
+    if constexpr (G1) {
+      // rotated point loop: [pointwise i, request plane i+1, backward i, forward i+1], so that
+      // the next plane's factors are in flight through a backward and a forward step, and a copy
+      // of them at the loop back edge (if the register allocator makes one) waits only where
+      // they are needed anyway
+      auto fwd = [&](const HexTabC<P, T>& tk, int i, T& u, T& d1, T& d2, T& d3) {
+        u = d1 = d2 = d3 = T(0);
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          u += tk.B(i, p) * C0[p];
+          d1 += tk.D(i, p) * C0[p];
+          d2 += tk.B(i, p) * C1[p];
+          d3 += tk.B(i, p) * (C2L ? L[p * Q2 + s] : C2[p]);
+        }
+      };
+      T u, d1, d2, d3;
+      fwd(HexTabC<P, T>{fresh_table(tabs)}, 0, u, d1, d2, d3);
+#pragma unroll 1
+      for (int i = 0; i < Q; ++i) {
+        const HexTabC<P, T> tk{fresh_table(tabs)};
+        T f1 = gn[0] * d1 + gn[1] * d2 + gn[2] * d3;
+        T f2 = gn[1] * d1 + gn[3] * d2 + gn[4] * d3;
+        T f3 = gn[2] * d1 + gn[4] * d2 + gn[5] * d3;
+        T m = lambda * gn[6] * u;
+        // the next plane's factors into the same registers; the last iteration requests its
+        // own plane again (a cache hit) instead of branching.  The empty asm makes the
+        // pointwise products complete before the requests, so that the old factors are dead
+        // and their registers can take the new ones
+        asm volatile("" : "+v"(f1), "+v"(f2), "+v"(f3), "+v"(m));
+        __builtin_amdgcn_sched_barrier(0);
+        const int inext = i + 1 < Q ? i + 1 : i;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) gn[c] = g[c * NQ + inext * Q2 + s];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          t0[p] += tk.B(i, p) * m;
+          t0[p] += tk.D(i, p) * f1;
+          t1[p] += tk.B(i, p) * f2;
+          t2[p] += tk.B(i, p) * f3;
+        }
+        if (i + 1 < Q) fwd(HexTabC<P, T>{fresh_table(tabs)}, i + 1, u, d1, d2, d3);
+      }
+    } else {
 #pragma unroll(PF ? Q : IU)
-    for (int i = 0; i < Q; ++i) {
-      const HexTabC<P, T> tk{fresh_table(tabs)};
-      T u = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
+      for (int i = 0; i < Q; ++i) {
+        const HexTabC<P, T> tk{fresh_table(tabs)};
+        T u = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        u += tk.B(i, p) * C0[p];
-        d1 += tk.D(i, p) * C0[p];
-        d2 += tk.B(i, p) * C1[p];
-        d3 += tk.B(i, p) * C2[p];
-      }
-      const int n = i * Q2 + s;
-      T G[7];
-      if (PF) {
+        for (int p = 0; p < P; ++p) {
+          u += tk.B(i, p) * C0[p];
+          d1 += tk.D(i, p) * C0[p];
+          d2 += tk.B(i, p) * C1[p];
+          d3 += tk.B(i, p) * C2[p];
+        }
+        const int n = i * Q2 + s;
+        T G[7];
+        if (PF) {
 #pragma unroll
-        for (int c = 0; c < 7; ++c) G[c] = pre[i * 7 + c];
-      } else if (DEF) {
+          for (int c = 0; c < 7; ++c) G[c] = pre[i * 7 + c];
+        } else if (DEF) {
 #pragma unroll
-        for (int c = 0; c < 7; ++c) G[c] = valid ? g[c * NQ + n] : T(0);
-      } else {
-        const T w = wq[n];
+          for (int c = 0; c < 7; ++c) G[c] = valid ? g[c * NQ + n] : T(0);
+        } else {
+          const T w = wq[n];
 #pragma unroll
-        for (int c = 0; c < 7; ++c) G[c] = valid ? g[c] * w : T(0);
-      }
-      const T f1 = G[0] * d1 + G[1] * d2 + G[2] * d3;
-      const T f2 = G[1] * d1 + G[3] * d2 + G[4] * d3;
-      const T f3 = G[2] * d1 + G[4] * d2 + G[5] * d3;
-      const T m = lambda * G[6] * u;
+          for (int c = 0; c < 7; ++c) G[c] = valid ? g[c] * w : T(0);
+        }
+        const T f1 = G[0] * d1 + G[1] * d2 + G[2] * d3;
+        const T f2 = G[1] * d1 + G[3] * d2 + G[4] * d3;
+        const T f3 = G[2] * d1 + G[4] * d2 + G[5] * d3;
+        const T m = lambda * G[6] * u;
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        t0[p] += tk.B(i, p) * m;
-        t0[p] += tk.D(i, p) * f1;
-        t1[p] += tk.B(i, p) * f2;
-        t2[p] += tk.B(i, p) * f3;
+        for (int p = 0; p < P; ++p) {
+          t0[p] += tk.B(i, p) * m;
+          t0[p] += tk.D(i, p) * f1;
+          t1[p] += tk.B(i, p) * f2;
+          t2[p] += tk.B(i, p) * f3;
+        }
       }
     }
     __syncthreads();
