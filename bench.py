@@ -415,7 +415,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variant", default="auto",
-                    choices=["auto", "generic", "pencil", "u2", "e1", "pf", "split", "gp", "split_gp"])
+                    choices=["auto", "generic", "pencil", "u2", "e1", "pf", "split", "gp", "split_gp", "eo",
+                             "eo_split"])
     ap.add_argument("--math", default="native", choices=["native", "f16split"])
     ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k", "collapsed", "copy", "ops"])
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
@@ -442,7 +443,8 @@ def main():
     vid = {"auto": nir.VARIANT_AUTO, "generic": nir.VARIANT_GENERIC, "pencil": nir.VARIANT_PENCIL,
            "u2": nir.VARIANT_PENCIL_U2, "e1": nir.VARIANT_PENCIL_E1, "pf": nir.VARIANT_PENCIL_PF,
            "split": nir.VARIANT_PENCIL_SPLIT, "gp": nir.VARIANT_PENCIL_GP,
-           "split_gp": nir.VARIANT_PENCIL_SPLIT_GP}[args.variant]
+           "split_gp": nir.VARIANT_PENCIL_SPLIT_GP, "eo": nir.VARIANT_PENCIL_EO,
+           "eo_split": nir.VARIANT_PENCIL_EO_SPLIT}[args.variant]
     for P in ps:
         nir.nir_set_helmholtz_variant(nir.HEX, P, nir.F64 if args.dtype == "f64" else nir.F32, vid)
     if args.math == "f16split" and args.dtype != "f32":

@@ -98,19 +98,14 @@ static int resolve_variant(int shape, int P, int dtype) {
   if (v != NIR_VARIANT_AUTO) return v;
   if (shape != kHex) return NIR_VARIANT_PENCIL;
   // defaults from a sweep of all variants on MI355X (32^3 curved hexes, per-point factors, the
-  // fastest of four interleaved rounds per variant): whole-pencil geometry prefetch for small P,
-  // the point loop one plane ahead on its factors (with the two-plane exchange where that frees
-  // the registers) for medium and large P, the twice-unrolled point loop at P=9 FP64 and P=3 FP32
-  static const int8_t def64[kMaxP + 1] = {0, 0, NIR_VARIANT_PENCIL_PF, NIR_VARIANT_PENCIL_PF,
-                                          NIR_VARIANT_PENCIL_PF, NIR_VARIANT_PENCIL_PF,
-                                          NIR_VARIANT_PENCIL_GP, NIR_VARIANT_PENCIL_SPLIT_GP,
-                                          NIR_VARIANT_PENCIL_GP, NIR_VARIANT_PENCIL_U2,
-                                          NIR_VARIANT_PENCIL_SPLIT_GP};
-  static const int8_t def32[kMaxP + 1] = {0, 0, NIR_VARIANT_PENCIL_PF, NIR_VARIANT_PENCIL_U2,
-                                          NIR_VARIANT_PENCIL_PF, NIR_VARIANT_PENCIL_PF,
-                                          NIR_VARIANT_PENCIL_SPLIT_GP, NIR_VARIANT_PENCIL_SPLIT_GP,
-                                          NIR_VARIANT_PENCIL_SPLIT, NIR_VARIANT_PENCIL_SPLIT,
-                                          NIR_VARIANT_PENCIL_SPLIT};
+  // fastest of four interleaved rounds per variant): the even-odd folded kernels where the
+  // contractions weigh (P = 2, 3 and 7..9 in FP64, all but P = 4, 5 in FP32), whole-pencil
+  // geometry prefetch at P = 4, 5, the point loop one plane ahead at P = 6 and, with the
+  // two-plane exchange, at P = 10 in FP64 (where the folded kernel does not fit 3 waves per SIMD)
+  constexpr int8_t PF = NIR_VARIANT_PENCIL_PF, GP = NIR_VARIANT_PENCIL_GP, SGP = NIR_VARIANT_PENCIL_SPLIT_GP,
+                   EO = NIR_VARIANT_PENCIL_EO, EOS = NIR_VARIANT_PENCIL_EO_SPLIT;
+  static const int8_t def64[kMaxP + 1] = {0, 0, EO, EO, PF, PF, GP, EO, EOS, EOS, SGP};
+  static const int8_t def32[kMaxP + 1] = {0, 0, EO, EO, PF, PF, EO, EOS, EOS, EO, EO};
   return dtype == NIR_F64 ? def64[P] : def32[P];
 }
 
@@ -127,6 +122,8 @@ nir_status launch_helm_auto(const nir_basis* basis, int dtype, int deformed, con
   if (v == NIR_VARIANT_PENCIL_SPLIT) return launch_helm_hex_pencil(basis, dtype, deformed, a, s, 4);
   if (v == NIR_VARIANT_PENCIL_GP) return launch_helm_hex_pencil(basis, dtype, deformed, a, s, 5);
   if (v == NIR_VARIANT_PENCIL_SPLIT_GP) return launch_helm_hex_pencil(basis, dtype, deformed, a, s, 6);
+  if (v == NIR_VARIANT_PENCIL_EO) return launch_helm_hex_eo(basis, dtype, deformed, a, s, false);
+  if (v == NIR_VARIANT_PENCIL_EO_SPLIT) return launch_helm_hex_eo(basis, dtype, deformed, a, s, true);
   return launch_generic(basis, kOpHelm, dtype, deformed, a, s);
 }
 
@@ -271,13 +268,37 @@ nir_status nir_basis_create(int32_t shape, int32_t P, int32_t Q, nir_basis** out
   fill(b->t32, d32);
   {
     const int Q = b->Q, P = b->P;
-    std::vector<double> p64(2 * Q * P);
-    std::vector<float> p32(2 * Q * P);
+    // [point][mode] direction-1 rows, then (hexahedra) the even-odd folded rows: for the point
+    // pair (h, Q-1-h), h < ceil(Q/2), 2P values ((B0+B1)/2, B2, B4, .. | (B0-B1)/2, B3, B5, ..
+    // | the same of B'); the Gauss-Lobatto points are symmetric and psi^a_0(-z) = psi^a_1(z),
+    // psi^a_p(-z) = (-1)^p psi^a_p(z) for p >= 2.  On a middle point (odd Q) the odd half of B
+    // and the even half of B' vanish and are stored as exact zeros.
+    const int H = (Q + 1) / 2, NE = 1 + (P - 1) / 2, neo = b->shape == kHex && Q == P + 1 ? H * 2 * P : 0;
+    std::vector<double> p64(2 * Q * P + neo);
+    std::vector<float> p32(p64.size());
+    auto B = [&](int i, int p) { return b->host.T1[p * Q + i]; };
+    auto Dd = [&](int i, int p) { return b->host.dT1[p * Q + i]; };
     for (int i = 0; i < Q; ++i)
       for (int p = 0; p < P; ++p) {
-        p64[i * P + p] = b->host.T1[p * Q + i];
-        p64[Q * P + i * P + p] = b->host.dT1[p * Q + i];
+        p64[i * P + p] = B(i, p);
+        p64[Q * P + i * P + p] = Dd(i, p);
       }
+    for (int h = 0; neo && h < H; ++h) {
+      double* r = p64.data() + 2 * Q * P + h * 2 * P;
+      const bool mid = 2 * h == Q - 1;
+      r[0] = 0.5 * (B(h, 0) + B(h, 1));
+      r[NE] = mid ? 0.0 : 0.5 * (B(h, 0) - B(h, 1));
+      r[P] = mid ? 0.0 : 0.5 * (Dd(h, 0) + Dd(h, 1));
+      r[P + NE] = 0.5 * (Dd(h, 0) - Dd(h, 1));
+      for (int k = 1; k < NE; ++k) {
+        r[k] = B(h, 2 * k);
+        r[P + k] = mid ? 0.0 : Dd(h, 2 * k);
+      }
+      for (int k = 1; k < P - NE; ++k) {
+        r[NE + k] = mid ? 0.0 : B(h, 2 * k + 1);
+        r[P + NE + k] = Dd(h, 2 * k + 1);
+      }
+    }
     for (size_t k = 0; k < p64.size(); ++k) p32[k] = float(p64[k]);
     const size_t nb64 = p64.size() * 8, nb32 = p32.size() * 4;
     if ((st = hip_check(hipMalloc(&b->devpencil, nb64 + nb32), "hipMalloc tables")) != NIR_OK ||
@@ -289,6 +310,10 @@ nir_status nir_basis_create(int32_t shape, int32_t P, int32_t Q, nir_basis** out
     }
     b->pencil64 = static_cast<const double*>(b->devpencil);
     b->pencil32 = reinterpret_cast<const float*>(static_cast<const char*>(b->devpencil) + nb64);
+    if (neo) {
+      b->eo64 = b->pencil64 + 2 * Q * P;
+      b->eo32 = b->pencil32 + 2 * Q * P;
+    }
     // MFMA basis tiles: 0 = B^T [r][k], 1 = B'^T [r][k], 2 = B [i][p], 3 = B' [i][p]
     std::vector<float> mt(4 * 256, 0.f), ms(4, 1.f);
     for (int p = 0; p < P; ++p)
@@ -512,12 +537,13 @@ nir_status nir_autotune_helmholtz(const nir_batch* b, const nir_basis* basis, co
   a.nelmt = b->nelmt;
   std::atomic<int>& slot = g_variant[b->shape][b->nmodes][b->dtype];
   const int before = slot.load();
-  const int cands_hex[8] = {NIR_VARIANT_GENERIC, NIR_VARIANT_PENCIL,    NIR_VARIANT_PENCIL_U2,
-                            NIR_VARIANT_PENCIL_E1, NIR_VARIANT_PENCIL_PF, NIR_VARIANT_PENCIL_SPLIT,
-                            NIR_VARIANT_PENCIL_GP, NIR_VARIANT_PENCIL_SPLIT_GP};
+  const int cands_hex[10] = {NIR_VARIANT_GENERIC,   NIR_VARIANT_PENCIL,    NIR_VARIANT_PENCIL_U2,
+                             NIR_VARIANT_PENCIL_E1, NIR_VARIANT_PENCIL_PF, NIR_VARIANT_PENCIL_SPLIT,
+                             NIR_VARIANT_PENCIL_GP, NIR_VARIANT_PENCIL_SPLIT_GP, NIR_VARIANT_PENCIL_EO,
+                             NIR_VARIANT_PENCIL_EO_SPLIT};
   const int cands_other[2] = {NIR_VARIANT_GENERIC, NIR_VARIANT_PENCIL};
   const int* cands = b->shape == kHex ? cands_hex : cands_other;
-  const int nc = b->shape == kHex ? 8 : 2;
+  const int nc = b->shape == kHex ? 10 : 2;
   hipEvent_t e0, e1;
   NIR_TRY(hip_check(hipEventCreate(&e0), "event"));
   NIR_TRY(hip_check(hipEventCreate(&e1), "event"));
@@ -598,7 +624,7 @@ nir_status nir_autotune_load(const char* path) {
                     &e.d, &e.v) != 4)
       return fail(NIR_EINVAL, "%s: malformed entry at offset %zu", path, ob);
     if (e.s < 0 || e.s > 2 || e.P < kMinP || e.P > kMaxP || e.d < 0 || e.d > 1 || e.v < NIR_VARIANT_AUTO ||
-        e.v > NIR_VARIANT_PENCIL_SPLIT_GP || (e.s != kHex && e.v > NIR_VARIANT_PENCIL))
+        e.v > NIR_VARIANT_PENCIL_EO_SPLIT || (e.s != kHex && e.v > NIR_VARIANT_PENCIL))
       return fail(NIR_EINVAL, "%s: invalid entry at offset %zu", path, ob);
     ents.push_back(e);
     pos = cb + 1;
@@ -610,7 +636,7 @@ nir_status nir_autotune_load(const char* path) {
 nir_status nir_set_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype, int32_t variant) {
   if (shape < kHex || shape > kTet || P < kMinP || P > kMaxP || (dtype != NIR_F64 && dtype != NIR_F32))
     return fail(NIR_EINVAL, "invalid (shape %d, P %d, dtype %d)", shape, P, dtype);
-  if (variant < NIR_VARIANT_AUTO || variant > NIR_VARIANT_PENCIL_SPLIT_GP)
+  if (variant < NIR_VARIANT_AUTO || variant > NIR_VARIANT_PENCIL_EO_SPLIT)
     return fail(NIR_EINVAL, "invalid variant %d", variant);
   if (variant > NIR_VARIANT_PENCIL && shape != kHex)
     return fail(NIR_ENOTSUP, "variant %d is a hex kernel (prism and tet have GENERIC and PENCIL)", variant);

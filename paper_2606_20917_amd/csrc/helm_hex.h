@@ -33,8 +33,11 @@ struct HexTabView {
 
 // variant: 0 = E_max elements per 256-thread block, 1 = point loop unrolled twice,
 // 2 = one element per block, 3 = geometry prefetched into registers, 4 = planes exchanged two
-// at a time
+// at a time, 5 = 0 and 6 = 4 with the point loop one plane ahead on its factors
 nir_status launch_helm_hex_pencil(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s,
                                   int variant = 0);
+// the even-odd folded variant (helm_hex_eo.hip); split: planes exchanged two at a time
+nir_status launch_helm_hex_eo(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s,
+                              bool split);
 
 }  // namespace nir

@@ -31,18 +31,6 @@
 
 namespace nir {
 
-// Register budget of the two-plane variant: the waves per SIMD that its LDS footprint allows
-// (160 KiB per CU, four SIMDs), capped at 3 (512 / 3 VGPRs), so that registers do not hold the
-// occupancy below what the smaller slab allows.  The other variants keep the compiler's own
-// choice (measured faster: at P >= 8 forcing the budget lowered their throughput).
-template <int P, class T, int E, bool TP>
-constexpr int hex_waves_target() {
-  using D = HexPencilDims<P, T, E, TP>;
-  const int blocks = (160 * 1024) / (D::LDS * int(sizeof(T)));
-  const int waves = blocks * (D::BLOCK / 64) / 4;
-  return !TP ? 1 : (waves < 1 ? 1 : (waves > 3 ? 3 : waves));
-}
-
 template <int P, class T, bool DEF, int IU, int E, bool PF, bool TP, bool GP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(hex_waves_target<P, T, E, TP>())))
 k_helm_hex(const T* __restrict__ tabs, const T* __restrict__ x,

@@ -22,6 +22,18 @@ struct HexPencilDims {
   static constexpr int LDS = E * SLAB;                    // values of T per block
 };
 
+// Register budget of the two-plane variant: the waves per SIMD that its LDS footprint allows
+// (160 KiB per CU, four SIMDs), capped at 3 (512 / 3 VGPRs), so that registers do not hold the
+// occupancy below what the smaller slab allows.  The other variants keep the compiler's own
+// choice (measured faster: at P >= 8 forcing the budget lowered their throughput).
+template <int P, class T, int E, bool TP>
+constexpr int hex_waves_target() {
+  using D = HexPencilDims<P, T, E, TP>;
+  const int blocks = (160 * 1024) / (D::LDS * int(sizeof(T)));
+  const int waves = blocks * (D::BLOCK / 64) / 4;
+  return !TP ? 1 : (waves < 1 ? 1 : (waves > 3 ? 3 : waves));
+}
+
 // One group of up to E elements starting at `base`, on a block of HexPencilDims<P,T,E>::BLOCK
 // threads; `lds` holds HexPencilDims<P,T,E>::LDS values.  Every thread of the block must call it (it synchronises).
 // IU is the unroll factor of the streamed point loop (register pressure vs. loads in flight);

@@ -84,6 +84,9 @@ struct nir_basis {
   void* devpencil = nullptr;
   const double* pencil64 = nullptr;
   const float* pencil32 = nullptr;
+  // hexahedra: the same rows folded by even-odd symmetry ([ceil(Q/2)][2P], inside devpencil)
+  const double* eo64 = nullptr;
+  const float* eo32 = nullptr;
   // zero-padded [16][16] FP32 basis tiles for the MFMA kernels (B^T, B'^T, B, B') and their
   // power-of-two split scales
   float* mfma_tabs = nullptr;

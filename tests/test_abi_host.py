@@ -165,12 +165,12 @@ def test_autotune_cache_roundtrip(tmp_path):
         assert nir.nir_get_helmholtz_variant(nir.HEX, 6, nir.F64) == nir.VARIANT_PENCIL_GP
         # built-in per-order defaults of the hex kernel family
         H, F64, F32 = nir.HEX, nir.F64, nir.F32
-        PF, U2, GP = nir.VARIANT_PENCIL_PF, nir.VARIANT_PENCIL_U2, nir.VARIANT_PENCIL_GP
-        SP, SGP = nir.VARIANT_PENCIL_SPLIT, nir.VARIANT_PENCIL_SPLIT_GP
+        PF, GP, SGP = nir.VARIANT_PENCIL_PF, nir.VARIANT_PENCIL_GP, nir.VARIANT_PENCIL_SPLIT_GP
+        EO, EOS = nir.VARIANT_PENCIL_EO, nir.VARIANT_PENCIL_EO_SPLIT
         assert [nir.nir_get_helmholtz_variant(H, P, F64) for P in range(2, 11)] == \
-            [PF, PF, PF, PF, GP, SGP, GP, U2, SGP]
+            [EO, EO, PF, PF, GP, EO, EOS, EOS, SGP]
         assert [nir.nir_get_helmholtz_variant(H, P, F32) for P in range(2, 11)] == \
-            [PF, U2, PF, PF, SGP, SGP, SP, SP, SP]
+            [EO, EO, PF, PF, EO, EOS, EOS, EO, EO]
         assert nir.nir_get_helmholtz_variant(nir.PRISM, 10, nir.F32) == nir.VARIANT_PENCIL
         nir.nir_autotune_load(path)
         assert nir.nir_get_helmholtz_variant(nir.HEX, 6, nir.F64) == nir.VARIANT_PENCIL_U2
@@ -179,7 +179,7 @@ def test_autotune_cache_roundtrip(tmp_path):
         bad = tmp_path / "bad.json"
         for txt in ("not json", '{"format": "libnir-autotune-1", "entries": [{"shape": 0, "P": 6}]}',
                     '{"format": "libnir-autotune-1", "entries": [{"shape": 1, "P": 6, "dtype": 0, "variant": 3}]}',
-                    '{"format": "libnir-autotune-1", "entries": [{"shape": 0, "P": 6, "dtype": 0, "variant": 9}]}',
+                    '{"format": "libnir-autotune-1", "entries": [{"shape": 0, "P": 6, "dtype": 0, "variant": 11}]}',
                     '{"format": "libnir-autotune-1", "entries": [{"shape": 0, "P": 12, "dtype": 0, "variant": 1}'):
             bad.write_text(txt)
             with pytest.raises(nir.NirError):
@@ -190,9 +190,9 @@ def test_autotune_cache_roundtrip(tmp_path):
         with pytest.raises(nir.NirError):   # the unrolled/E1/prefetch pencil kernels are hex only
             nir.nir_set_helmholtz_variant(nir.PRISM, 4, nir.F64, nir.VARIANT_PENCIL_U2)
         with pytest.raises(nir.NirError):
-            nir.nir_set_helmholtz_variant(nir.TET, 4, nir.F64, nir.VARIANT_PENCIL_SPLIT_GP)
+            nir.nir_set_helmholtz_variant(nir.TET, 4, nir.F64, nir.VARIANT_PENCIL_EO)
         with pytest.raises(nir.NirError):
-            nir.nir_set_helmholtz_variant(nir.HEX, 4, nir.F64, nir.VARIANT_PENCIL_SPLIT_GP + 1)
+            nir.nir_set_helmholtz_variant(nir.HEX, 4, nir.F64, nir.VARIANT_PENCIL_EO_SPLIT + 1)
         nir.nir_set_helmholtz_variant(nir.PRISM, 4, nir.F64, nir.VARIANT_PENCIL)
     finally:
         for s, P, d in ((nir.HEX, 6, nir.F64), (nir.TET, 3, nir.F32), (nir.PRISM, 4, nir.F64)):
