@@ -385,6 +385,78 @@ def bench_ops(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_fields(args):
+    """Three fields per element (nir_helmholtz_apply_fields, [element][field][mode]) on hex_sin32, FP64
+    and FP32, against three single-field applies of the same data: GDoF/s (DoF = fields x modes x
+    elements) and fraction of 8 TB/s against the multi-field apply's algorithmic bytes (the factors
+    once per element, three fields in and out)."""
+    import torch
+    from paper_2606_20917_amd import inputs, nir
+    dev = torch.device("cuda")
+    NF = 3
+    out = {"metric": "multi-field Helmholtz apply GDoF/s and HBM roofline fraction", "unit": "GDoF/s",
+           "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "hex_sin32 x 3 fields: 32^3 = 32768 curved hexes (sin deformation 0.1), "
+                                  "per-point factors shared by the fields, lambda=1, Q=P+1", "nfields": NF}}
+    ps = [int(p) for p in args.ps.split(",")]
+    for dt in ("f64", "f32"):
+        res = {}
+        for P in ps:
+            c = inputs.hex_sin32(P)
+            Q, ne, M = P + 1, len(c["verts"]), P ** 3
+            s = 8 if dt == "f64" else 4
+            tdt = torch.float64 if dt == "f64" else torch.float32
+            basis = nir.Basis(nir.HEX, P)
+            helm = torch.empty(ne, 7, Q ** 3, dtype=torch.float64, device=dev)
+            helm32 = torch.empty(ne, 7, Q ** 3, dtype=torch.float32, device=dev) if dt == "f32" else None
+            nir.nir_geom_from_vertices(nir.batch(nir.HEX, P, ne, nir.F64, 1), basis, torch.tensor(c["verts"], device=dev),
+                                       nir.MAP_VERTEX_SIN, c["amp"], None, None, helm, helm32)
+            h = helm if dt == "f64" else helm32
+            b = nir.batch(nir.HEX, P, ne, nir.F64 if dt == "f64" else nir.F32, 1)
+            rng = np.random.default_rng(P)
+            x = torch.tensor(rng.uniform(-1, 1, (ne, NF, M)), dtype=tdt, device=dev)
+            byts = s * ne * (7 * Q ** 3 + 2 * NF * M)
+            nsets = max(1, math.ceil(ROTATE_BYTES / byts))
+            sets = [(h, x, torch.empty_like(x))] + [(h.clone(), x.clone(), torch.empty_like(x))
+                                                    for _ in range(nsets - 1)]
+            xs = [torch.empty(NF, ne, M, dtype=tdt, device=dev) for _ in range(nsets)]   # field-major copies
+            for k in range(nsets):
+                xs[k].copy_(sets[k][1].permute(1, 0, 2))
+            ys = [torch.empty_like(xs[0][0]) for _ in range(NF)]
+
+            def multi(k):
+                hk, xk, yk = sets[k % nsets]
+                nir.nir_helmholtz_apply_fields(b, basis, nir.geom(None, None, hk), 1.0, NF, xk, yk)
+
+            def single(k):
+                hk = sets[k % nsets][0]
+                for f in range(NF):
+                    nir.nir_helmholtz_apply(b, basis, nir.geom(None, None, hk), 1.0, xs[k % nsets][f], ys[f])
+
+            r = {}
+            for name, fn in (("fields", multi), ("single_x3", single)):
+                for k in range(args.warmup):
+                    fn(k)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for k in range(args.steps):
+                    fn(k)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / args.steps
+                r[name] = {"ms": round(ms, 4), "gdofs": round(NF * ne * M / ms / 1e6, 3),
+                           "frac_hbm": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4)}
+            r["speedup"] = round(r["single_x3"]["ms"] / r["fields"]["ms"], 3)
+            r["rotating_sets"] = nsets
+            res[f"P{P}"] = r
+            del sets, xs, ys, helm, helm32, h, x
+            torch.cuda.empty_cache()
+        out[dt] = res
+    out["value"] = out["f64"][f"P{ps[-1]}"]["fields"]["gdofs"]
+    print(json.dumps(out), flush=True)
+
+
 def bench_copy(args):
     """Plain device copy of 1 GiB (calibrates the HBM byte counters: read 1 GiB, write 1 GiB)."""
     import torch
@@ -418,7 +490,7 @@ def main():
                     choices=["auto", "generic", "pencil", "u2", "e1", "pf", "split", "gp", "split_gp", "eo",
                              "eo_split"])
     ap.add_argument("--math", default="native", choices=["native", "f16split"])
-    ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k", "collapsed", "copy", "ops"])
+    ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k", "collapsed", "copy", "ops", "fields"])
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -439,6 +511,8 @@ def main():
         return bench_collapsed(args)
     if args.workload == "ops":
         return bench_ops(args)
+    if args.workload == "fields":
+        return bench_fields(args)
     ps = [int(p) for p in args.ps.split(",")]
     vid = {"auto": nir.VARIANT_AUTO, "generic": nir.VARIANT_GENERIC, "pencil": nir.VARIANT_PENCIL,
            "u2": nir.VARIANT_PENCIL_U2, "e1": nir.VARIANT_PENCIL_E1, "pf": nir.VARIANT_PENCIL_PF,

@@ -192,6 +192,19 @@ nir_status nir_iprod_wrt_deriv_base(const nir_batch* batch, const nir_basis* bas
 nir_status nir_helmholtz_apply(const nir_batch* batch, const nir_basis* basis, const nir_geom* geom,
                                double lambda, const void* coef_in, void* coef_out, void* stream);
 
+/* Several fields per element (the block type's field count and its (fields, elements,
+ * coefficients) layout permutation, section 3.1.1): y_f = (L + lambda M) u^_f for f < nfields,
+ * every field of an element under that element's geometry.  coef_in and coef_out are
+ * [nelmt][nfields][M] (fields interleaved per element), distinct and non-overlapping; geom as for
+ * nir_helmholtz_apply (one set of factors per element, not per field).  The kernels run the
+ * fields of an element in one workgroup, so its factors are read from HBM once.
+ * nfields = 1 is nir_helmholtz_apply.  nfields = 2 or 3 needs hexahedra, Q = P + 1 and
+ * NIR_MATH_NATIVE (FP64 or FP32); other field counts, shapes or math modes return NIR_ENOTSUP,
+ * nfields < 1 NIR_EINVAL. */
+nir_status nir_helmholtz_apply_fields(const nir_batch* batch, const nir_basis* basis, const nir_geom* geom,
+                                      double lambda, int32_t nfields, const void* coef_in, void* coef_out,
+                                      void* stream);
+
 /* ------------------------------------------------------------------ mixed batches
  * The fused Helmholtz apply over several batches of different shape and order (a mixed mesh
  * grouped by (shape, P)), replayed from one hipGraph.  Two strategies:

@@ -516,6 +516,33 @@ nir_status nir_helmholtz_apply(const nir_batch* b, const nir_basis* basis, const
   return launch_helm_auto(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
 }
 
+nir_status nir_helmholtz_apply_fields(const nir_batch* b, const nir_basis* basis, const nir_geom* g, double lambda,
+                                      int32_t nfields, const void* coef_in, void* coef_out, void* stream) {
+  NIR_TRY(check_batch(b, basis));
+  if (nfields < 1) return fail(NIR_EINVAL, "nfields must be >= 1 (got %d)", nfields);
+  if (nfields == 1) return nir_helmholtz_apply(b, basis, g, lambda, coef_in, coef_out, stream);
+  if (nfields > 3) return fail(NIR_ENOTSUP, "nfields=%d: the multi-field apply takes at most 3 fields", nfields);
+  if (b->shape != kHex) return fail(NIR_ENOTSUP, "the multi-field apply is implemented for hexahedra");
+  NIR_TRY(native_only(b));
+  if (b->nelmt == 0) return NIR_OK;
+  NIR_TRY(check_geom(b, g, false, false, true));
+  NIR_TRY(check_ptr(b, coef_in, "coef_in"));
+  NIR_TRY(check_ptr(b, coef_out, "coef_out"));
+  const size_t es = elem_size(b), n = size_t(b->nelmt), nq = size_t(basis->Q) * basis->Q * basis->Q;
+  const size_t cb = n * size_t(nfields) * basis->M * es;
+  if (overlap(coef_out, cb, coef_in, cb)) return fail(NIR_EINVAL, "coef_in and coef_out overlap");
+  if (overlap(coef_out, cb, g->helm, n * 7 * (b->deformed ? nq : 1) * es))
+    return fail(NIR_EINVAL, "coef_out overlaps the geometry");
+  if (!(lambda == lambda)) return fail(NIR_EINVAL, "lambda is NaN");
+  OpArgs a{};
+  a.in0 = coef_in;
+  a.out0 = coef_out;
+  a.helm = g->helm;
+  a.lambda = lambda;
+  a.nelmt = b->nelmt;
+  return launch_helm_hex_fields(basis, b->dtype, b->deformed, nfields, a, static_cast<hipStream_t>(stream));
+}
+
 nir_status nir_autotune_helmholtz(const nir_batch* b, const nir_basis* basis, const nir_geom* g, double lambda,
                                   const void* coef_in, void* coef_out, int32_t reps, int32_t* chosen,
                                   double* ms_per_variant, void* stream) {

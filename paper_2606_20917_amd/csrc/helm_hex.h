@@ -36,6 +36,9 @@ struct HexTabView {
 // at a time, 5 = 0 and 6 = 4 with the point loop one plane ahead on its factors
 nir_status launch_helm_hex_pencil(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s,
                                   int variant = 0);
+// several fields per element, [nelmt][nfields][M] (helm_hex_mf.hip); a.nelmt counts elements
+nir_status launch_helm_hex_fields(const nir_basis* b, int dtype, int deformed, int nfields, const OpArgs& a,
+                                  hipStream_t s);
 // the even-odd folded variant (helm_hex_eo.hip); split: planes exchanged two at a time
 nir_status launch_helm_hex_eo(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s,
                               bool split);

@@ -41,13 +41,15 @@ constexpr int hex_waves_target() {
 // geometric factors of the thread's pencil into registers before the first sweep, so their
 // HBM latency overlaps the forward sweeps (small P only: 7Q values per thread).  TP exchanges
 // the planes of the direction-2/direction-1 sweeps two at a time (two more barriers each way,
-// a third less LDS per element: more blocks per CU at large P).  GP (deformed geometry, point
+// a third less LDS per element: more blocks per CU at large P).  NF > 1: the group's "elements"
+// are NF fields of each element ([element][field][mode] coefficients), which share the element's
+// geometric factors (element index = group element / NF).  GP (deformed geometry, point
 // loop not unrolled) requests the factors of point plane i+1 when plane i is consumed, so each
 // plane's loads are in flight for a whole iteration of the point loop instead of being waited
 // for at once; plane 0 is requested after the coefficients are staged and stays in flight
 // through the forward sweeps (barriers do not wait for outstanding loads).
 template <int P, class T, bool DEF, int IU = 1, int E_ = 256 / ((P + 1) * (P + 1)), bool PF = false,
-          bool TP = false, bool GP = false>
+          bool TP = false, bool GP = false, int NF = 1>
 __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const T* __restrict__ x, T* __restrict__ y,
                                                const T* __restrict__ helm, const T* __restrict__ wq, T lambda,
                                                int64_t nelmt, int64_t base, T* __restrict__ lds) {
@@ -72,7 +74,7 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
     // ---- geometry prefetch (PF): the thread's pencil points (i, j, k), i = 0..Q-1
     T pre[PF ? 7 * Q : 1];
     if (PF) {
-      const T* gp = helm + (valid ? e : 0) * (DEF ? 7 * NQ : 7);
+      const T* gp = helm + (valid ? e / NF : 0) * (DEF ? 7 * NQ : 7);
 #pragma unroll
       for (int i = 0; i < Q; ++i)
 #pragma unroll
@@ -91,7 +93,7 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
     // an element past the end read element 0's factors (in bounds, finite) unmasked: a mask
     // would wait for the loads where it is applied, and those lanes' results are never stored
     constexpr bool G1 = GP && DEF && !PF && IU == 1;
-    const T* g = helm + (valid ? e : 0) * (DEF ? 7 * NQ : 7);
+    const T* g = helm + (valid ? e / NF : 0) * (DEF ? 7 * NQ : 7);
     T gn[G1 ? 7 : 1];
     if constexpr (G1) {
 #pragma unroll

@@ -129,8 +129,10 @@ __device__ __forceinline__ void eo_pair(const T* v, int h, bool mid, T& sv, T& a
 // threads; `lds` holds HexPencilDims<P,T,E,TP>::LDS values; every thread of the block calls it.
 // `tabs` is the folded table (EoDims<P>::H rows of 2P values).  TP and GP as in helm_hex_group:
 // TP exchanges the direction-2/direction-1 planes two at a time, GP (deformed geometry) runs the
-// point-pair loop one pair ahead on its factors.
-template <int P, class T, bool DEF, int E_ = 256 / ((P + 1) * (P + 1)), bool TP = false, bool GP = false>
+// point-pair loop one pair ahead on its factors.  NF > 1: the group's "elements" are NF fields of
+// each element, which share its geometric factors (as in helm_hex_group).
+template <int P, class T, bool DEF, int E_ = 256 / ((P + 1) * (P + 1)), bool TP = false, bool GP = false,
+          int NF = 1>
 __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, const T* __restrict__ x,
                                                   T* __restrict__ y, const T* __restrict__ helm,
                                                   const T* __restrict__ wq, T lambda, int64_t nelmt, int64_t base,
@@ -162,7 +164,7 @@ __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, co
   // ---- GP: the factors of point planes 0 and Q-1 (the first pair), in flight through the
   // forward sweeps; lanes past the batch end read element 0's factors (never stored)
   constexpr bool G1 = GP && DEF;
-  const T* g = helm + (valid ? e : 0) * (DEF ? 7 * NQ : 7);
+  const T* g = helm + (valid ? e / NF : 0) * (DEF ? 7 * NQ : 7);
   T gn[G1 ? 14 : 1];
   if constexpr (G1) {
 #pragma unroll

@@ -1,0 +1,129 @@
+"""GPU parity of the multi-field Helmholtz apply (nir_helmholtz_apply_fields) against the oracle.
+
+Coefficients are [element][field][mode]; every field of every element is compared with the
+oracle's dense Helmholtz matrix of its element (the fields share the element's geometry).
+Small meshes cover both parities of Q, element counts that leave a partial workgroup, affine
+and curved elements, FP64 and FP32; the full hex_sin32 size is checked on a seeded sample of
+elements (the oracle evaluates only those).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import geometry as og, operators as op
+from paper_2606_20917_amd import inputs, nir
+from tests.gpu_util import elem_relerr, small_mesh
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+TOL64, TOL32 = 1e-12, 2e-4   # FP32: the Helmholtz bar of the single-field tests
+
+
+def _apply_fields(verts, amp, deformed, P, nf, dtype, coef, lam):
+    ne, Q = len(verts), P + 1
+    npts = Q ** 3 if deformed else 1
+    basis = nir.Basis(nir.HEX, P)
+    helm = torch.empty(ne, 7, npts, dtype=torch.float64, device=DEV)
+    helm32 = torch.empty(ne, 7, npts, dtype=torch.float32, device=DEV)
+    nir.nir_geom_from_vertices(nir.batch(nir.HEX, P, ne, nir.F64, deformed), basis,
+                               torch.tensor(verts, device=DEV), nir.MAP_VERTEX_SIN if amp else nir.MAP_VERTEX,
+                               amp, None, None, helm, helm32)
+    tdt = torch.float64 if dtype == nir.F64 else torch.float32
+    x = torch.tensor(coef, dtype=tdt, device=DEV)
+    y = torch.full_like(x, float("nan"))
+    nir.nir_helmholtz_apply_fields(nir.batch(nir.HEX, P, ne, dtype, deformed), basis,
+                                   nir.geom(None, None, helm if dtype == nir.F64 else helm32), lam, nf, x, y)
+    torch.cuda.synchronize()
+    return y.double().cpu().numpy()
+
+
+def _reference(verts, amp, P, coef, lam):
+    tab = op.Tables(nir.HEX, P, P + 1)
+    geo = og.Geometry(nir.HEX, P + 1, verts, amp)
+    return np.stack([op.helmholtz(tab, geo, lam, coef[:, f]) for f in range(coef.shape[1])], axis=1)
+
+
+@pytest.mark.parametrize("dtype", [nir.F64, nir.F32])
+@pytest.mark.parametrize("nf", [2, 3])
+@pytest.mark.parametrize("P", [2, 3, 4, 5, 6, 7, 8, 9, 10])
+def test_fields_match_oracle(P, nf, dtype):
+    # 27 curved hexes: a partial last workgroup for every group size here
+    verts = small_mesh(nir.HEX, 3, 300 + P, 0.05, 0.1)
+    rng = np.random.default_rng(50 + P + 10 * nf)
+    coef = rng.uniform(-1, 1, (len(verts), nf, P ** 3))
+    if dtype == nir.F32:
+        coef = coef.astype(np.float32).astype(np.float64)
+    lam = 0.75
+    y = _apply_fields(verts, 0.1, 1, P, nf, dtype, coef, lam)
+    ref = _reference(verts, 0.1, P, coef, lam)
+    tol = TOL64 if dtype == nir.F64 else TOL32
+    for f in range(nf):
+        assert elem_relerr(y[:, f], ref[:, f]) <= tol, (P, nf, dtype, f)
+
+
+@pytest.mark.parametrize("P", [3, 6, 10])
+def test_fields_affine(P):
+    verts = small_mesh(nir.HEX, 2, 400 + P, 0.0, 0.0)   # parallelepipeds: per-element factors
+    rng = np.random.default_rng(P)
+    coef = rng.uniform(-1, 1, (len(verts), 3, P ** 3))
+    y = _apply_fields(verts, 0.0, 0, P, 3, nir.F64, coef, 1.0)
+    ref = _reference(verts, 0.0, P, coef, 1.0)
+    for f in range(3):
+        assert elem_relerr(y[:, f], ref[:, f]) <= TOL64
+
+
+def test_fields_equal_single_field_apply():
+    """Each field equals the single-field apply of that field alone (same element, same factors)."""
+    P, nf = 7, 3
+    verts = small_mesh(nir.HEX, 3, 77, 0.05, 0.1)
+    ne, Q = len(verts), P + 1
+    rng = np.random.default_rng(7)
+    coef = rng.uniform(-1, 1, (ne, nf, P ** 3))
+    y = _apply_fields(verts, 0.1, 1, P, nf, nir.F64, coef, 1.0)
+    basis = nir.Basis(nir.HEX, P)
+    helm = torch.empty(ne, 7, Q ** 3, dtype=torch.float64, device=DEV)
+    nir.nir_geom_from_vertices(nir.batch(nir.HEX, P, ne, nir.F64, 1), basis, torch.tensor(verts, device=DEV),
+                               nir.MAP_VERTEX_SIN, 0.1, None, None, helm, None)
+    for f in range(nf):
+        x = torch.tensor(np.ascontiguousarray(coef[:, f]), device=DEV)
+        y1 = torch.empty_like(x)
+        nir.nir_helmholtz_apply(nir.batch(nir.HEX, P, ne, nir.F64, 1), basis, nir.geom(None, None, helm), 1.0, x, y1)
+        torch.cuda.synchronize()
+        assert elem_relerr(y[:, f], y1.cpu().numpy()) <= 1e-14
+
+
+def test_fields_validation():
+    P, ne = 4, 5
+    basis = nir.Basis(nir.HEX, P)
+    helm = torch.zeros(ne, 7, 125, dtype=torch.float64, device=DEV)
+    x = torch.zeros(ne, 3, 64, dtype=torch.float64, device=DEV)
+    y = torch.empty_like(x)
+    b = nir.batch(nir.HEX, P, ne, nir.F64, 1)
+    g = nir.geom(None, None, helm)
+    with pytest.raises(nir.NirError):
+        nir.nir_helmholtz_apply_fields(b, basis, g, 1.0, 0, x, y)
+    with pytest.raises(nir.NirError):
+        nir.nir_helmholtz_apply_fields(b, basis, g, 1.0, 4, x, y)
+    with pytest.raises(nir.NirError):   # overlapping in/out
+        nir.nir_helmholtz_apply_fields(b, basis, g, 1.0, 3, x, x)
+    nir.nir_helmholtz_apply_fields(nir.batch(nir.HEX, P, 0, nir.F64, 1), basis, g, 1.0, 3, x, y)   # empty: no-op
+
+
+@pytest.mark.parametrize("dtype", [nir.F64, nir.F32])
+@pytest.mark.parametrize("P", [4, 10])
+def test_fields_hex_sin32_full(P, dtype):
+    """32^3 curved hexes, 3 fields, lambda = 1: seeded sample of elements against the oracle."""
+    c = inputs.hex_sin32(P)
+    ne = len(c["verts"])
+    rng = np.random.default_rng(900 + P)
+    coef = rng.uniform(-1, 1, (ne, 3, P ** 3))
+    if dtype == nir.F32:
+        coef = coef.astype(np.float32).astype(np.float64)
+    y = _apply_fields(c["verts"], c["amp"], 1, P, 3, dtype, coef, 1.0)
+    assert np.isfinite(y).all()
+    sel = np.unique(np.concatenate([np.random.default_rng(P).choice(ne, 24, replace=False), [0, ne - 1]]))
+    ref = _reference(c["verts"][sel], c["amp"], P, coef[sel], 1.0)
+    tol = TOL64 if dtype == nir.F64 else TOL32
+    for f in range(3):
+        assert elem_relerr(y[sel, f], ref[:, f]) <= tol, (P, dtype, f)
