@@ -457,6 +457,74 @@ def bench_fields(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_trilinear(args):
+    """Trilinear hexes (32^3, the jitter recipe of the small workload): the Helmholtz apply with the
+    geometric factors formed in the kernel from the 8 vertices (nir_helmholtz_apply_trilinear)
+    against the default apply streaming the same factors precomputed by nir_geom_from_vertices.
+    GDoF/s; HBM fraction of each against its own algorithmic bytes."""
+    import torch
+    from paper_2606_20917_amd import inputs, nir
+    dev = torch.device("cuda")
+    out = {"metric": "Helmholtz apply GDoF/s, factors formed in the kernel vs streamed", "unit": "GDoF/s",
+           "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "hex_tri32: 32^3 = 32768 trilinear hexes (interior vertices jittered by "
+                                  "U(-0.05h, 0.05h)), lambda=1, Q=P+1"}}
+    ps = [int(p) for p in args.ps.split(",")]
+    for dt in ("f64", "f32"):
+        res = {}
+        for P in ps:
+            c = inputs.hex_tri32(P)
+            Q, ne, M = P + 1, len(c["verts"]), P ** 3
+            s = 8 if dt == "f64" else 4
+            tdt = torch.float64 if dt == "f64" else torch.float32
+            basis = nir.Basis(nir.HEX, P)
+            b = nir.batch(nir.HEX, P, ne, nir.F64 if dt == "f64" else nir.F32, 1)
+            v = torch.tensor(c["verts"], dtype=torch.float64, device=dev)
+            helm = torch.empty(ne, 7, Q ** 3, dtype=torch.float64, device=dev)
+            helm32 = torch.empty(ne, 7, Q ** 3, dtype=torch.float32, device=dev) if dt == "f32" else None
+            nir.nir_geom_from_vertices(nir.batch(nir.HEX, P, ne, nir.F64, 1), basis, v, nir.MAP_VERTEX, 0.0, None,
+                                       None, helm, helm32)
+            h = helm if dt == "f64" else helm32
+            x = torch.tensor(c["coef"], dtype=tdt, device=dev)
+            b_tri, b_str = ne * (2 * M * s + 24 * 8), ne * (2 * M + 7 * Q ** 3) * s
+            n_tri = max(1, math.ceil(ROTATE_BYTES / b_tri))
+            n_str = max(1, math.ceil(ROTATE_BYTES / b_str))
+            tri_sets = [(v, x, torch.empty_like(x))] + [(v.clone(), x.clone(), torch.empty_like(x))
+                                                        for _ in range(n_tri - 1)]
+            str_sets = [(h, x, torch.empty_like(x))] + [(h.clone(), x.clone(), torch.empty_like(x))
+                                                        for _ in range(n_str - 1)]
+
+            def tri(k):
+                vk, xk, yk = tri_sets[k % n_tri]
+                nir.nir_helmholtz_apply_trilinear(b, basis, vk, 1.0, xk, yk)
+
+            def streamed(k):
+                hk, xk, yk = str_sets[k % n_str]
+                nir.nir_helmholtz_apply(b, basis, nir.geom(None, None, hk), 1.0, xk, yk)
+
+            r = {}
+            for name, fn, byts, ns in (("in_kernel", tri, b_tri, n_tri), ("streamed", streamed, b_str, n_str)):
+                for k in range(args.warmup):
+                    fn(k)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for k in range(args.steps):
+                    fn(k)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / args.steps
+                r[name] = {"ms": round(ms, 4), "gdofs": round(ne * M / ms / 1e6, 3),
+                           "frac_hbm": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4), "rotating_sets": ns}
+            r["speedup"] = round(r["streamed"]["ms"] / r["in_kernel"]["ms"], 3)
+            res[f"P{P}"] = r
+            del tri_sets, str_sets, helm, helm32, h, x, v
+            torch.cuda.empty_cache()
+        out[dt] = res
+    out["value"] = out["f64"][f"P{ps[-1]}"]["in_kernel"]["gdofs"]
+    print(json.dumps(out), flush=True)
+
+
 def bench_copy(args):
     """Plain device copy of 1 GiB (calibrates the HBM byte counters: read 1 GiB, write 1 GiB)."""
     import torch
@@ -490,7 +558,7 @@ def main():
                     choices=["auto", "generic", "pencil", "u2", "e1", "pf", "split", "gp", "split_gp", "eo",
                              "eo_split"])
     ap.add_argument("--math", default="native", choices=["native", "f16split"])
-    ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k", "collapsed", "copy", "ops", "fields"])
+    ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k", "collapsed", "copy", "ops", "fields", "trilinear"])
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -513,6 +581,8 @@ def main():
         return bench_ops(args)
     if args.workload == "fields":
         return bench_fields(args)
+    if args.workload == "trilinear":
+        return bench_trilinear(args)
     ps = [int(p) for p in args.ps.split(",")]
     vid = {"auto": nir.VARIANT_AUTO, "generic": nir.VARIANT_GENERIC, "pencil": nir.VARIANT_PENCIL,
            "u2": nir.VARIANT_PENCIL_U2, "e1": nir.VARIANT_PENCIL_E1, "pf": nir.VARIANT_PENCIL_PF,

@@ -205,6 +205,20 @@ nir_status nir_helmholtz_apply_fields(const nir_batch* batch, const nir_basis* b
                                       double lambda, int32_t nfields, const void* coef_in, void* coef_out,
                                       void* stream);
 
+/* Trilinear hexahedra with the geometric factors formed in the kernel (section 2.1: they are the
+ * metric terms of the element map at the points, and a trilinear map is fixed by its vertices):
+ * y = (L + lambda M) u^ as nir_helmholtz_apply with the factors of
+ * nir_geom_from_vertices(NIR_MAP_VERTEX), which are neither stored nor read.
+ * verts: [nelmt][8][3] FP64 device array, vertex v at the reference corner
+ * (s1, s2, s3) = (-,-,-), (+,-,-), (+,+,-), (-,+,-), then the same four at xi3 = +1 (the
+ * order of nir_geom_from_vertices).  J, det J and the fused factors are computed in FP64 at
+ * every point; FP32 batches round the factors to FP32 for the contractions.  Hexahedra,
+ * Q = P + 1, NIR_MATH_NATIVE (else NIR_ENOTSUP); batch->deformed is not used; coef_in, coef_out
+ * [nelmt][M], distinct; verts must not overlap coef_out.  A map that is not orientation
+ * preserving at a point gives meaningless values there (not checked on the device). */
+nir_status nir_helmholtz_apply_trilinear(const nir_batch* batch, const nir_basis* basis, const double* verts,
+                                         double lambda, const void* coef_in, void* coef_out, void* stream);
+
 /* ------------------------------------------------------------------ mixed batches
  * The fused Helmholtz apply over several batches of different shape and order (a mixed mesh
  * grouped by (shape, P)), replayed from one hipGraph.  Two strategies:

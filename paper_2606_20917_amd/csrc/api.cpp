@@ -543,6 +543,28 @@ nir_status nir_helmholtz_apply_fields(const nir_batch* b, const nir_basis* basis
   return launch_helm_hex_fields(basis, b->dtype, b->deformed, nfields, a, static_cast<hipStream_t>(stream));
 }
 
+nir_status nir_helmholtz_apply_trilinear(const nir_batch* b, const nir_basis* basis, const double* verts,
+                                         double lambda, const void* coef_in, void* coef_out, void* stream) {
+  NIR_TRY(check_batch(b, basis));
+  if (b->shape != kHex) return fail(NIR_ENOTSUP, "the in-kernel trilinear geometry is implemented for hexahedra");
+  NIR_TRY(native_only(b));
+  if (b->nelmt == 0) return NIR_OK;
+  if (!verts) return fail(NIR_EINVAL, "verts is NULL");
+  if (!aligned(verts, 8)) return fail(NIR_EINVAL, "verts is not 8-byte aligned");
+  NIR_TRY(check_ptr(b, coef_in, "coef_in"));
+  NIR_TRY(check_ptr(b, coef_out, "coef_out"));
+  const size_t es = elem_size(b), n = size_t(b->nelmt), cb = n * basis->M * es;
+  if (overlap(coef_out, cb, coef_in, cb)) return fail(NIR_EINVAL, "coef_in and coef_out overlap");
+  if (overlap(coef_out, cb, verts, n * 24 * sizeof(double))) return fail(NIR_EINVAL, "coef_out overlaps verts");
+  if (!(lambda == lambda)) return fail(NIR_EINVAL, "lambda is NaN");
+  OpArgs a{};
+  a.in0 = coef_in;
+  a.out0 = coef_out;
+  a.lambda = lambda;
+  a.nelmt = b->nelmt;
+  return launch_helm_hex_trilinear(basis, b->dtype, verts, a, static_cast<hipStream_t>(stream));
+}
+
 nir_status nir_autotune_helmholtz(const nir_batch* b, const nir_basis* basis, const nir_geom* g, double lambda,
                                   const void* coef_in, void* coef_out, int32_t reps, int32_t* chosen,
                                   double* ms_per_variant, void* stream) {

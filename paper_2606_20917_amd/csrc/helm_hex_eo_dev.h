@@ -125,18 +125,50 @@ __device__ __forceinline__ void eo_pair(const T* v, int h, bool mid, T& sv, T& a
   av = mid ? T(0) : v[h] - v[P - h];
 }
 
+// The fused factors at one point of a trilinear hexahedron from the pencil constants of
+// helm_hex_eo_group (TRI): J = [J1 | A2 + B2 xi1 | A3 + B3 xi1] (columns dx/dxi_a), the rows of
+// J^-1 are r_a / det with r0 = c1 x c2, r1 = c2 x c0, r2 = c0 x c1, so
+// G_ab = w det (J^-1 J^-T)_ab = w (r_a . r_b) / det and the mass factor is w det (FP64).
+template <class T>
+__device__ __forceinline__ void tri_factors(const double* J1, const double* A2, const double* B2, const double* A3,
+                                            const double* B3, double xi1, double w, T* G) {
+  double c1[3], c2[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    c1[d] = A2[d] + B2[d] * xi1;
+    c2[d] = A3[d] + B3[d] * xi1;
+  }
+  const double r0[3] = {c1[1] * c2[2] - c1[2] * c2[1], c1[2] * c2[0] - c1[0] * c2[2], c1[0] * c2[1] - c1[1] * c2[0]};
+  const double r1[3] = {c2[1] * J1[2] - c2[2] * J1[1], c2[2] * J1[0] - c2[0] * J1[2], c2[0] * J1[1] - c2[1] * J1[0]};
+  const double r2[3] = {J1[1] * c1[2] - J1[2] * c1[1], J1[2] * c1[0] - J1[0] * c1[2], J1[0] * c1[1] - J1[1] * c1[0]};
+  const double det = J1[0] * r0[0] + J1[1] * r0[1] + J1[2] * r0[2];
+  const double sc = w / det;
+  auto dot = [](const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+  G[0] = T(sc * dot(r0, r0));
+  G[1] = T(sc * dot(r0, r1));
+  G[2] = T(sc * dot(r0, r2));
+  G[3] = T(sc * dot(r1, r1));
+  G[4] = T(sc * dot(r1, r2));
+  G[5] = T(sc * dot(r2, r2));
+  G[6] = T(w * det);
+}
+
 // One group of up to E elements starting at `base` on a block of HexPencilDims<P,T,E,TP>::BLOCK
 // threads; `lds` holds HexPencilDims<P,T,E,TP>::LDS values; every thread of the block calls it.
 // `tabs` is the folded table (EoDims<P>::H rows of 2P values).  TP and GP as in helm_hex_group:
 // TP exchanges the direction-2/direction-1 planes two at a time, GP (deformed geometry) runs the
 // point-pair loop one pair ahead on its factors.  NF > 1: the group's "elements" are NF fields of
-// each element, which share its geometric factors (as in helm_hex_group).
+// each element, which share its geometric factors (as in helm_hex_group).  TRI: no factor stream;
+// the factors are computed at every point from the element's 8 vertices (vtx, [element][8][3]
+// FP64, the trilinear map) with the 1-D GLL points z1 and weights w1 (FP64).
 template <int P, class T, bool DEF, int E_ = 256 / ((P + 1) * (P + 1)), bool TP = false, bool GP = false,
-          int NF = 1>
+          int NF = 1, bool TRI = false>
 __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, const T* __restrict__ x,
                                                   T* __restrict__ y, const T* __restrict__ helm,
                                                   const T* __restrict__ wq, T lambda, int64_t nelmt, int64_t base,
-                                                  T* __restrict__ lds) {
+                                                  T* __restrict__ lds, const double* __restrict__ vtx = nullptr,
+                                                  const double* __restrict__ z1 = nullptr,
+                                                  const double* __restrict__ w1 = nullptr) {
   using D = HexPencilDims<P, T, E_, TP>;
   using F = EoDims<P>;
   constexpr int BLOCK = D::BLOCK;
@@ -163,8 +195,9 @@ __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, co
 
   // ---- GP: the factors of point planes 0 and Q-1 (the first pair), in flight through the
   // forward sweeps; lanes past the batch end read element 0's factors (never stored)
+  static_assert(!(TRI && GP), "the trilinear path streams no factors");
   constexpr bool G1 = GP && DEF;
-  const T* g = helm + (valid ? e / NF : 0) * (DEF ? 7 * NQ : 7);
+  const T* g = TRI ? helm : helm + (valid ? e / NF : 0) * (DEF ? 7 * NQ : 7);
   T gn[G1 ? 14 : 1];
   if constexpr (G1) {
 #pragma unroll
@@ -256,9 +289,10 @@ __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, co
 
   // ---- C, pointwise, C^T fused over point pairs (i, Q-1-i) with pencils (j,k): the values
   // at both points are formed, weighted and folded back into the folded accumulators at once.
-  // With GP, the two-plane variant reads the third plane in LDS at every pair (P values), and
-  // in FP64 at P >= 9 the second plane too, which frees the registers of the prefetch
-  constexpr bool C2L = TP && G1;
+  // With GP (or TRI), the two-plane variant reads the third plane in LDS at every pair (P values),
+  // and in FP64 at P >= 9 the second plane too, which frees the registers of the prefetch (or of
+  // the map's pencil constants)
+  constexpr bool C2L = TP && (G1 || TRI);
   constexpr bool C1L = C2L && sizeof(T) == 8 && P >= 9;
   T C0e[NE], C0o[NO], C1e[NE], C1o[NO], C2e[NE], C2o[NO];
   {
@@ -376,6 +410,32 @@ __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, co
       if (h + 1 < H) fwd(HexTabEO<P, T>{fresh_table(tabs + (h + 1) * ROW)}, u, d1, d2, d3);
     }
   } else {
+    // TRI: the map along the thread's point pencil (j, k): x = sum_v X_v f1 f2 f3 with
+    // f_a = (1 + s_a xi_a)/2 for vertex v at reference corner (s1, s2, s3); dx/dxi1 = J1 is
+    // constant on the pencil, dx/dxi2 = A2 + B2 xi1 and dx/dxi3 = A3 + B3 xi1
+    double J1[3] = {0, 0, 0}, A2[3] = {0, 0, 0}, B2[3] = {0, 0, 0}, A3[3] = {0, 0, 0}, B3[3] = {0, 0, 0};
+    double wjk = 0.0;
+    if constexpr (TRI) {
+      const int jj = s / Q, kk = s - jj * Q;
+      const double x2 = z1[jj], x3 = z1[kk];
+      wjk = w1[jj] * w1[kk];
+      const double* X = vtx + (valid ? e / NF : 0) * 24;   // lanes past the end: element 0 (never stored)
+      constexpr int S1[8] = {-1, 1, 1, -1, -1, 1, 1, -1}, S2[8] = {-1, -1, 1, 1, -1, -1, 1, 1},
+                    S3[8] = {-1, -1, -1, -1, 1, 1, 1, 1};
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const double f2 = 0.5 * (1.0 + S2[v] * x2), f3 = 0.5 * (1.0 + S3[v] * x3);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const double xv = X[v * 3 + d];
+          J1[d] += (0.5 * S1[v]) * f2 * f3 * xv;
+          A2[d] += (0.25 * S2[v]) * f3 * xv;
+          B2[d] += (0.25 * S1[v] * S2[v]) * f3 * xv;
+          A3[d] += (0.25 * S3[v]) * f2 * xv;
+          B3[d] += (0.25 * S1[v] * S3[v]) * f2 * xv;
+        }
+      }
+    }
 #pragma unroll 1
     for (int h = 0; h < H; ++h) {
       const HexTabEO<P, T> tk{fresh_table(tabs + h * ROW)};
@@ -385,9 +445,12 @@ __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, co
       T m[2], f1[2], f2[2], f3[2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const int n = (q == 0 ? h : Q - 1 - h) * Q2 + s;
+        const int iq = q == 0 ? h : Q - 1 - h;
+        const int n = iq * Q2 + s;
         T G[7];
-        if constexpr (DEF) {
+        if constexpr (TRI) {
+          tri_factors(J1, A2, B2, A3, B3, z1[iq], w1[iq] * wjk, G);
+        } else if constexpr (DEF) {
 #pragma unroll
           for (int c = 0; c < 7; ++c) G[c] = g[c * NQ + n];
         } else {

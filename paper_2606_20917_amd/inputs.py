@@ -157,6 +157,15 @@ def hex_sin32(P, n=32):
                 coef=coefficients(rng, len(verts), nmodes(HEX, P)))
 
 
+def hex_tri32(P, n=32):
+    """n^3 trilinear hexes: the jitter recipe of hex_jitter64 (interior vertices moved by
+    U(-0.05h, 0.05h)) at the element count of hex_sin32, without the sin deformation."""
+    rng = rng_for(9)
+    verts = hex_mesh(n, rng, jitter=0.05)
+    return dict(shape=HEX, P=P, Q=P + 1, verts=verts, amp=0.0, deformed=1,
+                coef=coefficients(rng, len(verts), nmodes(HEX, P)))
+
+
 def tet24(P, n=24):
     rng = rng_for(3)
     verts = tet_mesh(n, rng, jitter=0.03)

@@ -1,0 +1,107 @@
+"""GPU parity of the Helmholtz apply with in-kernel trilinear geometry (nir_helmholtz_apply_trilinear).
+
+The oracle builds the same trilinear map from the same vertices (dense matrices, per-point
+J, det J and inverse metric in FP64) and applies its Helmholtz matrix; every element is compared
+at the precision's bar.  Covered: P = 2..10 (both parities of Q), element counts that leave a
+partial workgroup, FP64 and FP32, lambda = 0 (Laplacian alone), the 4^3 jittered mesh of the
+small workload, agreement with the streamed-factor apply on the same mesh, a full-size 32^3
+sample and argument validation.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import geometry as og, operators as op
+from paper_2606_20917_amd import inputs, nir
+from tests.gpu_util import elem_relerr, small_mesh
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+TOL64, TOL32 = 1e-12, 2e-4
+
+
+def _apply_tri(verts, P, dtype, coef, lam):
+    ne = len(verts)
+    basis = nir.Basis(nir.HEX, P)
+    tdt = torch.float64 if dtype == nir.F64 else torch.float32
+    x = torch.tensor(coef, dtype=tdt, device=DEV)
+    y = torch.full_like(x, float("nan"))
+    v = torch.tensor(np.ascontiguousarray(verts), dtype=torch.float64, device=DEV)
+    nir.nir_helmholtz_apply_trilinear(nir.batch(nir.HEX, P, ne, dtype, 1), basis, v, lam, x, y)
+    torch.cuda.synchronize()
+    return y.double().cpu().numpy()
+
+
+def _reference(verts, P, coef, lam):
+    return op.helmholtz(op.Tables(nir.HEX, P, P + 1), og.Geometry(nir.HEX, P + 1, verts, 0.0), lam, coef)
+
+
+@pytest.mark.parametrize("dtype", [nir.F64, nir.F32])
+@pytest.mark.parametrize("P", [2, 3, 4, 5, 6, 7, 8, 9, 10])
+def test_trilinear_matches_oracle(P, dtype):
+    verts = small_mesh(nir.HEX, 3, 500 + P, 0.15, 0.0)   # 27 jittered trilinear hexes
+    rng = np.random.default_rng(600 + P)
+    coef = rng.uniform(-1, 1, (len(verts), P ** 3))
+    if dtype == nir.F32:
+        coef = coef.astype(np.float32).astype(np.float64)
+    for lam in (1.0, 0.0):
+        y = _apply_tri(verts, P, dtype, coef, lam)
+        err = elem_relerr(y, _reference(verts, P, coef, lam))
+        assert err <= (TOL64 if dtype == nir.F64 else TOL32), (P, dtype, lam, err)
+
+
+def test_trilinear_small_workload():
+    """The 4^3 jittered mesh of the small workload (P = 4): every element against the oracle."""
+    c = inputs.hex_jitter64()
+    y = _apply_tri(c["verts"], c["P"], nir.F64, c["coef"], 1.0)
+    assert elem_relerr(y, _reference(c["verts"], c["P"], c["coef"], 1.0)) <= TOL64
+
+
+@pytest.mark.parametrize("P", [3, 8])
+def test_trilinear_equals_streamed_factors(P):
+    """The same apply as the factors of nir_geom_from_vertices(NIR_MAP_VERTEX) streamed from HBM."""
+    verts = small_mesh(nir.HEX, 3, 700 + P, 0.1, 0.0)
+    ne, Q = len(verts), P + 1
+    coef = np.random.default_rng(P).uniform(-1, 1, (ne, P ** 3))
+    y = _apply_tri(verts, P, nir.F64, coef, 1.0)
+    basis = nir.Basis(nir.HEX, P)
+    helm = torch.empty(ne, 7, Q ** 3, dtype=torch.float64, device=DEV)
+    nir.nir_geom_from_vertices(nir.batch(nir.HEX, P, ne, nir.F64, 1), basis, torch.tensor(verts, device=DEV),
+                               nir.MAP_VERTEX, 0.0, None, None, helm, None)
+    x = torch.tensor(coef, device=DEV)
+    y2 = torch.empty_like(x)
+    nir.nir_helmholtz_apply(nir.batch(nir.HEX, P, ne, nir.F64, 1), basis, nir.geom(None, None, helm), 1.0, x, y2)
+    torch.cuda.synchronize()
+    assert elem_relerr(y, y2.cpu().numpy()) <= 1e-13
+
+
+def test_trilinear_validation():
+    P, ne = 4, 3
+    basis = nir.Basis(nir.HEX, P)
+    v = torch.zeros(ne, 8, 3, dtype=torch.float64, device=DEV)
+    x = torch.zeros(ne, 64, dtype=torch.float64, device=DEV)
+    y = torch.empty_like(x)
+    b = nir.batch(nir.HEX, P, ne, nir.F64, 1)
+    with pytest.raises(nir.NirError):
+        nir.nir_helmholtz_apply_trilinear(b, basis, None, 1.0, x, y)
+    with pytest.raises(nir.NirError):
+        nir.nir_helmholtz_apply_trilinear(b, basis, v, 1.0, x, x)
+    with pytest.raises(nir.NirError):
+        nir.nir_helmholtz_apply_trilinear(nir.batch(nir.HEX, P, ne, nir.F32, 1, math=nir.MATH_F16SPLIT), basis, v,
+                                          1.0, x.float(), y.float())
+    nir.nir_helmholtz_apply_trilinear(nir.batch(nir.HEX, P, 0, nir.F64, 1), basis, v, 1.0, x, y)   # empty: no-op
+
+
+@pytest.mark.parametrize("dtype", [nir.F64, nir.F32])
+@pytest.mark.parametrize("P", [4, 10])
+def test_trilinear_full(P, dtype):
+    """32^3 jittered trilinear hexes: seeded sample of elements (and both ends) against the oracle."""
+    c = inputs.hex_tri32(P)
+    ne = len(c["verts"])
+    coef = c["coef"] if dtype == nir.F64 else c["coef"].astype(np.float32).astype(np.float64)
+    y = _apply_tri(c["verts"], P, dtype, coef, 1.0)
+    assert np.isfinite(y).all()
+    sel = np.unique(np.concatenate([np.random.default_rng(P).choice(ne, 32, replace=False), [0, ne - 1]]))
+    err = elem_relerr(y[sel], _reference(c["verts"][sel], P, coef[sel], 1.0))
+    assert err <= (TOL64 if dtype == nir.F64 else TOL32), (P, dtype, err)
