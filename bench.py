@@ -525,6 +525,59 @@ def bench_trilinear(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_nodal(args):
+    """The Helmholtz apply in the nodal (GLL-Lagrange) basis on hex_sin32 (values at the Q^3 points,
+    the same per-point factors), FP64 and FP32: GDoF/s (DoF = Q^3 per element) and fraction of 8 TB/s
+    against its algorithmic bytes (7 factors and the values in and out at every point)."""
+    import torch
+    from paper_2606_20917_amd import inputs, nir
+    dev = torch.device("cuda")
+    out = {"metric": "nodal-basis Helmholtz apply GDoF/s and HBM roofline fraction", "unit": "GDoF/s",
+           "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "hex_sin32 nodal: 32^3 = 32768 curved hexes (sin deformation 0.1), GLL-Lagrange "
+                                  "basis on Q=P+1 points, per-point factors, lambda=1"}}
+    ps = [int(p) for p in args.ps.split(",")]
+    for dt in ("f64", "f32"):
+        res = {}
+        for P in ps:
+            c = inputs.hex_sin32(P)
+            Q, ne = P + 1, len(c["verts"])
+            NQ = Q ** 3
+            s = 8 if dt == "f64" else 4
+            tdt = torch.float64 if dt == "f64" else torch.float32
+            basis = nir.Basis(nir.HEX, P)
+            helm = torch.empty(ne, 7, NQ, dtype=torch.float64, device=dev)
+            helm32 = torch.empty(ne, 7, NQ, dtype=torch.float32, device=dev) if dt == "f32" else None
+            nir.nir_geom_from_vertices(nir.batch(nir.HEX, P, ne, nir.F64, 1), basis, torch.tensor(c["verts"], device=dev),
+                                       nir.MAP_VERTEX_SIN, c["amp"], None, None, helm, helm32)
+            h = helm if dt == "f64" else helm32
+            b = nir.batch(nir.HEX, P, ne, nir.F64 if dt == "f64" else nir.F32, 1)
+            u = torch.tensor(np.random.default_rng(P).uniform(-1, 1, (ne, NQ)), dtype=tdt, device=dev)
+            byts = s * ne * 9 * NQ
+            nsets = max(1, math.ceil(ROTATE_BYTES / byts))
+            sets = [(h, u, torch.empty_like(u))] + [(h.clone(), u.clone(), torch.empty_like(u))
+                                                    for _ in range(nsets - 1)]
+            for k in range(args.warmup):
+                hk, uk, yk = sets[k % nsets]
+                nir.nir_helmholtz_apply_nodal(b, basis, nir.geom(None, None, hk), 1.0, uk, yk)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for k in range(args.steps):
+                hk, uk, yk = sets[k % nsets]
+                nir.nir_helmholtz_apply_nodal(b, basis, nir.geom(None, None, hk), 1.0, uk, yk)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            res[f"P{P}"] = {"ms": round(ms, 4), "gdofs": round(ne * NQ / ms / 1e6, 3),
+                            "frac_hbm": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4), "rotating_sets": nsets}
+            del sets, helm, helm32, h, u
+            torch.cuda.empty_cache()
+        out[dt] = res
+    out["value"] = out["f64"][f"P{ps[-1]}"]["gdofs"]
+    print(json.dumps(out), flush=True)
+
+
 def bench_copy(args):
     """Plain device copy of 1 GiB (calibrates the HBM byte counters: read 1 GiB, write 1 GiB)."""
     import torch
@@ -558,7 +611,8 @@ def main():
                     choices=["auto", "generic", "pencil", "u2", "e1", "pf", "split", "gp", "split_gp", "eo",
                              "eo_split"])
     ap.add_argument("--math", default="native", choices=["native", "f16split"])
-    ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k", "collapsed", "copy", "ops", "fields", "trilinear"])
+    ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k", "collapsed", "copy", "ops", "fields", "trilinear",
+                             "nodal"])
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -583,6 +637,8 @@ def main():
         return bench_fields(args)
     if args.workload == "trilinear":
         return bench_trilinear(args)
+    if args.workload == "nodal":
+        return bench_nodal(args)
     ps = [int(p) for p in args.ps.split(",")]
     vid = {"auto": nir.VARIANT_AUTO, "generic": nir.VARIANT_GENERIC, "pencil": nir.VARIANT_PENCIL,
            "u2": nir.VARIANT_PENCIL_U2, "e1": nir.VARIANT_PENCIL_E1, "pf": nir.VARIANT_PENCIL_PF,

@@ -219,6 +219,17 @@ nir_status nir_helmholtz_apply_fields(const nir_batch* batch, const nir_basis* b
 nir_status nir_helmholtz_apply_trilinear(const nir_batch* batch, const nir_basis* basis, const double* verts,
                                          double lambda, const void* coef_in, void* coef_out, void* stream);
 
+/* The same weak operator (section 2.1, eqs. (6), (7)) in the nodal basis: the tensor-product
+ * Lagrange polynomials through the Q = P + 1 GLL points of each direction (degree Q - 1), with
+ * the values at those points as coefficients and the same points as quadrature (B = I, the
+ * reference derivatives are the collocation matrices of nir_table_host(NIR_TAB_D1..3)):
+ *   y = sum_a D_a^T (sum_b helm_ab D_b u) + lambda helm_6 u.
+ * u_in, u_out: [nelmt][Q^3], point (i, j, k) at i Q^2 + j Q + k, distinct.  geom->helm exactly as
+ * for nir_helmholtz_apply (the factors do not depend on the basis).  Hexahedra with Q = P + 1,
+ * NIR_MATH_NATIVE (else NIR_ENOTSUP). */
+nir_status nir_helmholtz_apply_nodal(const nir_batch* batch, const nir_basis* basis, const nir_geom* geom,
+                                     double lambda, const void* u_in, void* u_out, void* stream);
+
 /* ------------------------------------------------------------------ mixed batches
  * The fused Helmholtz apply over several batches of different shape and order (a mixed mesh
  * grouped by (shape, P)), replayed from one hipGraph.  Two strategies:

@@ -44,6 +44,14 @@ def element_matrix(Q, geo, e, lam):
 
 
 def helmholtz_nodal(Q, geo, lam, u):
-    """y[e] = H_e u[e] for nodal values u[e][Q^3] of every element of an oracle Geometry."""
+    """y[e] = H_e u[e] for nodal values u[e][Q^3] of every element of an oracle Geometry: the
+    same sum as element_matrix, with the dense D_a applied to the vectors."""
     u = np.asarray(u, dtype=np.float64)
-    return np.stack([element_matrix(Q, geo, e, lam) @ u[e] for e in range(u.shape[0])])
+    Da = derivative_matrices(Q)
+    du = np.einsum("anm,em->ean", Da, u)                 # D_b u
+    W, dxi = geo.W, geo.dxi_dx                           # [e][n], [e][a][i][n]
+    y = lam * W * u
+    for a in range(3):
+        fa = sum(W * sum(dxi[:, a, i] * dxi[:, b, i] for i in range(3)) * du[:, b] for b in range(3))
+        y = y + fa @ Da[a]                               # (D_a^T f_a)^T = f_a^T D_a
+    return y

@@ -565,6 +565,30 @@ nir_status nir_helmholtz_apply_trilinear(const nir_batch* b, const nir_basis* ba
   return launch_helm_hex_trilinear(basis, b->dtype, verts, a, static_cast<hipStream_t>(stream));
 }
 
+nir_status nir_helmholtz_apply_nodal(const nir_batch* b, const nir_basis* basis, const nir_geom* g, double lambda,
+                                     const void* u_in, void* u_out, void* stream) {
+  NIR_TRY(check_batch(b, basis));
+  if (b->shape != kHex) return fail(NIR_ENOTSUP, "the nodal basis is implemented for hexahedra");
+  NIR_TRY(native_only(b));
+  if (b->nelmt == 0) return NIR_OK;
+  NIR_TRY(check_geom(b, g, false, false, true));
+  NIR_TRY(check_ptr(b, u_in, "u_in"));
+  NIR_TRY(check_ptr(b, u_out, "u_out"));
+  const size_t es = elem_size(b), n = size_t(b->nelmt), nq = size_t(basis->Q) * basis->Q * basis->Q;
+  const size_t cb = n * nq * es;
+  if (overlap(u_out, cb, u_in, cb)) return fail(NIR_EINVAL, "u_in and u_out overlap");
+  if (overlap(u_out, cb, g->helm, n * 7 * (b->deformed ? nq : 1) * es))
+    return fail(NIR_EINVAL, "u_out overlaps the geometry");
+  if (!(lambda == lambda)) return fail(NIR_EINVAL, "lambda is NaN");
+  OpArgs a{};
+  a.in0 = u_in;
+  a.out0 = u_out;
+  a.helm = g->helm;
+  a.lambda = lambda;
+  a.nelmt = b->nelmt;
+  return launch_helm_hex_nodal(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+}
+
 nir_status nir_autotune_helmholtz(const nir_batch* b, const nir_basis* basis, const nir_geom* g, double lambda,
                                   const void* coef_in, void* coef_out, int32_t reps, int32_t* chosen,
                                   double* ms_per_variant, void* stream) {

@@ -42,6 +42,8 @@ nir_status launch_helm_hex_fields(const nir_basis* b, int dtype, int deformed, i
 // trilinear hexahedra, factors formed in the kernel from verts [nelmt][8][3] (helm_hex_tri.hip)
 nir_status launch_helm_hex_trilinear(const nir_basis* b, int dtype, const double* verts, const OpArgs& a,
                                      hipStream_t s);
+// the nodal (GLL-Lagrange) basis, values [nelmt][Q^3] (helm_hex_nodal.hip)
+nir_status launch_helm_hex_nodal(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
 // the even-odd folded variant (helm_hex_eo.hip); split: planes exchanged two at a time
 nir_status launch_helm_hex_eo(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s,
                               bool split);

@@ -73,6 +73,8 @@ _SIGS = {
     "nir_helmholtz_apply_fields": (_i32, [ctypes.POINTER(nir_batch), _vp, ctypes.POINTER(nir_geom), _dbl, _i32, _vp,
                                           _vp, _vp]),
     "nir_helmholtz_apply_trilinear": (_i32, [ctypes.POINTER(nir_batch), _vp, _vp, _dbl, _vp, _vp, _vp]),
+    "nir_helmholtz_apply_nodal": (_i32, [ctypes.POINTER(nir_batch), _vp, ctypes.POINTER(nir_geom), _dbl, _vp, _vp,
+                                         _vp]),
     "nir_set_helmholtz_variant": (_i32, [_i32, _i32, _i32, _i32]),
     "nir_points_from_vertices": (_i32, [ctypes.POINTER(nir_batch), _vp, _vp, _i32, _dbl, _vp, _vp]),
     "nir_c0_nglobal_hex": (_i64, [_i32, _i32]),
@@ -247,6 +249,11 @@ def nir_helmholtz_apply_fields(b, basis, g, lam, nfields, coef_in, coef_out, str
 def nir_helmholtz_apply_trilinear(b, basis, verts, lam, coef_in, coef_out, stream=None):
     _check(lib().nir_helmholtz_apply_trilinear(ctypes.byref(b), _basis(basis), _ptr(verts), lam, _ptr(coef_in),
                                                _ptr(coef_out), _stream(stream)))
+
+
+def nir_helmholtz_apply_nodal(b, basis, g, lam, u_in, u_out, stream=None):
+    _check(lib().nir_helmholtz_apply_nodal(ctypes.byref(b), _basis(basis), ctypes.byref(g), lam, _ptr(u_in),
+                                           _ptr(u_out), _stream(stream)))
 
 
 def nir_set_helmholtz_variant(shape, P, dtype, variant):
