@@ -578,6 +578,60 @@ def bench_nodal(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_convergence(args):
+    """Manufactured-solution study: u = cos(pi x) cos(pi y) cos(pi z) on the unit cube (homogeneous
+    Neumann, lambda = 1) on n^3 hexes (straight and sin-deformed), assembled Jacobi-PCG to 1e-12,
+    L2 error of the discrete solution at the quadrature points against u, P = 2..10."""
+    import torch
+    from paper_2606_20917_amd import inputs, nir
+    dev = torch.device("cuda")
+    n, lam = 3, 1.0
+    out = {"metric": "L2 error of the assembled solve against the manufactured solution", "unit": "L2 error",
+           "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": f"{n}^3 hexes on the unit cube, u = cos(pi x)cos(pi y)cos(pi z), homogeneous "
+                                  "Neumann, lambda=1, Q=P+1, PCG FP64 to 1e-12"}}
+    for amp in (0.0, 0.1):
+        res = {}
+        for P in range(2, 11):
+            Q = P + 1
+            verts = inputs.hex_mesh(n)
+            ne = len(verts)
+            basis = nir.Basis(nir.HEX, P)
+            b64 = nir.batch(nir.HEX, P, ne, nir.F64, 1)
+            dv = torch.tensor(verts, device=dev)
+            mp = nir.MAP_VERTEX_SIN if amp else nir.MAP_VERTEX
+            helm = torch.empty(ne, 7, Q ** 3, dtype=torch.float64, device=dev)
+            helm32 = torch.empty(ne, 7, Q ** 3, dtype=torch.float32, device=dev)
+            jac = torch.empty(ne, Q ** 3, dtype=torch.float64, device=dev)
+            nir.nir_geom_from_vertices(b64, basis, dv, mp, amp, None, jac, helm, helm32)
+            xyz = torch.empty(ne, 3, Q ** 3, dtype=torch.float64, device=dev)
+            nir.nir_points_from_vertices(b64, basis, dv, mp, amp, xyz)
+            u = torch.cos(np.pi * xyz[:, 0]) * torch.cos(np.pi * xyz[:, 1]) * torch.cos(np.pi * xyz[:, 2])
+            f = ((3 * np.pi ** 2 + lam) * u).contiguous()
+            ng = nir.nir_c0_nglobal_hex(n, P)
+            l2g = torch.empty(ne, P ** 3, dtype=torch.int32, device=dev)
+            nir.nir_c0_map_hex(n, P, l2g)
+            A = nir.Assembly(l2g, ng)
+            bl = torch.empty(ne, P ** 3, dtype=torch.float64, device=dev)
+            nir.nir_iprod_wrt_base(b64, basis, nir.geom(None, jac, None), f, bl)
+            bg = torch.zeros(ng, dtype=torch.float64, device=dev)
+            nir.nir_scatter_add(A, nir.F64, bl, bg)
+            plan = nir.CGPlan(b64, basis, nir.geom(None, None, helm), helm32, A, lam)
+            x = torch.zeros(ng, dtype=torch.float64, device=dev)
+            _, info = nir.nir_cg_solve(plan, nir.CG_FP64, bg, x, rtol=1e-12, maxit=100000)
+            xl = torch.empty(ne, P ** 3, dtype=torch.float64, device=dev)
+            nir.nir_gather(A, nir.F64, x, xl)
+            uh = torch.empty(ne, Q ** 3, dtype=torch.float64, device=dev)
+            nir.nir_bwd_trans(b64, basis, xl, uh)
+            w = torch.tensor(nir.nir_table_host(nir.HEX, P, Q, nir.TAB_WQ), device=dev)
+            err = float(torch.sqrt((w[None, :] * jac * (uh - u) ** 2).sum()))
+            res[f"P{P}"] = {"l2_error": err, "cg_iters": info.inner_iters, "rel_residual": info.rel_residual,
+                            "nglobal": ng}
+        out["straight" if amp == 0.0 else "curved_sin0.1"] = res
+    out["value"] = out["curved_sin0.1"]["P10"]["l2_error"]
+    print(json.dumps(out), flush=True)
+
+
 def bench_copy(args):
     """Plain device copy of 1 GiB (calibrates the HBM byte counters: read 1 GiB, write 1 GiB)."""
     import torch
@@ -612,7 +666,7 @@ def main():
                              "eo_split"])
     ap.add_argument("--math", default="native", choices=["native", "f16split"])
     ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k", "collapsed", "copy", "ops", "fields", "trilinear",
-                             "nodal"])
+                             "nodal", "convergence"])
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -639,6 +693,8 @@ def main():
         return bench_trilinear(args)
     if args.workload == "nodal":
         return bench_nodal(args)
+    if args.workload == "convergence":
+        return bench_convergence(args)
     ps = [int(p) for p in args.ps.split(",")]
     vid = {"auto": nir.VARIANT_AUTO, "generic": nir.VARIANT_GENERIC, "pencil": nir.VARIANT_PENCIL,
            "u2": nir.VARIANT_PENCIL_U2, "e1": nir.VARIANT_PENCIL_E1, "pf": nir.VARIANT_PENCIL_PF,
