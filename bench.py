@@ -96,7 +96,7 @@ def cpu_baseline(cases, budget_s):
 # HBM bytes per launch of the dominant kernel measured with FETCH_SIZE / WRITE_SIZE (calibrated
 # by a plain 1 GiB copy: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), valid for that kernel variant while
 # the kernel sources hash to `src_sha`
-TRAFFIC = {"P": 10, "dtype": "f64", "variant": 8, "bytes": 3005361355, "src_sha": "92b9cb60f922239b"}
+TRAFFIC = {"P": 10, "dtype": "f64", "variant": 8, "bytes": 3006381437, "src_sha": "22723980529fcef5"}
 
 
 def kernel_src_sha():
