@@ -274,7 +274,11 @@ nir_status nir_basis_create(int32_t shape, int32_t P, int32_t Q, nir_basis** out
     // psi^a_p(-z) = (-1)^p psi^a_p(z) for p >= 2.  On a middle point (odd Q) the odd half of B
     // and the even half of B' vanish and are stored as exact zeros.
     const int H = (Q + 1) / 2, NE = 1 + (P - 1) / 2, neo = b->shape == kHex && Q == P + 1 ? H * 2 * P : 0;
-    std::vector<double> p64(2 * Q * P + neo);
+    // collapsed shapes: the forward sweeps' factors in [slice][point][term] order (col_a_off,
+    // col_b_off), values then derivatives
+    const bool col = b->shape != kHex && Q == P + 1;
+    const int na = col ? col_a_off(b->shape, P, P) : 0, nbt = col ? col_b_off(b->shape, P, P) : 0;
+    std::vector<double> p64(2 * Q * P + neo + 2 * na + 2 * nbt);
     std::vector<float> p32(p64.size());
     auto B = [&](int i, int p) { return b->host.T1[p * Q + i]; };
     auto Dd = [&](int i, int p) { return b->host.dT1[p * Q + i]; };
@@ -299,6 +303,36 @@ nir_status nir_basis_create(int32_t shape, int32_t P, int32_t Q, nir_basis** out
         r[P + NE + k] = Dd(h, 2 * k + 1);
       }
     }
+    if (col) {
+      const int sh = b->shape;
+      double* A3 = p64.data() + 2 * Q * P + neo;
+      double* dA3 = A3 + na;
+      double* B2 = dA3 + na;
+      double* dB2 = B2 + nbt;
+      for (int sl = 0; sl < P; ++sl) {
+        const int nt = col_a_terms(sh, P, sl), off = col_a_off(sh, P, sl);
+        for (int r = 0; r < nt; ++r) {
+          // tet: psi^c_{sl,r} (the row of mode (0,sl,r)); prism: psi^b_{sl,r}, and for sl = 1 the
+          // extra term of the (0,q,1) vertex modes, psi^b_01 (the row of mode (0,0,1))
+          const int row = sh == kTet ? col_m0(sh, P, 0, sl) + r : (r < P - sl ? col_m0(sh, P, sl, 0) + r : 1);
+          for (int k = 0; k < Q; ++k) {
+            A3[off + k * nt + r] = b->host.T3[row * Q + k];
+            dA3[off + k * nt + r] = b->host.dT3[row * Q + k];
+          }
+        }
+      }
+      for (int p = 0; p < P; ++p) {
+        const int nt = col_b_terms(sh, P, p), off = col_b_off(sh, P, p);
+        const int nq = sh == kTet ? P - p : P;
+        for (int q = 0; q < nt; ++q) {
+          const int pr = q < nq ? col_pair(sh, P, p, q) : col_pair(sh, P, 0, 1);   // tet p = 1: pair (0,1)
+          for (int j = 0; j < Q; ++j) {
+            B2[off + j * nt + q] = b->host.T2[pr * Q + j];
+            dB2[off + j * nt + q] = b->host.dT2[pr * Q + j];
+          }
+        }
+      }
+    }
     for (size_t k = 0; k < p64.size(); ++k) p32[k] = float(p64[k]);
     const size_t nb64 = p64.size() * 8, nb32 = p32.size() * 4;
     if ((st = hip_check(hipMalloc(&b->devpencil, nb64 + nb32), "hipMalloc tables")) != NIR_OK ||
@@ -313,6 +347,17 @@ nir_status nir_basis_create(int32_t shape, int32_t P, int32_t Q, nir_basis** out
     if (neo) {
       b->eo64 = b->pencil64 + 2 * Q * P;
       b->eo32 = b->pencil32 + 2 * Q * P;
+    }
+    if (col) {
+      const size_t o = size_t(2 * Q * P + neo);
+      b->t64.T3t = b->pencil64 + o;
+      b->t64.dT3t = b->pencil64 + o + na;
+      b->t64.T2t = b->pencil64 + o + 2 * na;
+      b->t64.dT2t = b->pencil64 + o + 2 * na + nbt;
+      b->t32.T3t = b->pencil32 + o;
+      b->t32.dT3t = b->pencil32 + o + na;
+      b->t32.T2t = b->pencil32 + o + 2 * na;
+      b->t32.dT2t = b->pencil32 + o + 2 * na + nbt;
     }
     // MFMA basis tiles: 0 = B^T [r][k], 1 = B'^T [r][k], 2 = B [i][p], 3 = B' [i][p]
     std::vector<float> mt(4 * 256, 0.f), ms(4, 1.f);

@@ -42,17 +42,29 @@
 
 namespace nir {
 
-template <int SHAPE, int P>
-struct ColModes {
-  static constexpr int pair(int p, int q) { return SHAPE == kTet ? p * P - p * (p - 1) / 2 + q : p * P + q; }
-  static constexpr int nq(int p) { return SHAPE == kTet ? P - p : P; }
-  // first mode of pair (p,q) in the p-outer, q, r-inner order
-  static constexpr int m0(int p, int q) {
-    int m = 0;
-    for (int pp = 0; pp < p; ++pp) m += SHAPE == kTet ? (P - pp) * (P - pp + 1) / 2 : P * (P - pp);
-    return m + (SHAPE == kTet ? q * (P - p) - q * (q - 1) / 2 : q * (P - p));
-  }
-};
+// A fresh table pointer (see fresh_table) that is also not known before `dep`: in an unrolled
+// sweep the row loads of iteration k+1 wait for a value of iteration k.  Otherwise instruction
+// selection issues the scalar loads of every row of a slice up front (the rows do not depend on
+// each other) and the rows that do not fit in SGPRs are spilled into VGPR lanes.
+template <class T, class D>
+__device__ __forceinline__ const_ptr<T> fresh_table_after(const T* p, const D& dep) {
+  __builtin_amdgcn_sched_barrier(0);
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v))));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v >> 32))));
+  uint64_t u = (uint64_t(hi) << 32) | uint64_t(lo);
+  asm volatile("" : "+s"(u) : "v"(dep));
+  return (const_ptr<T>)u;
+}
+
+// Completes the N values of `v` before the next volatile asm (the next row's fresh_table): in an
+// unrolled sweep the loads of row k+1 then wait for all the products of row k, so only about one
+// row of factors is live in SGPRs.
+template <int N, class T>
+__device__ __forceinline__ void row_fence(const T* v) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) asm volatile("" ::"v"(v[i]));
+}
 
 // E_ = 0: the default group size (full slice wavefronts within 64 KiB of LDS)
 template <int SHAPE, int P, class T, int E_ = 0>
@@ -145,17 +157,23 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
           T c[nr];
 #pragma unroll
           for (int r = 0; r < nr; ++r) c[r] = (sl == 0 && r == 1) ? T(0) : Ls[m0 + r];   // vertex mode apart
+          // one row of nr terms per point k (transposed table): only that row is live in SGPRs
+          constexpr int off = col_a_off(SHAPE, P, sl);
 #pragma unroll
-          for (int k = 0; k < Q; ++k) a0[k] = a1[k] = T(0);
+          for (int k = 0; k < Q; ++k) {
+            const T dep = k > 0 ? a0[k - 1] : c[0];
+            const const_ptr<T> f = fresh_table_after(tb.T3t, dep) + (off + k * nr);
+            const const_ptr<T> df = fresh_table_after(tb.dT3t, dep) + (off + k * nr);
+            T v0 = T(0), v1 = T(0);
 #pragma unroll
-          for (int r = 0; r < nr; ++r) {
-            const const_ptr<T> f = fresh_table(tb.T3) + (MO::m0(0, sl) + r) * Q;
-            const const_ptr<T> df = fresh_table(tb.dT3) + (MO::m0(0, sl) + r) * Q;
-#pragma unroll
-            for (int k = 0; k < Q; ++k) {
-              a0[k] += f[k] * c[r];
-              a1[k] += df[k] * c[r];
+            for (int r = 0; r < nr; ++r) {
+              v0 += f[r] * c[r];
+              v1 += df[r] * c[r];
             }
+            a0[k] = v0;
+            a1[k] = v1;
+            row_fence<1>(&a0[k]);
+            row_fence<1>(&a1[k]);
           }
           dst = MO::pair(p, q);
         }
@@ -166,25 +184,28 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
         if (e2 < E) {
           Ls = lds + e2 * SLAB;
           const int m0 = MO::m0(p, 0) + q * nr;
-          T c[nr];
+          // term nr (p = 1 only): the (0,q,1) vertex modes with psi^b_01
+          constexpr int nt = col_a_terms(SHAPE, P, sl), off = col_a_off(SHAPE, P, sl);
+          T c[nt];
 #pragma unroll
           for (int r = 0; r < nr; ++r) c[r] = Ls[m0 + r];
-          T cx = T(0);
-          if (p == 1) cx = Ls[MO::m0(0, 0) + q * P + 1];
+          if constexpr (nt > nr) c[nr] = Ls[MO::m0(0, 0) + q * P + 1];
+          // one row of terms per point k (transposed table): only that row is live in SGPRs
 #pragma unroll
-          for (int k = 0; k < Q; ++k) a0[k] = a1[k] = T(0);
+          for (int k = 0; k < Q; ++k) {
+            const T dep = k > 0 ? a0[k - 1] : c[0];
+            const const_ptr<T> f = fresh_table_after(tb.T3t, dep) + (off + k * nt);
+            const const_ptr<T> df = fresh_table_after(tb.dT3t, dep) + (off + k * nt);
+            T v0 = T(0), v1 = T(0);
 #pragma unroll
-          for (int r = 0; r < nr + (p == 1 ? 1 : 0); ++r) {
-            // r = nr (p = 1 only): the (0,q,1) vertex modes with psi^b_01
-            const int row = r < nr ? MO::m0(p, 0) + r : 1;
-            const T cr = r < nr ? c[r] : cx;
-            const const_ptr<T> f = fresh_table(tb.T3) + row * Q;
-            const const_ptr<T> df = fresh_table(tb.dT3) + row * Q;
-#pragma unroll
-            for (int k = 0; k < Q; ++k) {
-              a0[k] += f[k] * cr;
-              a1[k] += df[k] * cr;
+            for (int r = 0; r < nt; ++r) {
+              v0 += f[r] * c[r];
+              v1 += df[r] * c[r];
             }
+            a0[k] = v0;
+            a1[k] = v1;
+            row_fence<1>(&a0[k]);
+            row_fence<1>(&a1[k]);
           }
           dst = MO::pair(p, q);
         }
@@ -222,19 +243,27 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
           av[nq] = Ls[MO::pair(0, 1) * Q + k];
           bv[nq] = Ls[NP * Q + MO::pair(0, 1) * Q + k];
         }
+        // one row of terms per point j (transposed table), the pair (0,1) term last for X
+        constexpr int nt = col_b_terms(SHAPE, P, p), off = col_b_off(SHAPE, P, p);
+        static_assert(nt == nq + (X ? 1 : 0), "B terms");
 #pragma unroll
-        for (int j = 0; j < Q; ++j) b0[j] = b1[j] = b2[j] = T(0);
+        for (int j = 0; j < Q; ++j) {
+          const T dep = j > 0 ? b0[j - 1] : av[0];
+          const const_ptr<T> f = fresh_table_after(tb.T2t, dep) + (off + j * nt);
+          const const_ptr<T> df = fresh_table_after(tb.dT2t, dep) + (off + j * nt);
+          T v0 = T(0), v1 = T(0), v2 = T(0);
 #pragma unroll
-        for (int q = 0; q < nq + (X ? 1 : 0); ++q) {
-          const int pr = q < nq ? MO::pair(p, q) : MO::pair(0, 1);
-          const const_ptr<T> f = fresh_table(tb.T2) + pr * Q;
-          const const_ptr<T> df = fresh_table(tb.dT2) + pr * Q;
-#pragma unroll
-          for (int j = 0; j < Q; ++j) {
-            b0[j] += f[j] * av[q];
-            b1[j] += df[j] * av[q];
-            b2[j] += f[j] * bv[q];
+          for (int q = 0; q < nt; ++q) {
+            v0 += f[q] * av[q];
+            v1 += df[q] * av[q];
+            v2 += f[q] * bv[q];
           }
+          b0[j] = v0;
+          b1[j] = v1;
+          b2[j] = v2;
+          row_fence<1>(&b0[j]);
+          row_fence<1>(&b1[j]);
+          row_fence<1>(&b2[j]);
         }
         pw = p;
       }
@@ -384,26 +413,24 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 #pragma unroll
           for (int j = 0; j < Q; ++j) sx += Ls[MAIN + j * Q + k];
         }
+        // outer loop over the points j, one row of terms per point (transposed table): only that
+        // row is live in SGPRs; the pair (0,1) term last for X
+        constexpr int nt = col_b_terms(SHAPE, P, p), off = col_b_off(SHAPE, P, p);
 #pragma unroll
-        for (int q = 0; q < nq + (X ? 1 : 0); ++q) {
-          const int pr = q < nq ? MO::pair(p, q) : MO::pair(0, 1);
-          // one table row live at a time: psi^b_pq first, then its derivative
-          T v0 = T(0), v1 = T(0);
-          {
-            const const_ptr<T> f = fresh_table(tb.T2) + pr * Q;
+        for (int q = 0; q < nt; ++q) s0[q] = s1[q] = T(0);
 #pragma unroll
-            for (int j = 0; j < Q; ++j) {
-              v0 += f[j] * tv0[j];
-              v1 += f[j] * tv2[j];
-            }
+        for (int j = 0; j < Q; ++j) {
+          const T dep = j > 0 ? s1[nt - 1] : tv0[0];
+          const const_ptr<T> f = fresh_table_after(tb.T2t, dep) + (off + j * nt);
+          const const_ptr<T> df = fresh_table_after(tb.dT2t, dep) + (off + j * nt);
+#pragma unroll
+          for (int q = 0; q < nt; ++q) {
+            s0[q] += f[q] * tv0[j];
+            s0[q] += df[q] * tv1[j];
+            s1[q] += f[q] * tv2[j];
           }
-          {
-            const const_ptr<T> df = fresh_table(tb.dT2) + pr * Q;
-#pragma unroll
-            for (int j = 0; j < Q; ++j) v0 += df[j] * tv1[j];
-          }
-          s0[q] = v0;
-          s1[q] = v1;
+          row_fence<nt>(s0);
+          row_fence<nt>(s1);
         }
         pw = p;
       }
@@ -451,21 +478,29 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
             sv0[k] = Ls[pr * Q + k] + (x01 ? Ls[MAIN + Q2 + k] : T(0));
             sv1[k] = Ls[NP * Q + pr * Q + k] + (x01 ? Ls[MAIN + Q2 + Q + k] : T(0));
           }
+          // outer loop over the points k, one row of terms per point (transposed table); the
+          // vertex mode (0,0,1) of slice 0 takes the sum of its row instead
+          constexpr int off = col_a_off(SHAPE, P, sl);
 #pragma unroll
-          for (int r = 0; r < nr; ++r) {
-            T v = T(0);
-            if (sl == 0 && r == 1) {
+          for (int r = 0; r < nr; ++r) yv[r] = T(0);
 #pragma unroll
-              for (int k = 0; k < Q; ++k) v += Ls[MAIN + Q2 + 2 * Q + k];
-            } else {
-              const const_ptr<T> f = fresh_table(tb.T3) + (MO::m0(0, sl) + r) * Q;
+          for (int k = 0; k < Q; ++k) {
+            const T dep = k > 0 ? yv[0] : sv0[0];
+            const const_ptr<T> f = fresh_table_after(tb.T3t, dep) + (off + k * nr);
+            const const_ptr<T> df = fresh_table_after(tb.dT3t, dep) + (off + k * nr);
 #pragma unroll
-              for (int k = 0; k < Q; ++k) v += f[k] * sv0[k];
-              const const_ptr<T> df = fresh_table(tb.dT3) + (MO::m0(0, sl) + r) * Q;
-#pragma unroll
-              for (int k = 0; k < Q; ++k) v += df[k] * sv1[k];
+            for (int r = 0; r < nr; ++r) {
+              if (sl == 0 && r == 1) continue;
+              yv[r] += f[r] * sv0[k];
+              yv[r] += df[r] * sv1[k];
             }
-            yv[r] = v;
+            row_fence<nr>(yv);
+          }
+          if constexpr (sl == 0) {
+            T v = T(0);
+#pragma unroll
+            for (int k = 0; k < Q; ++k) v += Ls[MAIN + Q2 + 2 * Q + k];
+            yv[1] = v;
           }
           dst = MO::m0(p, q);
           cnt = nr;
@@ -485,22 +520,27 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
             xv0[k] = p == 0 ? Ls[MO::pair(1, q) * Q + k] : T(0);
             xv1[k] = p == 0 ? Ls[NP * Q + MO::pair(1, q) * Q + k] : T(0);
           }
+          // outer loop over the points k, one row of terms per point (transposed table, whose
+          // p = 1 rows carry one more term, not used here)
+          constexpr int nt = col_a_terms(SHAPE, P, sl), off = col_a_off(SHAPE, P, sl);
 #pragma unroll
-          for (int r = 0; r < nr; ++r) {
-            const const_ptr<T> f = fresh_table(tb.T3) + (MO::m0(p, 0) + r) * Q;
-            const const_ptr<T> df = fresh_table(tb.dT3) + (MO::m0(p, 0) + r) * Q;
-            T v = T(0);
+          for (int r = 0; r < nr; ++r) yv[r] = T(0);
 #pragma unroll
-            for (int k = 0; k < Q; ++k) {
+          for (int k = 0; k < Q; ++k) {
+            const T dep = k > 0 ? yv[0] : sv0[0];
+            const const_ptr<T> f = fresh_table_after(tb.T3t, dep) + (off + k * nt);
+            const const_ptr<T> df = fresh_table_after(tb.dT3t, dep) + (off + k * nt);
+#pragma unroll
+            for (int r = 0; r < nr; ++r) {
               if (p == 0 && r == 1) {
-                v += f[k] * (sv0[k] + xv0[k]);
-                v += df[k] * (sv1[k] + xv1[k]);
+                yv[r] += f[r] * (sv0[k] + xv0[k]);
+                yv[r] += df[r] * (sv1[k] + xv1[k]);
               } else {
-                v += f[k] * sv0[k];
-                v += df[k] * sv1[k];
+                yv[r] += f[r] * sv0[k];
+                yv[r] += df[r] * sv1[k];
               }
             }
-            yv[r] = v;
+            row_fence<nr>(yv);
           }
           dst = MO::m0(p, 0) + q * nr;
           cnt = nr;

@@ -67,7 +67,49 @@ struct DevTab {
   const T* xi;
   const int32_t* pair;
   const int32_t* mode_pqr;
+  // collapsed shapes: the factors of the forward sweeps A (direction 3) and B (direction 2) of the
+  // register-pencil kernel, transposed to one row of terms per output point and slice (layout of
+  // col_a_off / col_b_off), and their derivatives
+  const T* T3t;
+  const T* dT3t;
+  const T* T2t;
+  const T* dT2t;
 };
+
+// Mode numbering of the collapsed shapes (p outer, q, r inner) and pair rows (p, q).
+constexpr int col_pair(int shape, int P, int p, int q) { return shape == kTet ? p * P - p * (p - 1) / 2 + q : p * P + q; }
+// first mode of pair (p,q) in the p-outer, q, r-inner order
+constexpr int col_m0(int shape, int P, int p, int q) {
+  int m = 0;
+  for (int pp = 0; pp < p; ++pp) m += shape == kTet ? (P - pp) * (P - pp + 1) / 2 : P * (P - pp);
+  return m + (shape == kTet ? q * (P - p) - q * (q - 1) / 2 : q * (P - p));
+}
+
+template <int SHAPE, int P>
+struct ColModes {
+  static constexpr int pair(int p, int q) { return col_pair(SHAPE, P, p, q); }
+  static constexpr int nq(int p) { return SHAPE == kTet ? P - p : P; }
+  static constexpr int m0(int p, int q) { return col_m0(SHAPE, P, p, q); }
+};
+
+// Terms of the forward sweeps of the collapsed shapes per slice: A of slice sl (tet: p+q, prism:
+// p) sums over r (the prism's p = 1 slice also over its (0,q,1) vertex modes), B of p sums over q
+// (the tet's p = 1 plane also over pair (0,1)); the transposed tables hold Q rows of that many
+// terms per slice, slices in order.
+constexpr int col_a_terms(int shape, int P, int sl) {
+  return shape == kTet ? P - sl : P - sl + (sl == 1 ? 1 : 0);
+}
+constexpr int col_b_terms(int shape, int P, int p) { return shape == kTet ? P - p + (p == 1 ? 1 : 0) : P; }
+constexpr int col_a_off(int shape, int P, int sl) {
+  int o = 0;
+  for (int s = 0; s < sl; ++s) o += col_a_terms(shape, P, s);
+  return o * (P + 1);
+}
+constexpr int col_b_off(int shape, int P, int p) {
+  int o = 0;
+  for (int s = 0; s < p; ++s) o += col_b_terms(shape, P, s);
+  return o * (P + 1);
+}
 
 }  // namespace nir
 
