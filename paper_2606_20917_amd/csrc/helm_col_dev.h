@@ -123,7 +123,8 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
   T* __restrict__ lds = lds0 + (in ? sub : 0) * D::LDS;
   const int ne = in ? int(max(int64_t(0), min(int64_t(E), nelmt - base))) : 0;
 
-  // pencil role: element el, point pencil s = (j,k)
+  // pencil role: element el, point pencil s = (j,k); the wavefronts past the first NWP hold no
+  // pencil
   const int el = t / Q2;
   const int s = t - el * Q2;
   const int jj = s / Q, kk = s - jj * Q;
@@ -281,7 +282,8 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
     __syncthreads();
   }
 
-  // ---- C, pointwise, C^T fused over the (j,k) pencils, streamed over i
+  // ---- C, pointwise, C^T fused over the (j,k) pencils, streamed over i (the wavefronts without
+  // pencils go straight to the barrier)
   {
     T C0[P], C1[P], C2[P];
     T t0[P], t1[P], t2[P];
@@ -316,66 +318,95 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
     }
     const T uv = c001 * vc, dv = c001 * vd;
     T vm = T(0), v3 = T(0);
-    const T* g = helm + (valid ? int64_t(base + el) : 0) * (DEF ? 7 * NQ : 7);
-    const T* wq = tb.wq;
-#pragma unroll 1
-    for (int i = 0; i < Q; ++i) {
-      const HexTabC<P, T> tk{fresh_table(pen)};
-      T u = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
+    if (in && wave < D::NWP) {
+      // The point loop is unrolled where the registers allow (FP64: tetrahedra to P = 9, affine
+      // prisms, prisms with per-point factors to P = 7).  The factors of point plane i+1 (per
+      // point) or its weight (affine) are requested once plane i's are consumed, so the rest of
+      // iteration i covers their latency (rolled, the last plane requests itself again, a cache
+      // hit).  Lanes past the batch end read element 0's (in bounds, finite, never stored).
+      constexpr bool UNR = sizeof(T) == 4 || (TET ? P <= 9 : (!DEF || P <= 7));
+      const T* g = helm + (valid ? int64_t(base + el) : 0) * (DEF ? 7 * NQ : 7);
+      T gn[DEF ? 7 : 1], ga[DEF ? 1 : 7];
+      if constexpr (DEF) {
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        const T f = tk.B(i, p), df = tk.D(i, p);
-        u += f * C0[p];
-        d1 += df * C0[p];
-        d2 += f * C1[p];
-        d3 += f * C2[p];
-      }
-      if (TET) {
-        u += uv;
-        d3 += dv;
-      }
-      const int n = i * Q2 + s;
-      T G[7];
-      if (DEF) {
-#pragma unroll
-        for (int c = 0; c < 7; ++c) G[c] = valid ? g[c * NQ + n] : T(0);
+        for (int c = 0; c < 7; ++c) gn[c] = g[c * NQ + s];
       } else {
-        const T w = valid ? wq[n] : T(0);
 #pragma unroll
-        for (int c = 0; c < 7; ++c) G[c] = valid ? g[c] * w : T(0);
+        for (int c = 0; c < 7; ++c) ga[c] = g[c];
+        gn[0] = tb.wq[s];
       }
-      const T c1 = c1k * (T(1) + tb.z[0][i]);
-      T x1, x2, x3;
-      if (TET) {
-        x1 = c00 * d1;
-        x2 = c1 * d1 + c11 * d2;
-        x3 = c1 * d1 + c12 * d2 + d3;
-      } else {
-        x1 = c00 * d1;
-        x2 = d2;
-        x3 = c1 * d1 + d3;
-      }
-      const T y1 = G[0] * x1 + G[1] * x2 + G[2] * x3;
-      const T y2 = G[1] * x1 + G[3] * x2 + G[4] * x3;
-      const T y3 = G[2] * x1 + G[4] * x2 + G[5] * x3;
-      const T m = lambda * G[6] * u;
-      T h1, h2;
-      if (TET) {
-        h1 = c00 * y1 + c1 * (y2 + y3);
-        h2 = c11 * y2 + c12 * y3;
-        vm += m;
-        v3 += y3;
-      } else {
-        h1 = c00 * y1 + c1 * y3;
-        h2 = y2;
-      }
+#pragma unroll(UNR ? Q : 1)
+      for (int i = 0; i < Q; ++i) {
+        const HexTabC<P, T> tk{fresh_table(pen)};
+        T u = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        const T f = tk.B(i, p), df = tk.D(i, p);
-        t0[p] += f * m;
-        t0[p] += df * h1;
-        t1[p] += f * h2;
-        t2[p] += f * y3;
+        for (int p = 0; p < P; ++p) {
+          const T f = tk.B(i, p), df = tk.D(i, p);
+          u += f * C0[p];
+          d1 += df * C0[p];
+          d2 += f * C1[p];
+          d3 += f * C2[p];
+        }
+        if (TET) {
+          u += uv;
+          d3 += dv;
+        }
+        T G[7];
+        if constexpr (DEF) {
+#pragma unroll
+          for (int c = 0; c < 7; ++c) G[c] = gn[c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 7; ++c) G[c] = ga[c] * gn[0];
+        }
+        const T c1 = c1k * (T(1) + tb.z[0][i]);
+        T x1, x2, x3;
+        if (TET) {
+          x1 = c00 * d1;
+          x2 = c1 * d1 + c11 * d2;
+          x3 = c1 * d1 + c12 * d2 + d3;
+        } else {
+          x1 = c00 * d1;
+          x2 = d2;
+          x3 = c1 * d1 + d3;
+        }
+        T y1 = G[0] * x1 + G[1] * x2 + G[2] * x3;
+        T y2 = G[1] * x1 + G[3] * x2 + G[4] * x3;
+        T y3 = G[2] * x1 + G[4] * x2 + G[5] * x3;
+        T m = lambda * G[6] * u;
+        if (!UNR || i + 1 < Q) {
+          // these factors are consumed: the next plane's into the same registers (unrolled, its
+          // address is opaque from here on, so the loads are issued here and not earlier)
+          asm volatile("" : "+v"(y1), "+v"(y2), "+v"(y3), "+v"(m));
+          __builtin_amdgcn_sched_barrier(0);
+          const int nn = (i + 1 < Q ? i + 1 : i) * Q2 + s;
+          const T* gp = DEF ? g + nn : tb.wq + nn;
+          if constexpr (UNR) asm volatile("" : "+v"(gp));
+          if constexpr (DEF) {
+#pragma unroll
+            for (int c = 0; c < 7; ++c) gn[c] = gp[c * NQ];
+          } else {
+            gn[0] = *gp;
+          }
+        }
+        T h1, h2;
+        if (TET) {
+          h1 = c00 * y1 + c1 * (y2 + y3);
+          h2 = c11 * y2 + c12 * y3;
+          vm += m;
+          v3 += y3;
+        } else {
+          h1 = c00 * y1 + c1 * y3;
+          h2 = y2;
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          const T f = tk.B(i, p), df = tk.D(i, p);
+          t0[p] += f * m;
+          t0[p] += df * h1;
+          t1[p] += f * h2;
+          t2[p] += f * y3;
+        }
       }
     }
     __syncthreads();

@@ -29,7 +29,7 @@ CASES = [
     (nir.HEX, 2, 0.0, 0.0, 0),
     (nir.TET, 2, 0.05, 0.0, 1),
 ]
-PS = {nir.HEX: [2, 3, 4, 5, 6, 7, 8, 9, 10], nir.PRISM: [2, 3, 5, 8, 10], nir.TET: [2, 3, 5, 8, 10]}
+PS = {c: list(range(2, 11)) for c in (nir.HEX, nir.PRISM, nir.TET)}   # every compiled order
 PARAMS = [(c, P) for c in CASES for P in PS[c[0]] if (c[3] == 1 or c[2] > 0 or P in (2, 5))]
 
 _CACHE = {}
