@@ -32,7 +32,7 @@ __attribute__((amdgpu_waves_per_eu(col_waves_target<SHAPE, P, T>())))
 template <int SHAPE, int P, class T>
 nir_status launch_col_PT(const nir_basis* b, int deformed, const OpArgs& a, hipStream_t s) {
   using D = ColDims<SHAPE, P, T>;
-  static_assert(D::LDS * sizeof(T) <= 65536, "LDS budget");
+  static_assert(D::LDS * sizeof(T) <= D::LDS_BYTES, "LDS budget");
   DevTab<T> tb;
   const T* pen;
   if constexpr (sizeof(T) == 8) {

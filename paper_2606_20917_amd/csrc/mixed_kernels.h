@@ -48,7 +48,7 @@ template <int S, int P, class T>
 struct MixedCol {
   static constexpr int Q = P + 1;
   static constexpr int E0 = (64 / Q) < (kMixedBlock / (Q * Q)) ? (64 / Q) : (kMixedBlock / (Q * Q));
-  static constexpr int E = E0 < ColDims<S, P, T>::EL ? E0 : ColDims<S, P, T>::EL;
+  static constexpr int E = E0 < ColDims<S, P, T>::EL64 ? E0 : ColDims<S, P, T>::EL64;
   using D = ColDims<S, P, T, E>;
   static constexpr int NS0 = kMixedBlock / D::BLOCK;
   static constexpr int NSL = (65536 / int(sizeof(T))) / D::LDS;
