@@ -67,9 +67,9 @@ __device__ __forceinline__ void row_fence(const T* v) {
 }
 
 // E_ = 0: the default group size: full slice wavefronts (E Q <= 64) within the LDS budget of a
-// standalone group, 64 KiB for the prism (two or more groups per CU for its HBM-bound stream) and
-// the whole 160 KiB of a CU for the tetrahedron (one group per CU, but up to 64/Q elements in
-// every slice wavefront instead of the 64 KiB share: at P = 8 in FP64, 7 elements instead of 3)
+// standalone group, half a CU's 160 KiB for the prism (two groups per CU for its HBM-bound
+// stream) and all of it for the tetrahedron (one group per CU, but up to 64/Q elements in every
+// slice wavefront instead of the 64 KiB share: at P = 8 in FP64, 7 elements instead of 3)
 template <int SHAPE, int P, class T, int E_ = 0>
 struct ColDims {
   static constexpr int Q = P + 1, Q2 = Q * Q, NQ = Q2 * Q;
@@ -80,7 +80,7 @@ struct ColDims {
   static constexpr int SLAB = MAIN + XTRA;
   static constexpr int EW = 64 / Q;                              // elements whose Q lanes fill a wavefront
   static constexpr int EL64 = (65536 / int(sizeof(T))) / SLAB;   // elements within 64 KiB of LDS
-  static constexpr int LDS_BYTES = SHAPE == kTet ? 160 * 1024 : 65536;   // standalone group budget
+  static constexpr int LDS_BYTES = SHAPE == kTet ? 160 * 1024 : 80 * 1024;   // standalone group budget
   static constexpr int EL = (LDS_BYTES / int(sizeof(T))) / SLAB;
   static constexpr int E = E_ > 0 ? E_ : (EW < EL ? EW : (EL > 0 ? EL : 1));
   static constexpr int NT = E * Q2;                              // pencil threads
