@@ -331,7 +331,8 @@ def bench_collapsed(args):
 
 def bench_ops(args):
     """The four elemental operators alone on hex_sin32 (32^3 curved hexes, per-point geometry), FP64,
-    P in {2,4,6,8,10}: GDoF/s and fraction of 8 TB/s against each operator's algorithmic bytes."""
+    P in {2,4,6,8,10}, then on prism24 and tet24 at P in {3,5,8}: GDoF/s and fraction of 8 TB/s
+    against each operator's algorithmic bytes."""
     import torch
     from paper_2606_20917_amd import nir
     dev = torch.device("cuda")
@@ -381,6 +382,54 @@ def bench_ops(args):
         out[f"P{P}"] = res
         del dxi, jac, phys, d, coef, cout
         torch.cuda.empty_cache()
+    # the collapsed shapes (LDS-staged per-element kernels): tet24 with per-element factors,
+    # prism24 with per-point factors, P in {3, 5, 8}; npts = geometry points per element
+    from paper_2606_20917_amd import inputs
+    for name, gen, shape in (("prism", inputs.prism24, nir.PRISM), ("tet", inputs.tet24, nir.TET)):
+        for P in (3, 5, 8):
+            c = gen(P)
+            Q, ne, deformed = P + 1, len(c["verts"]), c["deformed"]
+            NQ = Q ** 3
+            npts = NQ if deformed else 1
+            basis = nir.Basis(shape, P)
+            b = nir.batch(shape, P, ne, nir.F64, deformed)
+            dxi = torch.empty(ne, 9, npts, dtype=torch.float64, device=dev)
+            jac = torch.empty(ne, npts, dtype=torch.float64, device=dev)
+            nir.nir_geom_from_vertices(b, basis, torch.tensor(c["verts"], device=dev), nir.MAP_VERTEX, 0.0,
+                                       dxi, jac, None, None)
+            g = nir.geom(dxi, jac, None)
+            coef = torch.tensor(c["coef"], device=dev)
+            M = coef.shape[1]
+            phys = torch.empty(ne, NQ, dtype=torch.float64, device=dev)
+            nir.nir_bwd_trans(b, basis, coef, phys)
+            d = [torch.empty_like(phys) for _ in range(3)]
+            cout = torch.empty_like(coef)
+            ops = {
+                "bwd_trans": (lambda: nir.nir_bwd_trans(b, basis, coef, phys), 8 * (M + NQ)),
+                "iprod_wrt_base": (lambda: nir.nir_iprod_wrt_base(b, basis, g, phys, cout), 8 * (M + NQ + npts)),
+                "phys_deriv": (lambda: nir.nir_phys_deriv(b, basis, g, phys, *d), 8 * (4 * NQ + 9 * npts)),
+                "iprod_wrt_deriv_base": (lambda: nir.nir_iprod_wrt_deriv_base(b, basis, g, *d, cout),
+                                         8 * (3 * NQ + 10 * npts + M)),
+            }
+            res = {}
+            for op_name, (fn, byts) in ops.items():
+                for _ in range(args.warmup):
+                    fn()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(args.steps):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / args.steps
+                res[op_name] = {"ms": round(ms, 4), "gdofs": round(ne * M / ms / 1e6, 3),
+                                "frac_hbm": round(ne * byts / ms / 1e6 / HBM_PEAK_GBS, 4)}
+            out[f"{name}_P{P}"] = res
+            del dxi, jac, phys, d, coef, cout
+            torch.cuda.empty_cache()
+    out["config"]["collapsed"] = ("tet24 (82944 affine tets, per-element geometry) and prism24 (27648 prisms, "
+                                  "per-point geometry), P in {3,5,8}")
     out["value"] = out[f"P{ps[-1]}"]["bwd_trans"]["gdofs"]
     print(json.dumps(out), flush=True)
 
