@@ -447,7 +447,8 @@ nir_status nir_bwd_trans(const nir_batch* b, const nir_basis* basis, const void*
   a.nelmt = b->nelmt;
   if (basis->shape == kHex)
     return launch_ops_hex_pencil(basis, kOpBwd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
-  return launch_generic(basis, kOpBwd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+  if (basis->shape == kPrism) return launch_bwd_col_prism(basis, b->dtype, a, static_cast<hipStream_t>(stream));
+  return launch_bwd_col_tet(basis, b->dtype, a, static_cast<hipStream_t>(stream));
 }
 
 nir_status nir_iprod_wrt_base(const nir_batch* b, const nir_basis* basis, const nir_geom* g, const void* phys,

@@ -72,4 +72,51 @@ nir_status launch_col_shape(const nir_basis* b, int dtype, int deformed, const O
 #undef NIR_CASE
 }
 
+// BwdTrans (u = B c, eqs. (16), (17)) of the collapsed shapes: the value halves of sweeps A and B
+// of the Helmholtz group, then C writing u plane by plane (coalesced over the (j,k) pencils)
+template <int SHAPE, int P, class T>
+__global__ void __launch_bounds__((ColDims<SHAPE, P, T, 0, true>::BLOCK))
+    k_bwd_col(DevTab<T> tb, const T* __restrict__ pen, const T* __restrict__ x, T* __restrict__ y, int64_t nelmt) {
+  using D = ColDims<SHAPE, P, T, 0, true>;
+  __shared__ T lds[D::LDS];
+  helm_col_group<SHAPE, P, T, false, 0, 1, true>(tb, pen, x, y, nullptr, T(0), nelmt, int64_t(blockIdx.x) * D::E,
+                                                 lds);
+}
+
+template <int SHAPE, int P, class T>
+nir_status launch_bwd_col_PT(const nir_basis* b, const OpArgs& a, hipStream_t s) {
+  using D = ColDims<SHAPE, P, T, 0, true>;
+  static_assert(D::LDS * sizeof(T) <= D::LDS_BYTES, "LDS budget");
+  DevTab<T> tb;
+  const T* pen;
+  if constexpr (sizeof(T) == 8) {
+    tb = b->t64;
+    pen = b->pencil64;
+  } else {
+    tb = b->t32;
+    pen = b->pencil32;
+  }
+  const int64_t nb = (a.nelmt + D::E - 1) / D::E;
+  if (nb > 0x7fffffff) return fail(NIR_EINVAL, "too many elements for one launch");
+  if (nb == 0) return ok();
+  const dim3 grid(static_cast<unsigned>(nb)), block(D::BLOCK);
+  hipLaunchKernelGGL((k_bwd_col<SHAPE, P, T>), grid, block, 0, s, tb, pen, static_cast<const T*>(a.in0),
+                     static_cast<T*>(a.out0), a.nelmt);
+  return hip_check(hipGetLastError(), "collapsed BwdTrans launch");
+}
+
+template <int SHAPE>
+nir_status launch_bwd_col_shape(const nir_basis* b, int dtype, const OpArgs& a, hipStream_t s) {
+#define NIR_CASE(PP)                                                           \
+  case PP:                                                                     \
+    return dtype == NIR_F64 ? launch_bwd_col_PT<SHAPE, PP, double>(b, a, s)    \
+                            : launch_bwd_col_PT<SHAPE, PP, float>(b, a, s);
+  switch (b->P) {
+    NIR_CASE(2) NIR_CASE(3) NIR_CASE(4) NIR_CASE(5) NIR_CASE(6)
+    NIR_CASE(7) NIR_CASE(8) NIR_CASE(9) NIR_CASE(10)
+    default: return fail(NIR_ENOTSUP, "P=%d not compiled", b->P);
+  }
+#undef NIR_CASE
+}
+
 }  // namespace nir

@@ -70,14 +70,16 @@ __device__ __forceinline__ void row_fence(const T* v) {
 // standalone group, half a CU's 160 KiB for the prism (two groups per CU for its HBM-bound
 // stream) and all of it for the tetrahedron (one group per CU, but up to 64/Q elements in every
 // slice wavefront instead of the 64 KiB share: at P = 8 in FP64, 7 elements instead of 3)
-template <int SHAPE, int P, class T, int E_ = 0>
+// BWD: the backward transform alone, whose stages touch only the first P Q^2 values of an
+// element's region (coefficients, value rows of A, value planes of B)
+template <int SHAPE, int P, class T, int E_ = 0, bool BWD = false>
 struct ColDims {
   static constexpr int Q = P + 1, Q2 = Q * Q, NQ = Q2 * Q;
   static constexpr int M = SHAPE == kPrism ? P * P * (P + 1) / 2 : P * (P + 1) * (P + 2) / 6;
   static constexpr int NP = SHAPE == kTet ? P * (P + 1) / 2 : P * P;
   static constexpr int MAIN = 3 * P * Q2;
   static constexpr int XTRA = SHAPE == kTet ? Q2 + 3 * Q : 0;   // vertex partials, x0, x1, vertex row
-  static constexpr int SLAB = MAIN + XTRA;
+  static constexpr int SLAB = BWD ? P * Q2 : MAIN + XTRA;
   static constexpr int EW = 64 / Q;                              // elements whose Q lanes fill a wavefront
   static constexpr int EL64 = (65536 / int(sizeof(T))) / SLAB;   // elements within 64 KiB of LDS
   static constexpr int LDS_BYTES = SHAPE == kTet ? 160 * 1024 : 80 * 1024;   // standalone group budget
@@ -101,16 +103,18 @@ __device__ __forceinline__ void col_dispatch(int v, F& f) {
   }
 }
 
+// BWD: the backward transform only (u = B c at the points, into y[nelmt][Q^3]): the value
+// halves of A and B, then C without the pointwise step; helm and lambda are not used.
 // One call processes NSUB independent groups of E elements, group g starting at element
 // base + g E, on a block of at least NSUB * ColDims::BLOCK threads (g = wavefront / NW; the
 // wavefronts past the last group only take part in the barriers); `lds` holds NSUB * LDS
 // values.  Every thread of the block must call it (it synchronises).
 // pen: the direction-1 factor and its derivative in [point][mode] layout (B then B').
-template <int SHAPE, int P, class T, bool DEF, int E_ = 0, int NSUB = 1>
+template <int SHAPE, int P, class T, bool DEF, int E_ = 0, int NSUB = 1, bool BWD = false>
 __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __restrict__ pen, const T* __restrict__ x,
                                                T* __restrict__ y, const T* __restrict__ helm, T lambda, int64_t nelmt,
                                                int64_t base0, T* __restrict__ lds0) {
-  using D = ColDims<SHAPE, P, T, E_>;
+  using D = ColDims<SHAPE, P, T, E_, BWD>;
   using MO = ColModes<SHAPE, P>;
   constexpr int Q = D::Q, Q2 = D::Q2, NQ = D::NQ, M = D::M, NP = D::NP, E = D::E, SLAB = D::SLAB,
                 MAIN = D::MAIN, BLOCK = D::BLOCK;
@@ -179,7 +183,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
             a0[k] = v0;
             a1[k] = v1;
             row_fence<1>(&a0[k]);
-            row_fence<1>(&a1[k]);
+            if constexpr (!BWD) row_fence<1>(&a1[k]);
           }
           dst = MO::pair(p, q);
         }
@@ -211,7 +215,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
             a0[k] = v0;
             a1[k] = v1;
             row_fence<1>(&a0[k]);
-            row_fence<1>(&a1[k]);
+            if constexpr (!BWD) row_fence<1>(&a1[k]);
           }
           dst = MO::pair(p, q);
         }
@@ -223,7 +227,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
         Ls[dst * Q + k] = a0[k];
-        Ls[NP * Q + dst * Q + k] = a1[k];
+        if constexpr (!BWD) Ls[NP * Q + dst * Q + k] = a1[k];
       }
     }
     __syncthreads();
@@ -243,11 +247,11 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 #pragma unroll
         for (int q = 0; q < nq; ++q) {
           av[q] = Ls[MO::pair(p, q) * Q + k];
-          bv[q] = Ls[NP * Q + MO::pair(p, q) * Q + k];
+          if constexpr (!BWD) bv[q] = Ls[NP * Q + MO::pair(p, q) * Q + k];
         }
         if (X) {
           av[nq] = Ls[MO::pair(0, 1) * Q + k];
-          bv[nq] = Ls[NP * Q + MO::pair(0, 1) * Q + k];
+          if constexpr (!BWD) bv[nq] = Ls[NP * Q + MO::pair(0, 1) * Q + k];
         }
         // one row of terms per point j (transposed table), the pair (0,1) term last for X
         constexpr int nt = col_b_terms(SHAPE, P, p), off = col_b_off(SHAPE, P, p);
@@ -261,15 +265,19 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 #pragma unroll
           for (int q = 0; q < nt; ++q) {
             v0 += f[q] * av[q];
-            v1 += df[q] * av[q];
-            v2 += f[q] * bv[q];
+            if constexpr (!BWD) {
+              v1 += df[q] * av[q];
+              v2 += f[q] * bv[q];
+            }
           }
           b0[j] = v0;
           b1[j] = v1;
           b2[j] = v2;
           row_fence<1>(&b0[j]);
-          row_fence<1>(&b1[j]);
-          row_fence<1>(&b2[j]);
+          if constexpr (!BWD) {
+            row_fence<1>(&b1[j]);
+            row_fence<1>(&b2[j]);
+          }
         }
         pw = p;
       }
@@ -280,11 +288,33 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
         Ls[pw * Q2 + j * Q + k] = b0[j];
-        Ls[PQ2 + pw * Q2 + j * Q + k] = b1[j];
-        Ls[2 * PQ2 + pw * Q2 + j * Q + k] = b2[j];
+        if constexpr (!BWD) {
+          Ls[PQ2 + pw * Q2 + j * Q + k] = b1[j];
+          Ls[2 * PQ2 + pw * Q2 + j * Q + k] = b2[j];
+        }
       }
     }
     __syncthreads();
+  }
+
+  // ---- BWD: C alone, u at the points of each (j,k) pencil plane by plane into y
+  if constexpr (BWD) {
+    T C0[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) C0[p] = act ? L[p * Q2 + s] : T(0);
+    const T uv = TET ? c001 * tb.T3[1 * Q + (act ? kk : 0)] : T(0);   // tet vertex mode
+    if (valid) {
+      T* __restrict__ yo = y + int64_t(base + el) * NQ + s;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const HexTabC<P, T> tk{fresh_table(pen)};
+        T u = uv;
+#pragma unroll
+        for (int p = 0; p < P; ++p) u += tk.B(i, p) * C0[p];
+        yo[i * Q2] = u;
+      }
+    }
+    return;
   }
 
   // ---- C, pointwise, C^T fused over the (j,k) pencils, streamed over i (the wavefronts without
