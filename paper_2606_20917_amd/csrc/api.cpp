@@ -470,7 +470,9 @@ nir_status nir_iprod_wrt_base(const nir_batch* b, const nir_basis* basis, const 
   a.nelmt = b->nelmt;
   if (basis->shape == kHex)
     return launch_ops_hex_pencil(basis, kOpIProd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
-  return launch_generic(basis, kOpIProd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+  if (basis->shape == kPrism)
+    return launch_iprod_col_prism(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+  return launch_iprod_col_tet(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
 }
 
 nir_status nir_phys_deriv(const nir_batch* b, const nir_basis* basis, const nir_geom* g, const void* phys,

@@ -70,16 +70,17 @@ __device__ __forceinline__ void row_fence(const T* v) {
 // standalone group, half a CU's 160 KiB for the prism (two groups per CU for its HBM-bound
 // stream) and all of it for the tetrahedron (one group per CU, but up to 64/Q elements in every
 // slice wavefront instead of the 64 KiB share: at P = 8 in FP64, 7 elements instead of 3)
-// BWD: the backward transform alone, whose stages touch only the first P Q^2 values of an
-// element's region (coefficients, value rows of A, value planes of B)
-template <int SHAPE, int P, class T, int E_ = 0, bool BWD = false>
+// OPM: 0 the Helmholtz apply; 1 the backward transform alone, whose stages touch only the first
+// P Q^2 values of an element's region (coefficients, value rows of A, value planes of B); 2 the
+// inner product with the basis alone (value planes of C^T, then the tet's vertex region at P Q^2)
+template <int SHAPE, int P, class T, int E_ = 0, int OPM = 0>
 struct ColDims {
   static constexpr int Q = P + 1, Q2 = Q * Q, NQ = Q2 * Q;
   static constexpr int M = SHAPE == kPrism ? P * P * (P + 1) / 2 : P * (P + 1) * (P + 2) / 6;
   static constexpr int NP = SHAPE == kTet ? P * (P + 1) / 2 : P * P;
-  static constexpr int MAIN = 3 * P * Q2;
+  static constexpr int MAIN = (OPM == 0 ? 3 : 1) * P * Q2;
   static constexpr int XTRA = SHAPE == kTet ? Q2 + 3 * Q : 0;   // vertex partials, x0, x1, vertex row
-  static constexpr int SLAB = BWD ? P * Q2 : MAIN + XTRA;
+  static constexpr int SLAB = OPM == 1 ? P * Q2 : MAIN + XTRA;
   static constexpr int EW = 64 / Q;                              // elements whose Q lanes fill a wavefront
   static constexpr int EL64 = (65536 / int(sizeof(T))) / SLAB;   // elements within 64 KiB of LDS
   static constexpr int LDS_BYTES = SHAPE == kTet ? 160 * 1024 : 80 * 1024;   // standalone group budget
@@ -103,18 +104,22 @@ __device__ __forceinline__ void col_dispatch(int v, F& f) {
   }
 }
 
-// BWD: the backward transform only (u = B c at the points, into y[nelmt][Q^3]): the value
+// OPM = 1: the backward transform only (u = B c at the points, into y[nelmt][Q^3]): the value
 // halves of A and B, then C without the pointwise step; helm and lambda are not used.
+// OPM = 2: the inner product with the basis only (y = B^T W u for u = x[nelmt][Q^3], W = w |J|
+// with |J| in helm, per point or per element as DEF): C^T of the mass term alone, then the value
+// halves of B^T and A^T; lambda is not used.
 // One call processes NSUB independent groups of E elements, group g starting at element
 // base + g E, on a block of at least NSUB * ColDims::BLOCK threads (g = wavefront / NW; the
 // wavefronts past the last group only take part in the barriers); `lds` holds NSUB * LDS
 // values.  Every thread of the block must call it (it synchronises).
 // pen: the direction-1 factor and its derivative in [point][mode] layout (B then B').
-template <int SHAPE, int P, class T, bool DEF, int E_ = 0, int NSUB = 1, bool BWD = false>
+template <int SHAPE, int P, class T, bool DEF, int E_ = 0, int NSUB = 1, int OPM = 0>
 __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __restrict__ pen, const T* __restrict__ x,
                                                T* __restrict__ y, const T* __restrict__ helm, T lambda, int64_t nelmt,
                                                int64_t base0, T* __restrict__ lds0) {
-  using D = ColDims<SHAPE, P, T, E_, BWD>;
+  using D = ColDims<SHAPE, P, T, E_, OPM>;
+  constexpr bool BWD = OPM == 1, IPR = OPM == 2;
   using MO = ColModes<SHAPE, P>;
   constexpr int Q = D::Q, Q2 = D::Q2, NQ = D::NQ, M = D::M, NP = D::NP, E = D::E, SLAB = D::SLAB,
                 MAIN = D::MAIN, BLOCK = D::BLOCK;
@@ -142,7 +147,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
   T* L = lds + (act ? el : 0) * SLAB;
 
   // ---- stage the coefficients (coalesced)
-  for (int f = t; f < ne * M; f += BLOCK) {
+  for (int f = t; f < (IPR ? 0 : ne * M); f += BLOCK) {
     const int e2 = f / M;
     lds[e2 * SLAB + (f - e2 * M)] = x[base * M + f];
   }
@@ -150,8 +155,8 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 
   // ---- A: r -> k, one slice (tet: s = p+q, prism: p) per wavefront
   T c001 = T(0);
-  if (TET && act) c001 = L[1];
-  {
+  if (TET && !IPR && act) c001 = L[1];
+  if constexpr (!IPR) {
     T a0[Q], a1[Q];
     int dst = -1;   // pair row written by this lane
     T* Ls = lds;
@@ -234,7 +239,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
   }
 
   // ---- B: q -> j, one p per wavefront, lanes (element, k)
-  {
+  if constexpr (!IPR) {
     T b0[Q], b1[Q], b2[Q];
     const int e2 = lane / Q, k = lane - e2 * Q;
     T* Ls = lds + (e2 < E ? e2 : 0) * SLAB;
@@ -317,9 +322,37 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
     return;
   }
 
+  // ---- IPR: C^T of the mass term alone, m = u w |J| at the points of each (j,k) pencil
+  if constexpr (IPR) {
+    T t0[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) t0[p] = T(0);
+    T vm = T(0);
+    if (in && wave < D::NWP) {
+      // lanes past the batch end read element 0's values (in bounds, never stored)
+      const int64_t ev = valid ? int64_t(base + el) : 0;
+      const T* __restrict__ u = x + ev * NQ + s;
+      const T* __restrict__ jac = helm + ev * (DEF ? NQ : 1) + (DEF ? s : 0);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const HexTabC<P, T> tk{fresh_table(pen)};
+        const T m = u[i * Q2] * tb.wq[i * Q2 + s] * jac[DEF ? i * Q2 : 0];
+#pragma unroll
+        for (int p = 0; p < P; ++p) t0[p] += tk.B(i, p) * m;
+        vm += m;
+      }
+    }
+    if (act) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) L[p * Q2 + s] = t0[p];
+      if (TET) L[MAIN + s] = tb.T3[1 * Q + kk] * vm;
+    }
+    __syncthreads();
+  }
+
   // ---- C, pointwise, C^T fused over the (j,k) pencils, streamed over i (the wavefronts without
   // pencils go straight to the barrier)
-  {
+  if constexpr (!IPR) {
     T C0[P], C1[P], C2[P];
     T t0[P], t1[P], t2[P];
 #pragma unroll
@@ -472,8 +505,10 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 #pragma unroll
         for (int j = 0; j < Q; ++j) {
           tv0[j] = Ls[p * Q2 + j * Q + k];
-          tv1[j] = Ls[PQ2 + p * Q2 + j * Q + k];
-          tv2[j] = Ls[2 * PQ2 + p * Q2 + j * Q + k];
+          if constexpr (!IPR) {
+            tv1[j] = Ls[PQ2 + p * Q2 + j * Q + k];
+            tv2[j] = Ls[2 * PQ2 + p * Q2 + j * Q + k];
+          }
         }
         if (TET && p == 0) {
 #pragma unroll
@@ -486,17 +521,19 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
         for (int q = 0; q < nt; ++q) s0[q] = s1[q] = T(0);
 #pragma unroll
         for (int j = 0; j < Q; ++j) {
-          const T dep = j > 0 ? s1[nt - 1] : tv0[0];
+          const T dep = j > 0 ? (IPR ? s0[nt - 1] : s1[nt - 1]) : tv0[0];
           const const_ptr<T> f = fresh_table_after(tb.T2t, dep) + (off + j * nt);
           const const_ptr<T> df = fresh_table_after(tb.dT2t, dep) + (off + j * nt);
 #pragma unroll
           for (int q = 0; q < nt; ++q) {
             s0[q] += f[q] * tv0[j];
-            s0[q] += df[q] * tv1[j];
-            s1[q] += f[q] * tv2[j];
+            if constexpr (!IPR) {
+              s0[q] += df[q] * tv1[j];
+              s1[q] += f[q] * tv2[j];
+            }
           }
           row_fence<nt>(s0);
-          row_fence<nt>(s1);
+          if constexpr (!IPR) row_fence<nt>(s1);
         }
         pw = p;
       }
@@ -511,11 +548,11 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 #pragma unroll
         for (int q = 0; q < nq; ++q) {
           Ls[MO::pair(p, q) * Q + k] = s0[q];
-          Ls[NP * Q + MO::pair(p, q) * Q + k] = s1[q];
+          if constexpr (!IPR) Ls[NP * Q + MO::pair(p, q) * Q + k] = s1[q];
         }
         if (TET && p == 1) {
           Ls[MAIN + Q2 + k] = s0[nq];
-          Ls[MAIN + Q2 + Q + k] = s1[nq];
+          if constexpr (!IPR) Ls[MAIN + Q2 + Q + k] = s1[nq];
         }
         if (TET && p == 0) Ls[MAIN + Q2 + 2 * Q + k] = sx;
       };
@@ -542,7 +579,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 #pragma unroll
           for (int k = 0; k < Q; ++k) {
             sv0[k] = Ls[pr * Q + k] + (x01 ? Ls[MAIN + Q2 + k] : T(0));
-            sv1[k] = Ls[NP * Q + pr * Q + k] + (x01 ? Ls[MAIN + Q2 + Q + k] : T(0));
+            if constexpr (!IPR) sv1[k] = Ls[NP * Q + pr * Q + k] + (x01 ? Ls[MAIN + Q2 + Q + k] : T(0));
           }
           // outer loop over the points k, one row of terms per point (transposed table); the
           // vertex mode (0,0,1) of slice 0 takes the sum of its row instead
@@ -558,7 +595,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
             for (int r = 0; r < nr; ++r) {
               if (sl == 0 && r == 1) continue;
               yv[r] += f[r] * sv0[k];
-              yv[r] += df[r] * sv1[k];
+              if constexpr (!IPR) yv[r] += df[r] * sv1[k];
             }
             row_fence<nr>(yv);
           }
@@ -581,10 +618,12 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 #pragma unroll
           for (int k = 0; k < Q; ++k) {
             sv0[k] = Ls[pr * Q + k];
-            sv1[k] = Ls[NP * Q + pr * Q + k];
             // (0,q,1) modes also see the p = 1 rows
             xv0[k] = p == 0 ? Ls[MO::pair(1, q) * Q + k] : T(0);
-            xv1[k] = p == 0 ? Ls[NP * Q + MO::pair(1, q) * Q + k] : T(0);
+            if constexpr (!IPR) {
+              sv1[k] = Ls[NP * Q + pr * Q + k];
+              xv1[k] = p == 0 ? Ls[NP * Q + MO::pair(1, q) * Q + k] : T(0);
+            }
           }
           // outer loop over the points k, one row of terms per point (transposed table, whose
           // p = 1 rows carry one more term, not used here)
@@ -600,10 +639,10 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
             for (int r = 0; r < nr; ++r) {
               if (p == 0 && r == 1) {
                 yv[r] += f[r] * (sv0[k] + xv0[k]);
-                yv[r] += df[r] * (sv1[k] + xv1[k]);
+                if constexpr (!IPR) yv[r] += df[r] * (sv1[k] + xv1[k]);
               } else {
                 yv[r] += f[r] * sv0[k];
-                yv[r] += df[r] * sv1[k];
+                if constexpr (!IPR) yv[r] += df[r] * sv1[k];
               }
             }
             row_fence<nr>(yv);

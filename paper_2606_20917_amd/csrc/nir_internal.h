@@ -191,6 +191,9 @@ nir_status launch_helm_col_tet(const nir_basis* b, int dtype, int deformed, cons
 // BwdTrans of prisms / tetrahedra with the register-pencil sweeps of the collapsed Helmholtz kernel
 nir_status launch_bwd_col_prism(const nir_basis* b, int dtype, const OpArgs& a, hipStream_t s);
 nir_status launch_bwd_col_tet(const nir_basis* b, int dtype, const OpArgs& a, hipStream_t s);
+// IProductWRTBase of prisms / tetrahedra with the transposed register-pencil sweeps
+nir_status launch_iprod_col_prism(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
+nir_status launch_iprod_col_tet(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
 
 nir_status launch_helm_hex_f16split(const nir_basis* b, int deformed, const OpArgs& a, hipStream_t s);
 // the fused Helmholtz apply with the currently selected kernel variant (native contractions)
