@@ -504,6 +504,10 @@ nir_status nir_phys_deriv(const nir_batch* b, const nir_basis* basis, const nir_
   // hex pencils from P = 3 (at P = 2 the generic layout, 32 threads over 27 points, measured faster)
   if (basis->shape == kHex && basis->P >= 3)
     return launch_ops_hex_pencil(basis, kOpPhysDeriv, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+  if (basis->shape == kPrism)
+    return launch_phys_deriv_col_prism(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+  if (basis->shape == kTet)
+    return launch_phys_deriv_col_tet(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
   return launch_generic(basis, kOpPhysDeriv, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
 }
 

@@ -172,4 +172,160 @@ nir_status launch_iprod_col_shape(const nir_basis* b, int dtype, int deformed, c
 #undef NIR_CASE
 }
 
+// PhysDeriv (eqs. (9), (22), (23)) of the collapsed shapes from values at the points: collocation
+// derivatives along eta_1, eta_2, eta_3 with each direction's own 1-D matrix, each thread taking
+// the pencil roles (j,k) (i-derivative, in registers), (i,k) and (i,j) (j- and k-derivatives,
+// through two Q^3 LDS planes), then per point the eta -> xi chain rule of the collapsed
+// coordinates and the physical directions from d xi_a / d x_i (per point or per element, DEF)
+template <int P, class T>
+struct ColGradDims {
+  static constexpr int Q = P + 1, Q2 = Q * Q, NQ = Q2 * Q;
+  static constexpr int E = 256 / Q2;
+  static constexpr int BLOCK = (E * Q2 + 63) / 64 * 64;
+  static constexpr int SLAB = 2 * NQ;
+  static constexpr int LDS = E * SLAB;
+};
+
+template <int SHAPE, int P, class T, bool DEF>
+__global__ void __launch_bounds__(256) k_phys_deriv_col(DevTab<T> tb, const T* __restrict__ u,
+                                                        const T* __restrict__ dxi, T* __restrict__ o0,
+                                                        T* __restrict__ o1, T* __restrict__ o2, int64_t nelmt) {
+  using D = ColGradDims<P, T>;
+  constexpr int Q = D::Q, Q2 = D::Q2, NQ = D::NQ, E = D::E, SLAB = D::SLAB, BLOCK = D::BLOCK;
+  __shared__ T lds[D::LDS];
+  const int64_t base = int64_t(blockIdx.x) * E;
+  const int ne = int(min(int64_t(E), nelmt - base));
+  const int t = threadIdx.x;
+  const int el = t / Q2, s = t - el * Q2;
+  const bool act = el < E;
+  const bool valid = act && el < ne;
+  T* L = lds + (act ? el : 0) * SLAB;
+  const int hi = s / Q, lo = s - hi * Q;   // (j,k), (i,k) or (i,j) depending on the role
+
+  for (int f = t; f < ne * NQ; f += BLOCK) {
+    const int e2 = f / NQ;
+    lds[e2 * SLAB + (f - e2 * NQ)] = u[base * NQ + f];
+  }
+  __syncthreads();
+
+  T d1[Q], d2[Q], d3[Q];
+  if (act) {
+    T v[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) v[l] = L[l * Q2 + s];   // role (j,k): along eta_1
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const const_ptr<T> row = fresh_table(tb.D[0]) + i * Q;
+      T a = T(0);
+#pragma unroll
+      for (int l = 0; l < Q; ++l) a += row[l] * v[l];
+      d1[i] = a;
+    }
+#pragma unroll
+    for (int l = 0; l < Q; ++l) v[l] = L[hi * Q2 + l * Q + lo];   // role (i,k): along eta_2
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const const_ptr<T> row = fresh_table(tb.D[1]) + j * Q;
+      T a = T(0);
+#pragma unroll
+      for (int l = 0; l < Q; ++l) a += row[l] * v[l];
+      d2[j] = a;
+    }
+#pragma unroll
+    for (int l = 0; l < Q; ++l) v[l] = L[hi * Q2 + lo * Q + l];   // role (i,j): along eta_3
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const const_ptr<T> row = fresh_table(tb.D[2]) + k * Q;
+      T a = T(0);
+#pragma unroll
+      for (int l = 0; l < Q; ++l) a += row[l] * v[l];
+      d3[k] = a;
+    }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) L[hi * Q2 + j * Q + lo] = d2[j];        // plane A [i][j][k]
+#pragma unroll
+    for (int k = 0; k < Q; ++k) L[NQ + hi * Q2 + lo * Q + k] = d3[k];   // plane B [i][j][k]
+  }
+  __syncthreads();
+  if (valid) {
+    // chain-rule factors of the (j,k) pencil (eq. (23)); c01 = c02 = c1k (1 + eta_1) for the
+    // tet, c02 = c1k (1 + eta_1) and c01 = 0 for the prism
+    const T e2v = tb.z[1][hi], e3v = tb.z[2][lo];
+    T c00, c1k, c11, c12;
+    if (SHAPE == kTet) {
+      const T r3 = T(1) / (T(1) - e3v);
+      const T ra = r3 / (T(1) - e2v);
+      c00 = T(4) * ra;
+      c1k = T(2) * ra;
+      c11 = T(2) * r3;
+      c12 = (T(1) + e2v) * r3;
+    } else {
+      const T r3 = T(1) / (T(1) - e3v);
+      c00 = T(2) * r3;
+      c1k = r3;
+      c11 = T(1);
+      c12 = T(0);
+    }
+    const int64_t e = base + el;
+    const int64_t gb = e * 9 * (DEF ? NQ : 1), gs = DEF ? NQ : 1;
+#pragma unroll 1
+    for (int i = 0; i < Q; ++i) {
+      const int n = i * Q2 + s;
+      const int64_t gp = gb + (DEF ? n : 0);
+      T g[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) g[c] = dxi[gp + c * gs];
+      const T c1 = c1k * (T(1) + tb.z[0][i]);
+      const T y1 = d1[i], y2 = L[n], y3 = L[NQ + n];
+      const T x1 = c00 * y1;
+      const T x2 = (SHAPE == kTet ? c1 * y1 : T(0)) + c11 * y2;
+      const T x3 = c1 * y1 + c12 * y2 + y3;
+      o0[e * NQ + n] = g[0] * x1 + g[3] * x2 + g[6] * x3;
+      o1[e * NQ + n] = g[1] * x1 + g[4] * x2 + g[7] * x3;
+      o2[e * NQ + n] = g[2] * x1 + g[5] * x2 + g[8] * x3;
+    }
+  }
+}
+
+template <int SHAPE, int P, class T>
+nir_status launch_phys_deriv_col_PT(const nir_basis* b, int deformed, const OpArgs& a, hipStream_t s) {
+  using D = ColGradDims<P, T>;
+  DevTab<T> tb;
+  if constexpr (sizeof(T) == 8)
+    tb = b->t64;
+  else
+    tb = b->t32;
+  const int64_t nb = (a.nelmt + D::E - 1) / D::E;
+  if (nb > 0x7fffffff) return fail(NIR_EINVAL, "too many elements for one launch");
+  if (nb == 0) return ok();
+  const dim3 grid(static_cast<unsigned>(nb)), block(D::BLOCK);
+  const T* u = static_cast<const T*>(a.in0);
+  const T* dxi = static_cast<const T*>(a.dxi_dx);
+  T* o0 = static_cast<T*>(a.out0);
+  T* o1 = static_cast<T*>(a.out1);
+  T* o2 = static_cast<T*>(a.out2);
+  if (deformed)
+    hipLaunchKernelGGL((k_phys_deriv_col<SHAPE, P, T, true>), grid, block, 0, s, tb, u, dxi, o0, o1, o2, a.nelmt);
+  else
+    hipLaunchKernelGGL((k_phys_deriv_col<SHAPE, P, T, false>), grid, block, 0, s, tb, u, dxi, o0, o1, o2, a.nelmt);
+  return hip_check(hipGetLastError(), "collapsed PhysDeriv launch");
+}
+
+template <int SHAPE>
+nir_status launch_phys_deriv_col_shape(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
+#define NIR_CASE(PP)                                                                            \
+  case PP:                                                                                      \
+    return dtype == NIR_F64 ? launch_phys_deriv_col_PT<SHAPE, PP, double>(b, deformed, a, s)    \
+                            : launch_phys_deriv_col_PT<SHAPE, PP, float>(b, deformed, a, s);
+  switch (b->P) {
+    NIR_CASE(2) NIR_CASE(3) NIR_CASE(4) NIR_CASE(5) NIR_CASE(6)
+    NIR_CASE(7) NIR_CASE(8) NIR_CASE(9) NIR_CASE(10)
+    default: return fail(NIR_ENOTSUP, "P=%d not compiled", b->P);
+  }
+#undef NIR_CASE
+}
+
 }  // namespace nir

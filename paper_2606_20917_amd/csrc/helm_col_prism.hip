@@ -11,4 +11,7 @@ nir_status launch_bwd_col_prism(const nir_basis* b, int dtype, const OpArgs& a, 
 nir_status launch_iprod_col_prism(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
   return launch_iprod_col_shape<kPrism>(b, dtype, deformed, a, s);
 }
+nir_status launch_phys_deriv_col_prism(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
+  return launch_phys_deriv_col_shape<kPrism>(b, dtype, deformed, a, s);
+}
 }  // namespace nir
