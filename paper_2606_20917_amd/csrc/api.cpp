@@ -539,6 +539,10 @@ nir_status nir_iprod_wrt_deriv_base(const nir_batch* b, const nir_basis* basis, 
   // hex pencils from P = 3 (at P = 2 the generic layout, 32 threads over 27 points, measured faster)
   if (basis->shape == kHex && basis->P >= 3)
     return launch_ops_hex_pencil(basis, kOpIProdDeriv, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+  if (basis->shape == kPrism)
+    return launch_iprod_deriv_col_prism(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+  if (basis->shape == kTet)
+    return launch_iprod_deriv_col_tet(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
   return launch_generic(basis, kOpIProdDeriv, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
 }
 

@@ -172,6 +172,65 @@ nir_status launch_iprod_col_shape(const nir_basis* b, int dtype, int deformed, c
 #undef NIR_CASE
 }
 
+// IProductWRTDerivBase (y = sum_i (D_{x_i} B)^T W f_i, eq. (7)) of the collapsed shapes: the xi
+// fluxes of the three fields at the points, then the transposed sweeps of the Helmholtz group
+template <int SHAPE, int P, class T, bool DEF>
+__global__ void __launch_bounds__((ColDims<SHAPE, P, T, 0, 3>::BLOCK))
+    k_iprod_deriv_col(DevTab<T> tb, const T* __restrict__ pen, const T* __restrict__ f0, const T* __restrict__ f1,
+                      const T* __restrict__ f2, T* __restrict__ y, const T* __restrict__ dxi,
+                      const T* __restrict__ jac, int64_t nelmt) {
+  using D = ColDims<SHAPE, P, T, 0, 3>;
+  __shared__ T lds[D::LDS];
+  helm_col_group<SHAPE, P, T, DEF, 0, 1, 3>(tb, pen, f0, y, dxi, T(0), nelmt, int64_t(blockIdx.x) * D::E, lds, f1,
+                                            f2, jac);
+}
+
+template <int SHAPE, int P, class T>
+nir_status launch_iprod_deriv_col_PT(const nir_basis* b, int deformed, const OpArgs& a, hipStream_t s) {
+  using D = ColDims<SHAPE, P, T, 0, 3>;
+  static_assert(D::LDS * sizeof(T) <= D::LDS_BYTES, "LDS budget");
+  DevTab<T> tb;
+  const T* pen;
+  if constexpr (sizeof(T) == 8) {
+    tb = b->t64;
+    pen = b->pencil64;
+  } else {
+    tb = b->t32;
+    pen = b->pencil32;
+  }
+  const int64_t nb = (a.nelmt + D::E - 1) / D::E;
+  if (nb > 0x7fffffff) return fail(NIR_EINVAL, "too many elements for one launch");
+  if (nb == 0) return ok();
+  const dim3 grid(static_cast<unsigned>(nb)), block(D::BLOCK);
+  const T* f0 = static_cast<const T*>(a.in0);
+  const T* f1 = static_cast<const T*>(a.in1);
+  const T* f2 = static_cast<const T*>(a.in2);
+  T* y = static_cast<T*>(a.out0);
+  const T* dxi = static_cast<const T*>(a.dxi_dx);
+  const T* jac = static_cast<const T*>(a.jac);
+  if (deformed)
+    hipLaunchKernelGGL((k_iprod_deriv_col<SHAPE, P, T, true>), grid, block, 0, s, tb, pen, f0, f1, f2, y, dxi, jac,
+                       a.nelmt);
+  else
+    hipLaunchKernelGGL((k_iprod_deriv_col<SHAPE, P, T, false>), grid, block, 0, s, tb, pen, f0, f1, f2, y, dxi, jac,
+                       a.nelmt);
+  return hip_check(hipGetLastError(), "collapsed IProductWRTDerivBase launch");
+}
+
+template <int SHAPE>
+nir_status launch_iprod_deriv_col_shape(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
+#define NIR_CASE(PP)                                                                             \
+  case PP:                                                                                       \
+    return dtype == NIR_F64 ? launch_iprod_deriv_col_PT<SHAPE, PP, double>(b, deformed, a, s)    \
+                            : launch_iprod_deriv_col_PT<SHAPE, PP, float>(b, deformed, a, s);
+  switch (b->P) {
+    NIR_CASE(2) NIR_CASE(3) NIR_CASE(4) NIR_CASE(5) NIR_CASE(6)
+    NIR_CASE(7) NIR_CASE(8) NIR_CASE(9) NIR_CASE(10)
+    default: return fail(NIR_ENOTSUP, "P=%d not compiled", b->P);
+  }
+#undef NIR_CASE
+}
+
 // PhysDeriv (eqs. (9), (22), (23)) of the collapsed shapes from values at the points: collocation
 // derivatives along eta_1, eta_2, eta_3 with each direction's own 1-D matrix, each thread taking
 // the pencil roles (j,k) (i-derivative, in registers), (i,k) and (i,j) (j- and k-derivatives,

@@ -72,13 +72,14 @@ __device__ __forceinline__ void row_fence(const T* v) {
 // slice wavefront instead of the 64 KiB share: at P = 8 in FP64, 7 elements instead of 3)
 // OPM: 0 the Helmholtz apply; 1 the backward transform alone, whose stages touch only the first
 // P Q^2 values of an element's region (coefficients, value rows of A, value planes of B); 2 the
-// inner product with the basis alone (value planes of C^T, then the tet's vertex region at P Q^2)
+// inner product with the basis alone (value planes of C^T, then the tet's vertex region at P Q^2);
+// 3 the inner product with the derivative basis (the Helmholtz layout)
 template <int SHAPE, int P, class T, int E_ = 0, int OPM = 0>
 struct ColDims {
   static constexpr int Q = P + 1, Q2 = Q * Q, NQ = Q2 * Q;
   static constexpr int M = SHAPE == kPrism ? P * P * (P + 1) / 2 : P * (P + 1) * (P + 2) / 6;
   static constexpr int NP = SHAPE == kTet ? P * (P + 1) / 2 : P * P;
-  static constexpr int MAIN = (OPM == 0 ? 3 : 1) * P * Q2;
+  static constexpr int MAIN = (OPM == 0 || OPM == 3 ? 3 : 1) * P * Q2;
   static constexpr int XTRA = SHAPE == kTet ? Q2 + 3 * Q : 0;   // vertex partials, x0, x1, vertex row
   static constexpr int SLAB = OPM == 1 ? P * Q2 : MAIN + XTRA;
   static constexpr int EW = 64 / Q;                              // elements whose Q lanes fill a wavefront
@@ -109,6 +110,10 @@ __device__ __forceinline__ void col_dispatch(int v, F& f) {
 // OPM = 2: the inner product with the basis only (y = B^T W u for u = x[nelmt][Q^3], W = w |J|
 // with |J| in helm, per point or per element as DEF): C^T of the mass term alone, then the value
 // halves of B^T and A^T; lambda is not used.
+// OPM = 3: the inner product with the derivative basis only (y = sum_i (D_{x_i} B)^T W f_i for the
+// fields f_i = x, x1, x2 [nelmt][Q^3], d xi_a / d x_i in helm [nelmt][9][npts] and |J| in jac, per
+// point or per element as DEF): the xi fluxes W sum_i (d xi_a / d x_i) f_i at the points, then
+// the transposed chain rule and C^T, B^T, A^T of the Helmholtz group; lambda is not used.
 // One call processes NSUB independent groups of E elements, group g starting at element
 // base + g E, on a block of at least NSUB * ColDims::BLOCK threads (g = wavefront / NW; the
 // wavefronts past the last group only take part in the barriers); `lds` holds NSUB * LDS
@@ -117,9 +122,11 @@ __device__ __forceinline__ void col_dispatch(int v, F& f) {
 template <int SHAPE, int P, class T, bool DEF, int E_ = 0, int NSUB = 1, int OPM = 0>
 __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __restrict__ pen, const T* __restrict__ x,
                                                T* __restrict__ y, const T* __restrict__ helm, T lambda, int64_t nelmt,
-                                               int64_t base0, T* __restrict__ lds0) {
+                                               int64_t base0, T* __restrict__ lds0, const T* __restrict__ x1 = nullptr,
+                                               const T* __restrict__ x2 = nullptr, const T* __restrict__ jacp = nullptr) {
   using D = ColDims<SHAPE, P, T, E_, OPM>;
-  constexpr bool BWD = OPM == 1, IPR = OPM == 2;
+  constexpr bool BWD = OPM == 1, IPR = OPM == 2, IPD = OPM == 3;
+  constexpr bool NOFWD = IPR || IPD;   // no modal input: the forward stages are skipped
   using MO = ColModes<SHAPE, P>;
   constexpr int Q = D::Q, Q2 = D::Q2, NQ = D::NQ, M = D::M, NP = D::NP, E = D::E, SLAB = D::SLAB,
                 MAIN = D::MAIN, BLOCK = D::BLOCK;
@@ -147,7 +154,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
   T* L = lds + (act ? el : 0) * SLAB;
 
   // ---- stage the coefficients (coalesced)
-  for (int f = t; f < (IPR ? 0 : ne * M); f += BLOCK) {
+  for (int f = t; f < (NOFWD ? 0 : ne * M); f += BLOCK) {
     const int e2 = f / M;
     lds[e2 * SLAB + (f - e2 * M)] = x[base * M + f];
   }
@@ -155,8 +162,8 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 
   // ---- A: r -> k, one slice (tet: s = p+q, prism: p) per wavefront
   T c001 = T(0);
-  if (TET && !IPR && act) c001 = L[1];
-  if constexpr (!IPR) {
+  if (TET && !NOFWD && act) c001 = L[1];
+  if constexpr (!NOFWD) {
     T a0[Q], a1[Q];
     int dst = -1;   // pair row written by this lane
     T* Ls = lds;
@@ -239,7 +246,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
   }
 
   // ---- B: q -> j, one p per wavefront, lanes (element, k)
-  if constexpr (!IPR) {
+  if constexpr (!NOFWD) {
     T b0[Q], b1[Q], b2[Q];
     const int e2 = lane / Q, k = lane - e2 * Q;
     T* Ls = lds + (e2 < E ? e2 : 0) * SLAB;
@@ -350,9 +357,82 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
     __syncthreads();
   }
 
+  // ---- IPD: the xi fluxes of the three fields at the points, then C^T as in the Helmholtz group
+  if constexpr (IPD) {
+    T t0[P], t1[P], t2[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) t0[p] = t1[p] = t2[p] = T(0);
+    const T e2v = tb.z[1][act ? jj : 0], e3v = tb.z[2][act ? kk : 0];
+    T c00, c1k, c11, c12;   // as in C below
+    if (TET) {
+      const T r3 = T(1) / (T(1) - e3v);
+      const T ra = r3 / (T(1) - e2v);
+      c00 = T(4) * ra;
+      c1k = T(2) * ra;
+      c11 = T(2) * r3;
+      c12 = (T(1) + e2v) * r3;
+    } else {
+      const T r3 = T(1) / (T(1) - e3v);
+      c00 = T(2) * r3;
+      c1k = r3;
+      c11 = T(1);
+      c12 = T(0);
+    }
+    T v3 = T(0);
+    if (in && wave < D::NWP) {
+      // lanes past the batch end read element 0's values (in bounds, never stored)
+      const int64_t ev = valid ? int64_t(base + el) : 0;
+      const T* __restrict__ f0 = x + ev * NQ + s;
+      const T* __restrict__ f1 = x1 + ev * NQ + s;
+      const T* __restrict__ f2 = x2 + ev * NQ + s;
+      constexpr int GS = DEF ? NQ : 1;
+      const T* __restrict__ gx = helm + ev * 9 * GS + (DEF ? s : 0);
+      const T* __restrict__ jx = jacp + ev * GS + (DEF ? s : 0);
+#pragma unroll 1
+      for (int i = 0; i < Q; ++i) {
+        const HexTabC<P, T> tk{fresh_table(pen)};
+        const int o = DEF ? i * Q2 : 0;
+        T g[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) g[c] = gx[o + c * GS];
+        const T W = tb.wq[i * Q2 + s] * jx[o];
+        const T a0 = f0[i * Q2], a1 = f1[i * Q2], a2 = f2[i * Q2];
+        const T y1 = W * (g[0] * a0 + g[1] * a1 + g[2] * a2);
+        const T y2 = W * (g[3] * a0 + g[4] * a1 + g[5] * a2);
+        const T y3 = W * (g[6] * a0 + g[7] * a1 + g[8] * a2);
+        const T c1 = c1k * (T(1) + tb.z[0][i]);
+        T h1, h2;
+        if (TET) {
+          h1 = c00 * y1 + c1 * (y2 + y3);
+          h2 = c11 * y2 + c12 * y3;
+          v3 += y3;
+        } else {
+          h1 = c00 * y1 + c1 * y3;
+          h2 = y2;
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          t0[p] += tk.D(i, p) * h1;
+          t1[p] += tk.B(i, p) * h2;
+          t2[p] += tk.B(i, p) * y3;
+        }
+      }
+    }
+    if (act) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        L[p * Q2 + s] = t0[p];
+        L[PQ2 + p * Q2 + s] = t1[p];
+        L[2 * PQ2 + p * Q2 + s] = t2[p];
+      }
+      if (TET) L[MAIN + s] = tb.dT3[1 * Q + kk] * v3;
+    }
+    __syncthreads();
+  }
+
   // ---- C, pointwise, C^T fused over the (j,k) pencils, streamed over i (the wavefronts without
   // pencils go straight to the barrier)
-  if constexpr (!IPR) {
+  if constexpr (!NOFWD) {
     T C0[P], C1[P], C2[P];
     T t0[P], t1[P], t2[P];
 #pragma unroll

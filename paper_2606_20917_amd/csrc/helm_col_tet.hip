@@ -14,4 +14,8 @@ nir_status launch_iprod_col_tet(const nir_basis* b, int dtype, int deformed, con
 nir_status launch_phys_deriv_col_tet(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
   return launch_phys_deriv_col_shape<kTet>(b, dtype, deformed, a, s);
 }
+nir_status launch_iprod_deriv_col_tet(const nir_basis* b, int dtype, int deformed, const OpArgs& a,
+                                        hipStream_t s) {
+  return launch_iprod_deriv_col_shape<kTet>(b, dtype, deformed, a, s);
+}
 }  // namespace nir

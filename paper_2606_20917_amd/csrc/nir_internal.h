@@ -197,6 +197,9 @@ nir_status launch_iprod_col_tet(const nir_basis* b, int dtype, int deformed, con
 // PhysDeriv of prisms / tetrahedra: collocation pencils with the collapsed chain rule
 nir_status launch_phys_deriv_col_prism(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
 nir_status launch_phys_deriv_col_tet(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
+// IProductWRTDerivBase of prisms / tetrahedra with the transposed register-pencil sweeps
+nir_status launch_iprod_deriv_col_prism(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
+nir_status launch_iprod_deriv_col_tet(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
 
 nir_status launch_helm_hex_f16split(const nir_basis* b, int deformed, const OpArgs& a, hipStream_t s);
 // the fused Helmholtz apply with the currently selected kernel variant (native contractions)
