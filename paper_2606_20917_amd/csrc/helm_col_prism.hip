@@ -5,17 +5,4 @@ namespace nir {
 nir_status launch_helm_col_prism(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
   return launch_col_shape<kPrism>(b, dtype, deformed, a, s);
 }
-nir_status launch_bwd_col_prism(const nir_basis* b, int dtype, const OpArgs& a, hipStream_t s) {
-  return launch_bwd_col_shape<kPrism>(b, dtype, a, s);
-}
-nir_status launch_iprod_col_prism(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
-  return launch_iprod_col_shape<kPrism>(b, dtype, deformed, a, s);
-}
-nir_status launch_phys_deriv_col_prism(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
-  return launch_phys_deriv_col_shape<kPrism>(b, dtype, deformed, a, s);
-}
-nir_status launch_iprod_deriv_col_prism(const nir_basis* b, int dtype, int deformed, const OpArgs& a,
-                                        hipStream_t s) {
-  return launch_iprod_deriv_col_shape<kPrism>(b, dtype, deformed, a, s);
-}
 }  // namespace nir

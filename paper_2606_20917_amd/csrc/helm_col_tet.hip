@@ -5,17 +5,4 @@ namespace nir {
 nir_status launch_helm_col_tet(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
   return launch_col_shape<kTet>(b, dtype, deformed, a, s);
 }
-nir_status launch_bwd_col_tet(const nir_basis* b, int dtype, const OpArgs& a, hipStream_t s) {
-  return launch_bwd_col_shape<kTet>(b, dtype, a, s);
-}
-nir_status launch_iprod_col_tet(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
-  return launch_iprod_col_shape<kTet>(b, dtype, deformed, a, s);
-}
-nir_status launch_phys_deriv_col_tet(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
-  return launch_phys_deriv_col_shape<kTet>(b, dtype, deformed, a, s);
-}
-nir_status launch_iprod_deriv_col_tet(const nir_basis* b, int dtype, int deformed, const OpArgs& a,
-                                        hipStream_t s) {
-  return launch_iprod_deriv_col_shape<kTet>(b, dtype, deformed, a, s);
-}
 }  // namespace nir
