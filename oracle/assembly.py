@@ -105,11 +105,23 @@ def assembled_diagonal(tab, geo, lam, l2g, nglobal):
     return scatter_add(l2g, op.helmholtz_diagonal(tab, geo, lam), nglobal)
 
 
-def manufactured_rhs(tab, geo, lam, l2g, nglobal):
-    x = geo.x
-    u = np.sin(np.pi * x[..., 0]) * np.cos(np.pi * x[..., 1]) * np.sin(np.pi * x[..., 2])
-    f = (3.0 * np.pi ** 2 + lam) * u
-    return scatter_add(l2g, op.iprod_wrt_base(tab, geo, f), nglobal)
+def manufactured_u(x):
+    """The manufactured solution u = sin(pi x) cos(pi y) sin(pi z) at points x[..., 3]."""
+    return np.sin(np.pi * x[..., 0]) * np.cos(np.pi * x[..., 1]) * np.sin(np.pi * x[..., 2])
+
+
+def manufactured_rhs(tab, geo, lam, l2g, nglobal, forcing=None):
+    """Assembled b = sum_e P_e^T B^T W g, with g = -(lap(u) - lam u) at the points.
+
+    ``forcing(x)`` returns g at the points x[e][n][3]; by default g = (3 pi^2 + lam) u for
+    the manufactured u above (lap u = -3 pi^2 u), i.e. b = -B^T W f of the Helmholtz
+    equation lap(u) - lam u = f (eq. (1)) under the sign of eqs. (5)-(6).
+    """
+    if forcing is None:
+        g = (3.0 * np.pi ** 2 + lam) * manufactured_u(geo.x)
+    else:
+        g = forcing(geo.x)
+    return scatter_add(l2g, op.iprod_wrt_base(tab, geo, g), nglobal)
 
 
 def pcg(apply, diag, b, x0=None, rtol=1e-10, maxit=10000):

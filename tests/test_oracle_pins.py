@@ -384,3 +384,140 @@ def test_assembled_cg_small_mesh():
     assert res <= 1e-10
     ref = np.linalg.solve(A, b)
     assert np.abs(xs - ref).max() < 1e-8 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------------ curved (sin) map
+def test_sin_field_closed_form_values():
+    """s = sin 2pi x sin 2pi y sin 2pi z and its gradient at points where both are known."""
+    pts = np.array([[0.25, 0.25, 0.25], [0.25, 0.25, 0.75], [0.125, 0.25, 0.25], [0.0, 0.25, 0.25],
+                    [0.5, 0.75, 0.25]])
+    s, g = geometry.sin_field(pts)
+    assert np.allclose(s, [1.0, -1.0, math.sqrt(0.5), 0.0, 0.0], atol=1e-15)
+    tp = 2 * math.pi
+    ref = np.array([[0, 0, 0], [0, 0, 0], [tp * math.sqrt(0.5), 0, 0], [tp, 0, 0], [tp, 0, 0]])
+    assert np.allclose(g, ref, atol=1e-14)
+
+
+def _unit_cube_hex():
+    """One hex whose vertex map is x = (xi + 1) / 2 (the unit cube)."""
+    return np.array([[inputs._HEX_CORNERS[v] for v in range(8)]], dtype=np.float64)
+
+
+def test_sin_map_points_closed_form():
+    """x' = x + amp s(x) on every component: at x = (1/4, 1/4, 1/4), s = 1; at (1/4, 1/4, 3/4), s = -1."""
+    verts = _unit_cube_hex()
+    x, _ = geometry.map_points(basis.HEX, verts, np.array([-0.5, -0.5]), np.array([-0.5, -0.5]),
+                               np.array([-0.5, 0.5]), amp=0.1)
+    assert np.allclose(x[0, 0], [0.35, 0.35, 0.35], atol=1e-15)
+    assert np.allclose(x[0, 1], [0.15, 0.15, 0.65], atol=1e-15)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("amp", [0.0, 0.1])
+def test_map_jacobian_equals_central_differences(shape, amp):
+    """J = dx/dxi of map_points against central differences of its own points, at random xi inside
+    the reference element, on jittered meshes with and without the sin deformation.  A transposed
+    rank-one term (grad s and 1 swapped) or a wrong factor in the gradient of s fails here."""
+    verts, _, _ = _mesh(shape, 2, n=2, jitter=0.05, seed=5)
+    rng = np.random.default_rng(13)
+    xi = _random_ref_points(shape, 40, rng) * 0.97
+    _, J = geometry.map_points(shape, verts, *xi, amp=amp)
+    h = 1e-5
+    for j in range(3):
+        xp, xm = xi.copy(), xi.copy()
+        xp[j] += h
+        xm[j] -= h
+        fd = (geometry.map_points(shape, verts, *xp, amp=amp)[0] - geometry.map_points(shape, verts, *xm, amp=amp)[0])
+        fd /= 2 * h
+        assert np.abs(J[..., j] - fd).max() < 1e-8 * max(1.0, np.abs(J).max()), (shape, amp, j)
+
+
+def test_sin_map_determinant_extremes_closed_form():
+    """det(I + amp 1 grad(s)^T) = 1 + amp (ds/dx + ds/dy + ds/dz) (matrix determinant lemma), and
+    ds/dx + ds/dy + ds/dz = 2 pi * 3 c s^2 on the diagonal x = y = z with c = cos 2 pi t, s = sin 2 pi t,
+    whose extremes are +-2/sqrt(3) at c = +-1/sqrt(3).  So on the unit cube (J_vertex = I/2) the
+    deformed det J ranges over (1 -+ amp 4 pi / sqrt(3)) / 8 = [0.2745, 1.7255] / 8, reached at those
+    two diagonal points."""
+    amp = 0.1
+    verts = _unit_cube_hex()
+    lo, hi = 1 - amp * 4 * math.pi / math.sqrt(3), 1 + amp * 4 * math.pi / math.sqrt(3)
+    assert 0.2744 < lo < 0.2746 and 1.7254 < hi < 1.7256
+    t_hi = math.acos(1 / math.sqrt(3)) / (2 * math.pi)
+    t_lo = math.acos(-1 / math.sqrt(3)) / (2 * math.pi)
+    xi = np.array([2 * t_hi - 1, 2 * t_lo - 1])
+    _, J = geometry.map_points(basis.HEX, verts, xi, xi, xi, amp=amp)
+    det = np.linalg.det(J[0])
+    assert abs(det[0] - hi / 8) < 1e-14 and abs(det[1] - lo / 8) < 1e-14
+    # and no point of a fine sample of the cube leaves that range
+    g = np.linspace(-1, 1, 41)
+    X1, X2, X3 = (a.ravel() for a in np.meshgrid(g, g, g, indexing="ij"))
+    _, J = geometry.map_points(basis.HEX, verts, X1, X2, X3, amp=amp)
+    det = 8 * np.linalg.det(J[0])
+    assert det.min() >= lo - 1e-14 and det.max() <= hi + 1e-14
+    assert det.min() < lo + 2e-3 and det.max() > hi - 2e-3
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("Q,tol", [(5, 1e-8), (9, 1e-13)])
+def test_curved_unit_cube_volume(shape, Q, tol):
+    """The sin deformation fixes the boundary of [0,1]^3 (s = 0 there) and is one-to-one, so the
+    deformed, jittered mesh still has volume 1; sum W = sum w det J converges to it with Q."""
+    verts, _, _ = _mesh(shape, Q - 1, n=4, jitter=0.05, seed=1)
+    geo = geometry.Geometry(shape, Q, verts, 0.1)
+    assert abs(geo.W.sum() - 1.0) < tol, geo.W.sum() - 1.0
+
+
+# ------------------------------------------------------------------ manufactured right-hand side
+def _global_coefficients(tab, l2g, nglobal, local):
+    """Global coefficient vector of a C0 function given by its local coefficients (shared modes agree)."""
+    g = np.full(nglobal, np.nan)
+    g[l2g] = local
+    assert np.isfinite(g).all()
+    return g
+
+
+@pytest.mark.parametrize("lam", [1.0, 3.0])
+def test_manufactured_rhs_integrals(lam):
+    """b = sum_e P_e^T B^T W g.  Against the global coefficients c_1 of the constant 1 and c_y of the
+    coordinate y (exact on straight trilinear meshes), b . c_1 = int g and b . c_y = int y g.  For the
+    default g = (3 pi^2 + lam) sin(pi x) cos(pi y) sin(pi z) on the unit cube: int g = 0 (int_0^1
+    cos(pi y) dy = 0) and int y g = (3 pi^2 + lam) (2/pi)^2 int_0^1 y cos(pi y) dy
+    = -(3 pi^2 + lam) 8 / pi^4."""
+    n, P = 3, 9
+    verts = inputs.hex_mesh(n, np.random.default_rng(2), 0.05)
+    tab = op.Tables(basis.HEX, P, P + 1)
+    geo = geometry.Geometry(basis.HEX, P + 1, verts, 0.0)
+    l2g, ng = assembly.c0_map_closed_form_vec(n, P)
+    b = assembly.manufactured_rhs(tab, geo, lam, l2g, ng)
+    c1 = _global_coefficients(tab, l2g, ng, np.tile(op.constant_coefficients(tab), (n ** 3, 1)))
+    cy = _global_coefficients(tab, l2g, ng, op.linear_coefficients(tab, verts, 1))
+    assert abs(b @ c1) < 1e-9
+    assert abs(b @ cy - (-(3 * math.pi ** 2 + lam) * 8 / math.pi ** 4)) < 1e-9
+    # a forcing given as a parameter: g = 1 integrates the volume (exactly: det J of a trilinear map is
+    # a polynomial the rule integrates), g = y gives int y = 1/2
+    b1 = assembly.manufactured_rhs(tab, geo, lam, l2g, ng, forcing=lambda x: np.ones(x.shape[:-1]))
+    assert abs(b1 @ c1 - 1.0) < 1e-13
+    by = assembly.manufactured_rhs(tab, geo, lam, l2g, ng, forcing=lambda x: x[..., 1])
+    assert abs(by @ c1 - 0.5) < 1e-13
+
+
+def test_manufactured_neumann_solution_converges():
+    """Sign and consistency of the assembled problem A x = b: for u = cos(pi x) cos(pi y) cos(pi z),
+    which satisfies the homogeneous Neumann condition on the unit cube, g = (3 pi^2 + lam) u and the
+    discrete solution converges to u spectrally in P (a wrong sign of b or of H diverges instead)."""
+    lam, n = 1.0, 2
+    verts = inputs.hex_mesh(n)
+    errs = []
+    for P in (3, 5, 7):
+        tab = op.Tables(basis.HEX, P, P + 1)
+        geo = geometry.Geometry(basis.HEX, P + 1, verts, 0.0)
+        l2g, ng = assembly.c0_map_closed_form_vec(n, P)
+        u = lambda x: np.cos(np.pi * x[..., 0]) * np.cos(np.pi * x[..., 1]) * np.cos(np.pi * x[..., 2])
+        b = assembly.manufactured_rhs(tab, geo, lam, l2g, ng, forcing=lambda x: (3 * np.pi ** 2 + lam) * u(x))
+        A = np.zeros((ng, ng))
+        for e in range(n ** 3):
+            A[np.ix_(l2g[e], l2g[e])] += op.helmholtz_matrix(tab, geo, e, lam)
+        x = np.linalg.solve(A, b)
+        uh = op.bwd_trans(tab, x[l2g])
+        errs.append(np.abs(uh - u(geo.x)).max())
+    assert errs[0] < 0.1 and errs[1] < errs[0] / 20 and errs[2] < errs[1] / 20, errs
