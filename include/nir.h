@@ -157,6 +157,21 @@ nir_status nir_geom_from_vertices(const nir_batch* batch, const nir_basis* basis
                                   int32_t map, double amp, double* dxi_dx, double* jac,
                                   double* helm64, float* helm32, void* stream);
 
+/* FP64 geometric factors from caller-supplied Jacobians of the element map, for curved
+ * elements whose map the library does not know (section 2.1: W is the point weight times det J,
+ * and the physical derivative of eq. (9) needs d xi_j / d x_i; section 3.1.1: the block's
+ * Deformed attribute selects factors per point or per element).
+ *   jacobian [nelmt][9][npts] FP64 device array, component 3d+j = d x_d / d xi_j at point n
+ *            (npts = Q^3 at the points of nir_table_host(NIR_TAB_XI) if batch->deformed, else 1:
+ *            one constant Jacobian per affine element).
+ * Outputs exactly as nir_geom_from_vertices (any may be NULL, not all): dxi_dx, jac, helm64 and
+ * helm32 (the round-to-nearest FP32 copy), with the weights of the batch's quadrature.  The
+ * batch dtype is ignored.  No output may overlap the Jacobians (NIR_EINVAL).  det J is not
+ * checked on the device: a Jacobian that is singular or not orientation preserving gives
+ * meaningless factors at that point. */
+nir_status nir_geom_prepare(const nir_batch* batch, const nir_basis* basis, const double* jacobian, double* dxi_dx,
+                            double* jac, double* helm64, float* helm32, void* stream);
+
 /* Physical coordinates of the quadrature points (same maps as above): xyz [nelmt][3][Q^3]
  * FP64 device array.  Used to sample forcing functions at the points. */
 nir_status nir_points_from_vertices(const nir_batch* batch, const nir_basis* basis, const double* verts,

@@ -422,6 +422,25 @@ nir_status nir_geom_from_vertices(const nir_batch* batch, const nir_basis* basis
                      dxi_dx, jac, helm64, helm32, static_cast<hipStream_t>(stream));
 }
 
+nir_status nir_geom_prepare(const nir_batch* batch, const nir_basis* basis, const double* jacobian, double* dxi_dx,
+                            double* jac, double* helm64, float* helm32, void* stream) {
+  NIR_TRY(check_batch(batch, basis));
+  if (batch->nelmt == 0) return NIR_OK;
+  if (!jacobian || !aligned(jacobian, 8)) return fail(NIR_EINVAL, "jacobian is NULL or misaligned");
+  if (!dxi_dx && !jac && !helm64 && !helm32) return fail(NIR_EINVAL, "no output requested");
+  for (const void* p : {(const void*)dxi_dx, (const void*)jac, (const void*)helm64})
+    if (p && !aligned(p, 8)) return fail(NIR_EINVAL, "geometry output misaligned");
+  if (helm32 && !aligned(helm32, 4)) return fail(NIR_EINVAL, "helm32 misaligned");
+  const size_t npts = batch->deformed ? size_t(basis->Q) * basis->Q * basis->Q : 1;
+  const size_t n = size_t(batch->nelmt) * npts;
+  const size_t nj = 9 * n * 8;
+  if (overlap(jacobian, nj, dxi_dx, dxi_dx ? nj : 0) || overlap(jacobian, nj, jac, jac ? n * 8 : 0) ||
+      overlap(jacobian, nj, helm64, helm64 ? 7 * n * 8 : 0) || overlap(jacobian, nj, helm32, helm32 ? 7 * n * 4 : 0))
+    return fail(NIR_EINVAL, "an output overlaps the Jacobians");
+  return launch_geom_prepare(basis, batch->deformed, batch->nelmt, jacobian, dxi_dx, jac, helm64, helm32,
+                             static_cast<hipStream_t>(stream));
+}
+
 nir_status nir_points_from_vertices(const nir_batch* batch, const nir_basis* basis, const double* verts, int32_t map,
                                    double amp, double* xyz, void* stream) {
   NIR_TRY(check_batch(batch, basis));

@@ -52,6 +52,52 @@ __device__ __forceinline__ void shape_fn(double x1, double x2, double x3, double
   }
 }
 
+// From J[d][j] = d x_d / d xi_j at point n of element e (quadrature weight w, 1 for an affine
+// batch): the inverse metric d xi_a / d x_i by the adjugate, det J, and the 7 fused Helmholtz
+// factors G_ab = w det J sum_i (d xi_a/d x_i)(d xi_b/d x_i) and w det J, written SoA per element.
+__device__ __forceinline__ void metric_out(const double J[3][3], double w, int64_t e, int n, int npts,
+                                           double* __restrict__ dxi_dx, double* __restrict__ jac,
+                                           double* __restrict__ helm64, float* __restrict__ helm32) {
+  const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+  const double id = 1.0 / det;
+  double inv[3][3];
+  inv[0][0] = c00 * id;
+  inv[1][0] = c01 * id;
+  inv[2][0] = c02 * id;
+  inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+  inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+  inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+  inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+  inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+  inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+  if (dxi_dx) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) dxi_dx[(e * 9 + 3 * a + i) * npts + n] = inv[a][i];
+  }
+  if (jac) jac[e * npts + n] = det;
+  if (helm64 || helm32) {
+    const double Jw = det * w;
+    double h[7];
+    const int ab[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const int a = ab[c][0], b = ab[c][1];
+      h[c] = Jw * (inv[a][0] * inv[b][0] + inv[a][1] * inv[b][1] + inv[a][2] * inv[b][2]);
+    }
+    h[6] = Jw;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      if (helm64) helm64[(e * 7 + c) * npts + n] = h[c];
+      if (helm32) helm32[(e * 7 + c) * npts + n] = float(h[c]);
+    }
+  }
+}
+
 template <int SHAPE>
 __global__ void __launch_bounds__(256) k_geom(const double* __restrict__ verts, int64_t nelmt, int npts,
                                               const double* __restrict__ xi, const double* __restrict__ wq, int NQ,
@@ -102,45 +148,26 @@ __global__ void __launch_bounds__(256) k_geom(const double* __restrict__ verts, 
 #pragma unroll
         for (int j = 0; j < 3; ++j) J[d][j] += amp * gJ[j];
     }
-    // inverse by the adjugate: inv[a][i] = d xi_a / d x_i
-    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-    const double id = 1.0 / det;
-    double inv[3][3];
-    inv[0][0] = c00 * id;
-    inv[1][0] = c01 * id;
-    inv[2][0] = c02 * id;
-    inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
-    inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
-    inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
-    inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
-    inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
-    inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
-    if (dxi_dx) {
+    metric_out(J, w, e, n, npts, dxi_dx, jac, helm64, helm32);
+  }
+}
+
+// Geometry from caller-supplied Jacobians jacobian[e][3d+j][n] = d x_d / d xi_j (general curved
+// elements): the same outputs as k_geom, with the map's derivative given instead of computed.
+__global__ void __launch_bounds__(256) k_geom_prepare(const double* __restrict__ jacobian, int64_t nelmt, int npts,
+                                                      const double* __restrict__ wq, int NQ,
+                                                      double* __restrict__ dxi_dx, double* __restrict__ jac,
+                                                      double* __restrict__ helm64, float* __restrict__ helm32) {
+  const int64_t total = nelmt * npts;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t e = t / npts;
+    const int n = int(t - e * npts);
+    double J[3][3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+    for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) dxi_dx[(e * 9 + 3 * a + i) * npts + n] = inv[a][i];
-    }
-    if (jac) jac[e * npts + n] = det;
-    if (helm64 || helm32) {
-      const double Jw = det * w;
-      double h[7];
-      const int ab[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        const int a = ab[c][0], b = ab[c][1];
-        h[c] = Jw * (inv[a][0] * inv[b][0] + inv[a][1] * inv[b][1] + inv[a][2] * inv[b][2]);
-      }
-      h[6] = Jw;
-#pragma unroll
-      for (int c = 0; c < 7; ++c) {
-        if (helm64) helm64[(e * 7 + c) * npts + n] = h[c];
-        if (helm32) helm32[(e * 7 + c) * npts + n] = float(h[c]);
-      }
-    }
+      for (int j = 0; j < 3; ++j) J[d][j] = jacobian[(e * 9 + 3 * d + j) * npts + n];
+    metric_out(J, npts == NQ ? wq[n] : 1.0, e, n, npts, dxi_dx, jac, helm64, helm32);
   }
 }
 
@@ -204,6 +231,17 @@ nir_status launch_geom(const nir_basis* b, int deformed, int64_t nelmt, const do
       hipLaunchKernelGGL(k_geom<kTet>, grid, block, 0, s, verts, nelmt, npts, xi, wq, NQ, amp, dxi_dx, jac, helm64, helm32);
       break;
   }
+  return hip_check(hipGetLastError(), "geometry kernel launch");
+}
+
+nir_status launch_geom_prepare(const nir_basis* b, int deformed, int64_t nelmt, const double* jacobian,
+                               double* dxi_dx, double* jac, double* helm64, float* helm32, hipStream_t s) {
+  const int NQ = b->Q * b->Q * b->Q;
+  const int npts = deformed ? NQ : 1;
+  const int64_t nb = (nelmt * npts + 255) / 256;
+  const dim3 grid(unsigned(nb < (1 << 20) ? nb : (1 << 20))), block(256);
+  hipLaunchKernelGGL(k_geom_prepare, grid, block, 0, s, jacobian, nelmt, npts, b->t64.wq, NQ, dxi_dx, jac, helm64,
+                     helm32);
   return hip_check(hipGetLastError(), "geometry kernel launch");
 }
 

@@ -141,6 +141,10 @@ __global__ void __launch_bounds__(kMixedBlock) __attribute__((amdgpu_waves_per_e
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const MixedItem w = items[it];
     run_item<T>(batches + w.batch, w.first, lambda, lds);
+    // The collapsed groups return right after copying their results out of LDS; the next item
+    // (another shape or order) writes its coefficients into the same LDS before its first
+    // barrier, so every wavefront must be done reading before any starts the next item.
+    __syncthreads();
   }
 }
 

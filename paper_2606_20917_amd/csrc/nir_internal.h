@@ -181,6 +181,8 @@ nir_status launch_generic_tet(const nir_basis* b, int op, int dtype, int deforme
 nir_status launch_geom(const nir_basis* b, int deformed, int64_t nelmt, const double* verts, int map,
                        double amp, double* dxi_dx, double* jac, double* helm64, float* helm32,
                        hipStream_t s);
+nir_status launch_geom_prepare(const nir_basis* b, int deformed, int64_t nelmt, const double* jacobian,
+                               double* dxi_dx, double* jac, double* helm64, float* helm32, hipStream_t s);
 
 // the four elemental operators on hexahedra with register pencils (ops_hex_pencil.hip)
 nir_status launch_ops_hex_pencil(const nir_basis* b, int op, int dtype, int deformed, const OpArgs& a,

@@ -64,6 +64,7 @@ _SIGS = {
     "nir_basis_destroy": (_i32, [_vp]),
     "nir_basis_table_device": (_vp, [_vp, _i32]),
     "nir_geom_from_vertices": (_i32, [ctypes.POINTER(nir_batch), _vp, _vp, _i32, _dbl, _vp, _vp, _vp, _vp, _vp]),
+    "nir_geom_prepare": (_i32, [ctypes.POINTER(nir_batch), _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "nir_bwd_trans": (_i32, [ctypes.POINTER(nir_batch), _vp, _vp, _vp, _vp]),
     "nir_phys_deriv": (_i32, [ctypes.POINTER(nir_batch), _vp, ctypes.POINTER(nir_geom), _vp, _vp, _vp, _vp, _vp]),
     "nir_iprod_wrt_base": (_i32, [ctypes.POINTER(nir_batch), _vp, ctypes.POINTER(nir_geom), _vp, _vp, _vp]),
@@ -125,14 +126,57 @@ def _check(st):
 
 
 def _ptr(x):
-    """Address of a tensor (contiguous) or an int; None -> NULL."""
+    """Address of a contiguous device tensor, or an int (a raw address, passed unchecked);
+    None -> NULL.  Host tensors are rejected: the library would read them as device memory."""
     if x is None:
         return None
     if isinstance(x, int):
         return x
     if not x.is_contiguous():
-        raise ValueError("tensor must be contiguous")
+        raise NirError(1, "tensor must be contiguous")
+    if not x.is_cuda:
+        raise NirError(1, f"tensor on {x.device}: the library takes device memory")
     return x.data_ptr()
+
+
+_TORCH_DT = {F64: "float64", F32: "float32"}
+
+
+def _need(x, name, count, dt, device=False):
+    """Check a tensor argument before its address crosses the ABI: element type `dt` (F64, F32
+    or "int32") and at least `count` elements; with `device`, also contiguous device memory
+    (the other tensors get that check from _ptr when the call is marshalled).  None and raw
+    integer addresses pass through (the C side rejects NULL where it needs a pointer)."""
+    if x is None or isinstance(x, int):
+        return
+    want = _TORCH_DT.get(dt, dt)
+    got = str(x.dtype).replace("torch.", "")
+    if got != want:
+        raise NirError(1, f"{name}: element type {got}, the call needs {want}")
+    if x.numel() < count:
+        raise NirError(1, f"{name}: {x.numel()} elements, the call needs at least {count}")
+    if device:
+        _ptr(x)
+
+
+def _dims(b):
+    """(nelmt, M, Q^3, geometry points per element) of a batch; M = 0 for an invalid shape/order."""
+    M = max(0, int(lib().nir_nmodes(b.shape, b.nmodes)))
+    nq = b.nquad ** 3
+    return b.nelmt, M, nq, (nq if b.deformed else 1)
+
+
+def _need_geom(b, g, dxi=False, jac=False, helm=False, dt=None):
+    """Check the tensors a nir_geom was built from (nir.geom keeps them) against the batch."""
+    ne, _, _, ng = _dims(b)
+    dt = b.dtype if dt is None else dt
+    t = getattr(g, "_tensors", (None, None, None))
+    if dxi:
+        _need(t[0], "geom.dxi_dx", ne * 9 * ng, dt, device=True)
+    if jac:
+        _need(t[1], "geom.jac", ne * ng, dt, device=True)
+    if helm:
+        _need(t[2], "geom.helm", ne * 7 * ng, dt, device=True)
 
 
 def _stream(stream):
@@ -146,8 +190,20 @@ def batch(shape, P, nelmt, dtype=F64, deformed=1, math=MATH_NATIVE, Q=None):
     return nir_batch(shape, P, P + 1 if Q is None else Q, deformed, nelmt, dtype, math)
 
 
+def _addr(x):
+    if x is None or isinstance(x, int):
+        return x
+    if not x.is_contiguous():
+        raise NirError(1, "tensor must be contiguous")
+    return x.data_ptr()
+
+
 def geom(dxi_dx=None, jac=None, helm=None):
-    return nir_geom(_ptr(dxi_dx), _ptr(jac), _ptr(helm))
+    """A nir_geom of device tensors.  It keeps the tensors: each call checks the fields it
+    uses (device, element type, size against its batch) before the addresses cross the ABI."""
+    g = nir_geom(_addr(dxi_dx), _addr(jac), _addr(helm))
+    g._tensors = (dxi_dx, jac, helm)
+    return g
 
 
 class Basis:
@@ -211,47 +267,99 @@ def nir_basis_create(shape, P, Q=None):
     return Basis(shape, P, Q)
 
 
+_NVERT = {HEX: 8, PRISM: 6, TET: 4}
+
+
 def nir_geom_from_vertices(b, basis, verts, map_, amp, dxi_dx=None, jac=None, helm64=None, helm32=None,
                            stream=None):
+    ne, _, _, ng = _dims(b)
+    _need(verts, "verts", ne * _NVERT.get(b.shape, 0) * 3, F64)
+    _need(dxi_dx, "dxi_dx", ne * 9 * ng, F64)
+    _need(jac, "jac", ne * ng, F64)
+    _need(helm64, "helm64", ne * 7 * ng, F64)
+    _need(helm32, "helm32", ne * 7 * ng, F32)
     _check(lib().nir_geom_from_vertices(ctypes.byref(b), _basis(basis), _ptr(verts), map_, amp, _ptr(dxi_dx),
                                         _ptr(jac), _ptr(helm64), _ptr(helm32), _stream(stream)))
 
 
+def nir_geom_prepare(b, basis, jacobian, dxi_dx=None, jac=None, helm64=None, helm32=None, stream=None):
+    ne, _, _, ng = _dims(b)
+    _need(jacobian, "jacobian", ne * 9 * ng, F64)
+    _need(dxi_dx, "dxi_dx", ne * 9 * ng, F64)
+    _need(jac, "jac", ne * ng, F64)
+    _need(helm64, "helm64", ne * 7 * ng, F64)
+    _need(helm32, "helm32", ne * 7 * ng, F32)
+    _check(lib().nir_geom_prepare(ctypes.byref(b), _basis(basis), _ptr(jacobian), _ptr(dxi_dx), _ptr(jac),
+                                  _ptr(helm64), _ptr(helm32), _stream(stream)))
+
+
 def nir_bwd_trans(b, basis, coef, phys, stream=None):
+    ne, M, nq, _ = _dims(b)
+    _need(coef, "coef", ne * M, b.dtype)
+    _need(phys, "phys", ne * nq, b.dtype)
     _check(lib().nir_bwd_trans(ctypes.byref(b), _basis(basis), _ptr(coef), _ptr(phys), _stream(stream)))
 
 
 def nir_phys_deriv(b, basis, g, phys, d0, d1, d2, stream=None):
+    ne, M, nq, _ = _dims(b)
+    for name, t in (("phys", phys), ("d0", d0), ("d1", d1), ("d2", d2)):
+        _need(t, name, ne * nq, b.dtype)
+    _need_geom(b, g, dxi=True)
     _check(lib().nir_phys_deriv(ctypes.byref(b), _basis(basis), ctypes.byref(g), _ptr(phys), _ptr(d0), _ptr(d1),
                                 _ptr(d2), _stream(stream)))
 
 
 def nir_iprod_wrt_base(b, basis, g, phys, coef, stream=None):
+    ne, M, nq, _ = _dims(b)
+    _need(phys, "phys", ne * nq, b.dtype)
+    _need(coef, "coef", ne * M, b.dtype)
+    _need_geom(b, g, jac=True)
     _check(lib().nir_iprod_wrt_base(ctypes.byref(b), _basis(basis), ctypes.byref(g), _ptr(phys), _ptr(coef),
                                     _stream(stream)))
 
 
 def nir_iprod_wrt_deriv_base(b, basis, g, f0, f1, f2, coef, stream=None):
+    ne, M, nq, _ = _dims(b)
+    for name, t in (("f0", f0), ("f1", f1), ("f2", f2)):
+        _need(t, name, ne * nq, b.dtype)
+    _need(coef, "coef", ne * M, b.dtype)
+    _need_geom(b, g, dxi=True, jac=True)
     _check(lib().nir_iprod_wrt_deriv_base(ctypes.byref(b), _basis(basis), ctypes.byref(g), _ptr(f0), _ptr(f1),
                                           _ptr(f2), _ptr(coef), _stream(stream)))
 
 
 def nir_helmholtz_apply(b, basis, g, lam, coef_in, coef_out, stream=None):
+    ne, M, _, _ = _dims(b)
+    _need(coef_in, "coef_in", ne * M, b.dtype)
+    _need(coef_out, "coef_out", ne * M, b.dtype)
+    _need_geom(b, g, helm=True)
     _check(lib().nir_helmholtz_apply(ctypes.byref(b), _basis(basis), ctypes.byref(g), lam, _ptr(coef_in),
                                      _ptr(coef_out), _stream(stream)))
 
 
 def nir_helmholtz_apply_fields(b, basis, g, lam, nfields, coef_in, coef_out, stream=None):
+    ne, M, _, _ = _dims(b)
+    _need(coef_in, "coef_in", ne * max(nfields, 0) * M, b.dtype)
+    _need(coef_out, "coef_out", ne * max(nfields, 0) * M, b.dtype)
+    _need_geom(b, g, helm=True)
     _check(lib().nir_helmholtz_apply_fields(ctypes.byref(b), _basis(basis), ctypes.byref(g), lam, nfields,
                                             _ptr(coef_in), _ptr(coef_out), _stream(stream)))
 
 
 def nir_helmholtz_apply_trilinear(b, basis, verts, lam, coef_in, coef_out, stream=None):
+    ne, M, _, _ = _dims(b)
+    _need(verts, "verts", ne * 24, F64)
+    _need(coef_in, "coef_in", ne * M, b.dtype)
+    _need(coef_out, "coef_out", ne * M, b.dtype)
     _check(lib().nir_helmholtz_apply_trilinear(ctypes.byref(b), _basis(basis), _ptr(verts), lam, _ptr(coef_in),
                                                _ptr(coef_out), _stream(stream)))
 
 
 def nir_helmholtz_apply_nodal(b, basis, g, lam, u_in, u_out, stream=None):
+    ne, _, nq, _ = _dims(b)
+    _need(u_in, "u_in", ne * nq, b.dtype)
+    _need(u_out, "u_out", ne * nq, b.dtype)
+    _need_geom(b, g, helm=True)
     _check(lib().nir_helmholtz_apply_nodal(ctypes.byref(b), _basis(basis), ctypes.byref(g), lam, _ptr(u_in),
                                            _ptr(u_out), _stream(stream)))
 
@@ -265,6 +373,9 @@ def nir_get_helmholtz_variant(shape, P, dtype):
 
 
 def nir_points_from_vertices(b, basis, verts, map_, amp, xyz, stream=None):
+    ne, _, nq, _ = _dims(b)
+    _need(verts, "verts", ne * _NVERT.get(b.shape, 0) * 3, F64)
+    _need(xyz, "xyz", ne * 3 * nq, F64)
     _check(lib().nir_points_from_vertices(ctypes.byref(b), _basis(basis), _ptr(verts), map_, amp, _ptr(xyz),
                                           _stream(stream)))
 
@@ -281,6 +392,7 @@ def nir_c0_map_hex_host(n, P):
 
 
 def nir_c0_map_hex(n, P, l2g, stream=None):
+    _need(l2g, "l2g", n ** 3 * P ** 3, "int32")
     _check(lib().nir_c0_map_hex(n, P, _ptr(l2g), _stream(stream)))
 
 
@@ -288,9 +400,10 @@ class Assembly:
     """Owner of a nir_assembly handle (built from a device l2g tensor)."""
 
     def __init__(self, l2g, nglobal):
+        _need(l2g, "l2g", l2g.numel(), "int32")
         h = ctypes.c_void_p()
         _check(lib().nir_assembly_create(_ptr(l2g), l2g.shape[0], l2g.shape[1], nglobal, ctypes.byref(h)))
-        self.handle, self.nglobal = h, nglobal
+        self.handle, self.nglobal, self.nlocal = h, nglobal, l2g.numel()
 
     def __del__(self):
         if getattr(self, "handle", None) is not None and _lib is not None:
@@ -303,14 +416,21 @@ def nir_assembly_create(l2g, nglobal):
 
 
 def nir_gather(a, dtype, xg, xl, stream=None):
+    _need(xg, "xg", a.nglobal, dtype)
+    _need(xl, "xl", a.nlocal, dtype)
     _check(lib().nir_gather(a.handle, dtype, _ptr(xg), _ptr(xl), _stream(stream)))
 
 
 def nir_scatter_add(a, dtype, yl, yg, stream=None):
+    _need(yl, "yl", a.nlocal, dtype)
+    _need(yg, "yg", a.nglobal, dtype)
     _check(lib().nir_scatter_add(a.handle, dtype, _ptr(yl), _ptr(yg), _stream(stream)))
 
 
 def nir_helmholtz_diagonal(b, basis, g, lam, dl, stream=None):
+    ne, M, _, _ = _dims(b)
+    _need(dl, "dl", ne * M, b.dtype)
+    _need_geom(b, g, helm=True)
     _check(lib().nir_helmholtz_diagonal(ctypes.byref(b), _basis(basis), ctypes.byref(g), lam, _ptr(dl),
                                         _stream(stream)))
 
@@ -319,6 +439,9 @@ class CGPlan:
     """Owner of a nir_cg_plan handle; keeps the objects it points into alive."""
 
     def __init__(self, b64, basis, g64, helm32, assembly, lam):
+        ne, _, _, ng = _dims(b64)
+        _need_geom(b64, g64, helm=True, dt=F64)
+        _need(helm32, "helm32", ne * 7 * ng, F32)
         h = ctypes.c_void_p()
         _check(lib().nir_cg_plan_create(ctypes.byref(b64), _basis(basis), ctypes.byref(g64), _ptr(helm32),
                                         assembly.handle, lam, ctypes.byref(h)))
@@ -337,6 +460,8 @@ def nir_cg_plan_create(b64, basis, g64, helm32, assembly, lam):
 
 def nir_cg_solve(plan, mode, b, x, rtol=1e-10, maxit=100000, inner_rtol=1e-4, stream=None, check=True):
     """Returns (status, nir_cg_info); raises on a non-OK status when check is True."""
+    _need(b, "b", plan._keep[4].nglobal, F64)
+    _need(x, "x", plan._keep[4].nglobal, F64)
     info = nir_cg_info()
     st = lib().nir_cg_solve(plan.handle, mode, _ptr(b), _ptr(x), rtol, maxit, inner_rtol, ctypes.byref(info),
                             _stream(stream))
@@ -351,6 +476,8 @@ class MixedPlan:
 
     def __init__(self, batches, bases, geoms):
         n = len(batches)
+        for bb, gg in zip(batches, geoms):
+            _need_geom(bb, gg, helm=True)
         self._b = (nir_batch * n)(*batches)
         self._h = (ctypes.c_void_p * n)(*[_basis(x).value if hasattr(_basis(x), "value") else _basis(x)
                                           for x in bases])
@@ -386,6 +513,10 @@ def nir_mixed_plan_create(batches, bases, geoms):
 
 def nir_mixed_helmholtz_apply(plan, lam, coef_in, coef_out, stream=None):
     n = plan.n
+    for k, bb in enumerate(plan._keep[0]):
+        ne, M, _, _ = _dims(bb)
+        _need(coef_in[k], f"coef_in[{k}]", ne * M, bb.dtype)
+        _need(coef_out[k], f"coef_out[{k}]", ne * M, bb.dtype)
     ins = (ctypes.c_void_p * n)(*[_ptr(x) for x in coef_in])
     outs = (ctypes.c_void_p * n)(*[_ptr(x) for x in coef_out])
     _check(lib().nir_mixed_helmholtz_apply(plan.handle, lam, ctypes.cast(ins, _vp), ctypes.cast(outs, _vp),
@@ -394,6 +525,10 @@ def nir_mixed_helmholtz_apply(plan, lam, coef_in, coef_out, stream=None):
 
 def nir_autotune_helmholtz(b, basis, g, lam, coef_in, coef_out, reps=10, stream=None):
     """Returns (chosen variant, {variant: ms})."""
+    ne, M, _, _ = _dims(b)
+    _need(coef_in, "coef_in", ne * M, b.dtype)
+    _need(coef_out, "coef_out", ne * M, b.dtype)
+    _need_geom(b, g, helm=True)
     ch = ctypes.c_int32()
     ms = (ctypes.c_double * 10)(*([-1.0] * 10))
     _check(lib().nir_autotune_helmholtz(ctypes.byref(b), _basis(basis), ctypes.byref(g), lam, _ptr(coef_in),

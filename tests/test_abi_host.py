@@ -197,3 +197,38 @@ def test_autotune_cache_roundtrip(tmp_path):
     finally:
         for s, P, d in ((nir.HEX, 6, nir.F64), (nir.TET, 3, nir.F32), (nir.PRISM, 4, nir.F64)):
             nir.nir_set_helmholtz_variant(s, P, d, nir.VARIANT_AUTO)
+
+
+def test_binding_rejects_wrong_tensors_before_the_call():
+    """The binding checks device, element type and size of every tensor it passes; a host
+    tensor, a tensor of the other precision or a short buffer never reaches a kernel."""
+    torch = pytest.importorskip("torch")
+    b = nir.batch(nir.HEX, 3, 4, nir.F64, 1)          # M = 27, Q^3 = 64
+    coef = torch.zeros(4, 27, dtype=torch.float64)
+    phys = torch.zeros(4, 64, dtype=torch.float64)
+    cases = [
+        (lambda: nir.nir_bwd_trans(b, None, coef.float(), phys), "element type"),
+        (lambda: nir.nir_bwd_trans(b, None, coef[:3], phys), "elements"),
+        (lambda: nir.nir_bwd_trans(b, None, coef, phys[:, :63].contiguous()), "elements"),
+        (lambda: nir.nir_bwd_trans(b, None, coef, phys), "device"),
+        (lambda: nir.nir_helmholtz_apply(b, None, nir.geom(None, None, torch.zeros(4, 7, 64)), 1.0, coef,
+                                         coef.clone()), "element type"),
+        (lambda: nir.nir_helmholtz_apply(b, None, nir.geom(None, None, torch.zeros(4, 7, 63, dtype=torch.float64)),
+                                         1.0, coef, coef.clone()), "elements"),
+        (lambda: nir.nir_iprod_wrt_base(b, None, nir.geom(None, torch.zeros(4, 64, dtype=torch.float64), None),
+                                        phys, coef), "device"),
+        (lambda: nir.nir_phys_deriv(b, None, nir.geom(torch.zeros(4, 9, 64), None, None), phys, phys, phys, phys),
+         "element type"),
+        (lambda: nir.nir_geom_from_vertices(b, None, torch.zeros(4, 8, 3, dtype=torch.float32), 0, 0.0), "element type"),
+        (lambda: nir.nir_helmholtz_diagonal(b, None, nir.geom(), 1.0, torch.zeros(4, 27)), "element type"),
+        (lambda: nir.nir_c0_map_hex(2, 3, torch.zeros(8, 27, dtype=torch.int64)), "element type"),
+    ]
+    for k, (call, what) in enumerate(cases):
+        with pytest.raises(nir.NirError) as e:
+            call()
+        assert e.value.status == 1 and what in str(e.value), (k, str(e.value))
+    # the FP32 batch needs FP32 tensors
+    b32 = nir.batch(nir.HEX, 3, 4, nir.F32, 1)
+    with pytest.raises(nir.NirError) as e:
+        nir.nir_bwd_trans(b32, None, coef, phys)
+    assert "float32" in str(e.value)

@@ -122,7 +122,7 @@ def test_fields_hex_sin32_full(P, dtype):
         coef = coef.astype(np.float32).astype(np.float64)
     y = _apply_fields(c["verts"], c["amp"], 1, P, 3, dtype, coef, 1.0)
     assert np.isfinite(y).all()
-    sel = np.unique(np.concatenate([np.random.default_rng(P).choice(ne, 24, replace=False), [0, ne - 1]]))
+    sel = np.unique(np.concatenate([np.random.default_rng(P).choice(ne, 256, replace=False), [0, ne - 1]]))
     ref = _reference(c["verts"][sel], c["amp"], P, coef[sel], 1.0)
     tol = TOL64 if dtype == nir.F64 else TOL32
     for f in range(3):

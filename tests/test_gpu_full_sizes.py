@@ -1,8 +1,15 @@
 """Parity at the full workload sizes, in the launch configuration the benchmark times.
 
 The whole batch runs on the GPU (same generators, same geometry path, default kernel variant per
-(shape, P, dtype)); the oracle then evaluates a seeded sample of elements one by one (dense
-matrices of those elements only) and every sampled output is compared at the precision's bar.
+(shape, P, dtype)).  Two kinds of checks:
+- sampled outputs: the oracle evaluates a seeded sample of 512 elements (32 per group of the mixed
+  mesh) one by one, from dense matrices of those elements only, and every sampled output is
+  compared at the precision's bar;
+- whole-batch properties that hold at any size: every output finite; per-element energy
+  x_e . (H x_e) > 0 (H_e is SPD for lambda > 0); per-element symmetry x2_e . (H x1_e) =
+  x1_e . (H x2_e); and the constant function (1 on the vertex modes): with lambda = 0 its output
+  vanishes (the Laplacian annihilates constants), with lambda = 1 the sum over the mesh of
+  c_1 . (H c_1) is the mesh volume, 1 for these meshes of the unit cube.
 The CG workload is checked through global rows: the GPU residual b - A x of the solution at a
 seeded sample of global unknowns against the oracle's rows, assembled from the elements that
 touch them, plus the GPU-recomputed global residual norm.
@@ -19,16 +26,17 @@ from tests.gpu_util import elem_relerr
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
 TOL64, TOL32 = 1e-12, 2e-4   # FP32: the Helmholtz bar (10 x 2e-5, derivative tables)
-NSAMPLE = 40
+NSAMPLE = 512
+NSAMPLE_MIXED = 32           # per (shape, P) group of the mixed mesh
 
 
-def _sample(ne, seed):
+def _sample(ne, seed, n=NSAMPLE):
     rng = np.random.default_rng(seed)
-    idx = rng.choice(ne, size=min(NSAMPLE, ne), replace=False)
+    idx = rng.choice(ne, size=min(n, ne), replace=False)
     return np.unique(np.concatenate([idx, [0, ne - 1]]))   # both ends of the batch too
 
 
-def _run_batch(c, shape, P, dtype):
+def _geometry(c, shape, P, dtype):
     ne, Q, deformed = len(c["verts"]), P + 1, c["deformed"]
     npts = Q ** 3 if deformed else 1
     basis = nir.Basis(shape, P)
@@ -36,32 +44,56 @@ def _run_batch(c, shape, P, dtype):
     helm32 = torch.empty(ne, 7, npts, dtype=torch.float32, device=DEV) if dtype == nir.F32 else None
     nir.nir_geom_from_vertices(nir.batch(shape, P, ne, nir.F64, deformed), basis, torch.tensor(c["verts"], device=DEV),
                                nir.MAP_VERTEX_SIN if c["amp"] else nir.MAP_VERTEX, c["amp"], None, None, helm, helm32)
+    return basis, nir.geom(None, None, helm if dtype == nir.F64 else helm32), (helm, helm32)
+
+
+def _apply(b, basis, g, lam, x):
+    y = torch.full_like(x, float("nan"))
+    nir.nir_helmholtz_apply(b, basis, g, lam, x, y)
+    return y
+
+
+def _check_batch(c, shape, P, dtype):
+    ne, deformed = len(c["verts"]), c["deformed"]
+    basis, g, _keep = _geometry(c, shape, P, dtype)
+    b = nir.batch(shape, P, ne, dtype, deformed)
     tdt = torch.float64 if dtype == nir.F64 else torch.float32
     x = torch.tensor(c["coef"], dtype=tdt, device=DEV)
-    y = torch.full_like(x, float("nan"))
-    nir.nir_helmholtz_apply(nir.batch(shape, P, ne, dtype, deformed), basis,
-                            nir.geom(None, None, helm if dtype == nir.F64 else helm32), 1.0, x, y)
+    y = _apply(b, basis, g, 1.0, x)
     torch.cuda.synchronize()
-    return y.double().cpu().numpy(), x.double().cpu().numpy()
-
-
-def _check_sampled(c, shape, P, dtype, y, x):
-    assert np.isfinite(y).all()
-    sel = _sample(len(c["verts"]), 1000 + 10 * shape + P)
+    yh, xh = y.double().cpu().numpy(), x.double().cpu().numpy()
+    # sampled outputs against the oracle
+    assert np.isfinite(yh).all()
+    sel = _sample(ne, 1000 + 10 * shape + P)
     tab = op.Tables(shape, P, P + 1)
     geo = og.Geometry(shape, P + 1, c["verts"][sel], c["amp"])
-    ref = op.helmholtz(tab, geo, 1.0, x[sel])
-    err = elem_relerr(y[sel], ref)
+    err = elem_relerr(yh[sel], op.helmholtz(tab, geo, 1.0, xh[sel]))
     assert err <= (TOL64 if dtype == nir.F64 else TOL32), (shape, P, dtype, err)
+    # whole-batch properties
+    tol = 1e-12 if dtype == nir.F64 else 1e-5
+    energy = (xh * yh).sum(axis=1)
+    assert (energy > 0).all(), int((energy <= 0).sum())
+    x2 = torch.tensor(np.random.default_rng(77 + P).uniform(-1, 1, xh.shape), dtype=tdt, device=DEV)
+    y2 = _apply(b, basis, g, 1.0, x2)
+    one = torch.tensor(np.tile(op.constant_coefficients(tab), (ne, 1)), dtype=tdt, device=DEV)
+    y1 = _apply(b, basis, g, 1.0, one)
+    y0 = _apply(b, basis, g, 0.0, one)
+    torch.cuda.synchronize()
+    x2h, y2h = x2.double().cpu().numpy(), y2.double().cpu().numpy()
+    sym = np.abs((x2h * yh).sum(axis=1) - (xh * y2h).sum(axis=1))
+    scale = np.linalg.norm(x2h, axis=1) * np.linalg.norm(yh, axis=1) + np.linalg.norm(xh, axis=1) * np.linalg.norm(
+        y2h, axis=1)
+    assert (sym <= tol * scale).all(), float((sym / scale).max())
+    assert float(y0.abs().max()) <= tol * float(y.abs().max())
+    vol = float((one.double() * y1.double()).sum())
+    assert abs(vol - 1.0) <= (1e-12 if dtype == nir.F64 else 1e-4), vol
 
 
 @pytest.mark.parametrize("dtype", [nir.F64, nir.F32])
 @pytest.mark.parametrize("P", [2, 4, 6, 8, 10])
 def test_hex_sin32_full(P, dtype):
     """32^3 curved hexes, per-point factors, lambda = 1."""
-    c = inputs.hex_sin32(P)
-    y, x = _run_batch(c, nir.HEX, P, dtype)
-    _check_sampled(c, nir.HEX, P, dtype, y, x)
+    _check_batch(inputs.hex_sin32(P), nir.HEX, P, dtype)
 
 
 @pytest.mark.parametrize("dtype", [nir.F64, nir.F32])
@@ -70,13 +102,10 @@ def test_hex_sin32_full(P, dtype):
 def test_collapsed24_full(shape, P, dtype):
     """82944 affine tets (per-element factors) / 27648 prisms (per-point factors)."""
     c = inputs.tet24(P) if shape == nir.TET else inputs.prism24(P)
-    y, x = _run_batch(c, shape, P, dtype)
-    _check_sampled(c, shape, P, dtype, y, x)
+    _check_batch(c, shape, P, dtype)
 
 
-@pytest.mark.parametrize("dtype", [nir.F32, nir.F64])
-def test_mixed100k_full(dtype):
-    """100k elements of mixed shape and order through the mixed plan (its own strategy choice)."""
+def _mixed_plan(dtype):
     c = inputs.mixed100k()
     groups = {}
     for i, (s, p) in enumerate(zip(c["shapes"], c["P"])):
@@ -98,25 +127,34 @@ def test_mixed100k_full(dtype):
         xs.append(torch.tensor(coef, dtype=tdt, device=DEV))
         ys.append(torch.full_like(xs[-1], float("nan")))
         keep.append((s, p, verts, helm, helm32))
-    plan = nir.MixedPlan(batches, bases, geoms)
+    return c, nir.MixedPlan(batches, bases, geoms), xs, ys, keep
+
+
+@pytest.mark.parametrize("strategy", [nir.MIXED_AUTO, nir.MIXED_PERSISTENT])
+@pytest.mark.parametrize("dtype", [nir.F32, nir.F64])
+def test_mixed100k_full(dtype, strategy):
+    """100k elements of mixed shape and order through the mixed plan: its own strategy choice, and
+    the persistent launch forced."""
+    c, plan, xs, ys, keep = _mixed_plan(dtype)
+    plan.set_strategy(strategy)
     nir.nir_mixed_helmholtz_apply(plan, 1.0, xs, ys)
     nir.nir_mixed_helmholtz_apply(plan, 1.0, xs, ys)   # replay of the tuned graph
     torch.cuda.synchronize()
-    assert plan.info()["strategy"] in (nir.MIXED_PERSISTENT, nir.MIXED_PER_BATCH)
+    used = plan.info()["strategy"]
+    assert used == strategy if strategy != nir.MIXED_AUTO else used in (nir.MIXED_PERSISTENT, nir.MIXED_PER_BATCH)
     for k, (s, p, verts, _, _) in enumerate(keep):
         y = ys[k].double().cpu().numpy()
         x = xs[k].double().cpu().numpy()
         assert np.isfinite(y).all(), (s, p)
-        sel = _sample(len(verts), 2000 + 16 * s + p)[:8]
+        assert ((x * y).sum(axis=1) > 0).all(), (s, p)
+        sel = _sample(len(verts), 2000 + 16 * s + p, NSAMPLE_MIXED)
         tab = op.Tables(s, p, p + 1)
         geo = og.Geometry(s, p + 1, verts[sel], c["amp"])
         err = elem_relerr(y[sel], op.helmholtz(tab, geo, 1.0, x[sel]))
         assert err <= (TOL64 if dtype == nir.F64 else TOL32), (s, p, err)
 
 
-def test_cg48_full():
-    """48^3 curved hexes, P = 6: the FP32-inner refinement CG reaches 1e-10; the GPU residual
-    rows of the solution match the oracle's rows at sampled global unknowns."""
+def _cg48_problem():
     c = inputs.cg48()
     n, P, Q, amp, lam = c["n"], c["P"], c["P"] + 1, c["amp"], 1.0
     verts = c["verts"]
@@ -142,9 +180,20 @@ def test_cg48_full():
     del f
     bg = torch.empty(ng, dtype=torch.float64, device=DEV)
     nir.nir_scatter_add(A, nir.F64, bl, bg)
-    plan = nir.CGPlan(b64, basis, nir.geom(None, None, helm), helm32, A, lam)
+    return dict(c=c, n=n, P=P, Q=Q, amp=amp, lam=lam, verts=verts, ne=ne, basis=basis, b64=b64, helm=helm,
+                helm32=helm32, ng=ng, A=A, bg=bg)
+
+
+@pytest.mark.parametrize("mode", [nir.CG_FP64, nir.CG_MIXED_F32, nir.CG_MIXED_F16SPLIT])
+def test_cg48_full(mode):
+    """48^3 curved hexes, P = 6: every CG mode reaches 1e-10; the GPU residual rows of the solution
+    match the oracle's rows at sampled global unknowns."""
+    pr = _cg48_problem()
+    n, P, Q, amp, lam, ne, ng = pr["n"], pr["P"], pr["Q"], pr["amp"], pr["lam"], pr["ne"], pr["ng"]
+    basis, b64, helm, A, bg = pr["basis"], pr["b64"], pr["helm"], pr["A"], pr["bg"]
+    plan = nir.CGPlan(b64, basis, nir.geom(None, None, helm), pr["helm32"], A, lam)
     x = torch.zeros(ng, dtype=torch.float64, device=DEV)
-    st, info = nir.nir_cg_solve(plan, nir.CG_MIXED_F32, bg, x, rtol=1e-10, maxit=20000, inner_rtol=1e-4)
+    st, info = nir.nir_cg_solve(plan, mode, bg, x, rtol=1e-10, maxit=20000, inner_rtol=1e-4)
     assert info.rel_residual <= 1e-10
     # residual recomputed with separate calls: gather, FP64 element apply, scatter
     xl = torch.empty(ne, P ** 3, dtype=torch.float64, device=DEV)
@@ -157,18 +206,16 @@ def test_cg48_full():
     torch.cuda.synchronize()
     bnorm = float(torch.linalg.norm(bg))
     assert float(torch.linalg.norm(r)) / bnorm <= 1.5e-10
-    # sampled global rows against the oracle: b_g and (A x)_g from the elements touching g
+    # sampled global rows against the oracle: b_g and (A x)_g from the elements that touch g
     l2g_h, ng_h = assembly.c0_map_closed_form_vec(n, P)
     assert ng_h == ng
     rng = np.random.default_rng(48)
-    rows = rng.choice(ng, size=12, replace=False)
+    rows = rng.choice(ng, size=24, replace=False)
     elems = np.unique(np.nonzero(np.isin(l2g_h, rows))[0])
     tab = op.Tables(nir.HEX, P, Q)
-    geo = og.Geometry(nir.HEX, Q, verts[elems], amp)
-    xg = geo.x
-    u = np.sin(np.pi * xg[..., 0]) * np.cos(np.pi * xg[..., 1]) * np.sin(np.pi * xg[..., 2])
+    geo = og.Geometry(nir.HEX, Q, pr["verts"][elems], amp)
     xh = x.cpu().numpy()
-    bloc = op.iprod_wrt_base(tab, geo, (3 * np.pi ** 2 + lam) * u)
+    bloc = op.iprod_wrt_base(tab, geo, (3 * np.pi ** 2 + lam) * assembly.manufactured_u(geo.x))
     aloc = op.helmholtz(tab, geo, lam, xh[l2g_h[elems]])
     b_rows = np.zeros(len(rows))
     ax_rows = np.zeros(len(rows))

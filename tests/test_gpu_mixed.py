@@ -82,7 +82,7 @@ def test_mixed_plan_matches_per_batch_and_oracle(dtype, strategy):
         if strategy == nir.MIXED_AUTO:
             assert info["ms_persistent"] > 0 and info["ms_per_batch"] > 0
         # against the oracle (lambda = 0.5, last call)
-        tol = 1e-11 if dtype == nir.F64 else 2e-4
+        tol = 1e-12 if dtype == nir.F64 else 2e-4
         for k, b in enumerate(bs):
             tab = op.Tables(b["shape"], b["P"], b["Q"])
             geo = og.Geometry(b["shape"], b["Q"], b["verts"], b["amp"])

@@ -70,7 +70,7 @@ def test_nodal_hex_sin32_full(P):
     u = np.random.default_rng(20 + P).uniform(-1, 1, (ne, Q ** 3))
     y = _apply(c["verts"], c["amp"], 1, P, nir.F64, u, 1.0)
     assert np.isfinite(y).all()
-    sel = np.unique(np.concatenate([np.random.default_rng(P).choice(ne, 12, replace=False), [0, ne - 1]]))
+    sel = np.unique(np.concatenate([np.random.default_rng(P).choice(ne, 256, replace=False), [0, ne - 1]]))
     geo = og.Geometry(nir.HEX, Q, c["verts"][sel], c["amp"])
     assert elem_relerr(y[sel], nodal.helmholtz_nodal(Q, geo, 1.0, u[sel])) <= TOL64
 

@@ -94,6 +94,8 @@ def test_operators_match_oracle(case, P, dtype):
     s = _setup(case, P)
     shape, tab, geo, ne, Q = s["shape"], s["tab"], s["geo"], s["ne"], s["Q"]
     tol = TOL64 if dtype == nir.F64 else TOL32
+    # FP32 derivative paths pass through tables with entries up to P^2/2: 10x the FP32 bar
+    tolx = TOL64 if dtype == nir.F64 else 10 * TOL32
     rng = s["rng"]
     b = nir.batch(shape, P, ne, dtype, s["deformed"])
     g, _keep = _geom(s, dtype)
@@ -122,14 +124,14 @@ def test_operators_match_oracle(case, P, dtype):
     for i in range(3):   # a component may vanish identically on an element: compare to the gradient norm
         err = np.linalg.norm((d[i].cpu().numpy() - ref[i]).reshape(ne, -1), axis=1)
         den = np.sqrt(sum(np.linalg.norm(r.reshape(ne, -1), axis=1) ** 2 for r in ref))
-        assert (err / den).max() <= tol * 10, (i, (err / den).max())
+        assert (err / den).max() <= tolx, (i, (err / den).max())
 
     f = [rng.uniform(-1, 1, (ne, Q ** 3)) for _ in range(3)]
     if dtype == nir.F32:
         f = [x.astype(np.float32).astype(np.float64) for x in f]
     nir.nir_iprod_wrt_deriv_base(b, s["basis"], g, *[_t(x, dtype) for x in f], cout)
     torch.cuda.synchronize()
-    assert elem_relerr(cout.cpu().numpy(), op.iprod_wrt_deriv_base(tab, geo, *f)) <= tol * 10
+    assert elem_relerr(cout.cpu().numpy(), op.iprod_wrt_deriv_base(tab, geo, *f)) <= tolx
 
     variants = [nir.VARIANT_GENERIC, nir.VARIANT_PENCIL] + ([nir.VARIANT_PENCIL_U2, nir.VARIANT_PENCIL_E1,
                                                              nir.VARIANT_PENCIL_PF, nir.VARIANT_PENCIL_SPLIT,
@@ -143,7 +145,7 @@ def test_operators_match_oracle(case, P, dtype):
             for lam in (1.0, 0.0, 0.5, 3.0):
                 nir.nir_helmholtz_apply(b, s["basis"], g, lam, dc, cout)
                 torch.cuda.synchronize()
-                assert elem_relerr(cout.cpu().numpy(), op.helmholtz(tab, geo, lam, coef)) <= tol * 10, (v, lam)
+                assert elem_relerr(cout.cpu().numpy(), op.helmholtz(tab, geo, lam, coef)) <= tolx, (v, lam)
     finally:
         nir.nir_set_helmholtz_variant(shape, P, dtype, nir.VARIANT_AUTO)
 
@@ -233,6 +235,6 @@ def test_autotune_selects_a_valid_variant(shape, P):
         nir.nir_helmholtz_apply(b, s["basis"], g, 1.0, x, y)
         torch.cuda.synchronize()
         ref = op.helmholtz(s["tab"], s["geo"], 1.0, x.cpu().numpy())
-        assert elem_relerr(y.cpu().numpy(), ref) <= 10 * TOL64
+        assert elem_relerr(y.cpu().numpy(), ref) <= TOL64
     finally:
         nir.nir_set_helmholtz_variant(shape, P, nir.F64, nir.VARIANT_AUTO)

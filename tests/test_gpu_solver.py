@@ -155,3 +155,19 @@ def test_cg_is_deterministic():
     nir.nir_cg_solve(plan, nir.CG_MIXED_F32, bg, x1)
     nir.nir_cg_solve(plan, nir.CG_MIXED_F32, bg, x2)
     assert torch.equal(x1, x2)
+
+
+def test_cg_breakdown_on_negative_definite_operator():
+    """lambda = -1e9 makes every elemental H_e = L_e + lambda M_e negative definite on this mesh (its
+    largest eigenvalue is about -3.4, computed by the oracle), so the assembled A and its Jacobi
+    diagonal are too and p^T A p < 0 at the first iteration: FP64 PCG reports NIR_EBREAKDOWN.
+    Every kernel still runs to its end; the breakdown is read from the solver's flag."""
+    pr = _problem(3, 4, lam=-1e9)
+    tab, geo, l2g, ng = _oracle_parts(pr)
+    assert max(np.linalg.eigvalsh(op.helmholtz_matrix(tab, geo, e, -1e9)).max() for e in (0, 13, 26)) < 0
+    bg = _gpu_rhs(pr)
+    plan = nir.CGPlan(pr["b64"], pr["basis"], nir.geom(None, None, pr["helm"]), pr["helm32"], pr["A"], -1e9)
+    x = torch.zeros(pr["ng"], dtype=torch.float64, device=DEV)
+    st, info = nir.nir_cg_solve(plan, nir.CG_FP64, bg, x, rtol=1e-10, maxit=200, check=False)
+    assert st == 6, (st, nir.nir_last_error())          # NIR_EBREAKDOWN
+    assert info.inner_iters <= 10

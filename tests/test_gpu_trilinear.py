@@ -102,6 +102,6 @@ def test_trilinear_full(P, dtype):
     coef = c["coef"] if dtype == nir.F64 else c["coef"].astype(np.float32).astype(np.float64)
     y = _apply_tri(c["verts"], P, dtype, coef, 1.0)
     assert np.isfinite(y).all()
-    sel = np.unique(np.concatenate([np.random.default_rng(P).choice(ne, 32, replace=False), [0, ne - 1]]))
+    sel = np.unique(np.concatenate([np.random.default_rng(P).choice(ne, 256, replace=False), [0, ne - 1]]))
     err = elem_relerr(y[sel], _reference(c["verts"][sel], P, coef[sel], 1.0))
     assert err <= (TOL64 if dtype == nir.F64 else TOL32), (P, dtype, err)
