@@ -330,6 +330,8 @@ nir_status nir_helmholtz_diagonal(const nir_batch* batch, const nir_basis* basis
  *                     (helm32 given at plan creation), FP64 dot products, stopped at inner_rtol
  *   NIR_CG_MIXED_F16SPLIT  as NIR_CG_MIXED_F32 with the element apply's contractions as
  *                     FP16-split products on the matrix cores (FP32 accumulation)
+ * lambda may be any finite value; PCG needs A SPD (lambda > 0 with natural boundary
+ * conditions), and an operator that is not reports NIR_EBREAKDOWN.
  * Errors: NIR_ENONFINITE (NaN/Inf in b or x0, or a non-finite residual), NIR_EBREAKDOWN
  * (FP64 p^T A p <= 0), NIR_ENOCONV (maxit inner iterations used; x and info still hold the
  * last iterate).  x holds x0 on entry (warm start / resume) and the solution on return.

@@ -531,7 +531,9 @@ nir_status nir_cg_plan_create(const nir_batch* b64, const nir_basis* basis, cons
   if (b64->dtype != NIR_F64) return fail(NIR_EINVAL, "the plan's batch must be FP64");
   if (!geom64 || !geom64->helm || !A) return fail(NIR_EINVAL, "NULL geometry or assembly");
   if (A->nelmt != b64->nelmt || A->M != basis->M) return fail(NIR_EINVAL, "assembly does not match the batch");
-  if (!(lambda >= 0.0)) return fail(NIR_EINVAL, "lambda must be >= 0");
+  // Any finite lambda is accepted: the solver needs A SPD (lambda > 0 under natural boundary
+  // conditions) and reports NIR_EBREAKDOWN at the first p^T A p <= 0 when it is not.
+  if (!std::isfinite(lambda)) return fail(NIR_EINVAL, "lambda is not finite");
   nir_cg_plan* pl = new (std::nothrow) nir_cg_plan();
   if (!pl) return fail(NIR_ENOMEM, "host allocation failed");
   pl->b64 = *b64;
