@@ -1,4 +1,4 @@
-"""Modified C0 Jacobi bases of the hexahedron, prism and tetrahedron - oracle.
+"""Modified C0 Jacobi bases of the hexahedron, prism, tetrahedron and pyramid - oracle.
 
 Test infrastructure only.
 
@@ -22,9 +22,24 @@ in xi and the vertex modes are the barycentric vertex functions:
 * tet, mode (0,0,1):  + (1 - psi^a_0(eta_1) psi^b_00(eta_2)) (1+eta_3)/2
 * prism, modes (0,q,1): + psi^a_1(eta_1) psi^a_q(xi_2) psi^b_01(xi_3)
 
+The paper names pyramids among the elements of hybrid meshes (section 1) but
+gives no expansion.  The one used here collapses both eta_1 and eta_2 towards
+the apex (-1,-1,1) and couples the third direction to max(p, q):
+
+    pyramid: phi_pqr = psi^a_p(eta_1) psi^a_q(eta_2) psi^b_{max(p,q), r}(eta_3),
+             0 <= p, q < P, 0 <= r < P - max(p, q),
+    mode (0,0,1): + (1 - psi^a_0(eta_1) psi^a_0(eta_2)) (1+eta_3)/2,
+
+so that the vertex modes are the five (rational) pyramid vertex functions, the
+quadrilateral face carries the hexahedron's tensor modes and every triangular
+face the tetrahedron's face modes.  Most pyramid modes, the four base vertex
+functions among them, are rational in xi, as a conforming pyramid space needs;
+their span contains every polynomial of degree P-1.
+
 Collapsed coordinates, eq. (13) with the missing "-1" restored in eta_1:
-    tet:   eta_1 = 2(1+xi_1)/(-xi_2-xi_3) - 1, eta_2 = 2(1+xi_2)/(1-xi_3) - 1, eta_3 = xi_3
-    prism: eta_1 = 2(1+xi_1)/(1-xi_3) - 1,     eta_2 = xi_2,                  eta_3 = xi_3
+    tet:     eta_1 = 2(1+xi_1)/(-xi_2-xi_3) - 1, eta_2 = 2(1+xi_2)/(1-xi_3) - 1, eta_3 = xi_3
+    prism:   eta_1 = 2(1+xi_1)/(1-xi_3) - 1,     eta_2 = xi_2,                  eta_3 = xi_3
+    pyramid: eta_1 = 2(1+xi_1)/(1-xi_3) - 1,     eta_2 = 2(1+xi_2)/(1-xi_3) - 1, eta_3 = xi_3
 Gradients with respect to xi use the chain rule of eq. (23).
 
 Mode order (the storage order of the coefficients) is lexicographic with p
@@ -36,8 +51,8 @@ import numpy as np
 from .jacobi import jacobi, jacobi_deriv
 from . import quadrature
 
-HEX, PRISM, TET = 0, 1, 2
-SHAPE_NAMES = {HEX: "hex", PRISM: "prism", TET: "tet"}
+HEX, PRISM, TET, PYR = 0, 1, 2, 3
+SHAPE_NAMES = {HEX: "hex", PRISM: "prism", TET: "tet", PYR: "pyramid"}
 
 
 # ---------------------------------------------------------------- 1-D functions
@@ -96,6 +111,8 @@ def modes(shape, P):
                 rmax = P
             elif shape == PRISM:
                 rmax = P - p
+            elif shape == PYR:
+                rmax = P - max(p, q)
             else:
                 rmax = P - p - q
             for r in range(rmax):
@@ -112,7 +129,8 @@ def vertex_modes(shape, P):
 
     Reference vertices: hex (-1,-1,-1),(1,-1,-1),(1,1,-1),(-1,1,-1),(-1,-1,1),
     (1,-1,1),(1,1,1),(-1,1,1); prism (-1,-1,-1),(1,-1,-1),(1,1,-1),(-1,1,-1),
-    (-1,-1,1),(-1,1,1); tet (-1,-1,-1),(1,-1,-1),(-1,1,-1),(-1,-1,1).
+    (-1,-1,1),(-1,1,1); tet (-1,-1,-1),(1,-1,-1),(-1,1,-1),(-1,-1,1); pyramid
+    (-1,-1,-1),(1,-1,-1),(1,1,-1),(-1,1,-1),(-1,-1,1).
     """
     idx = {m: i for i, m in enumerate(modes(shape, P))}
     if shape == HEX:
@@ -121,6 +139,8 @@ def vertex_modes(shape, P):
     elif shape == PRISM:
         pairs = [((0, 0, 0), 0), ((1, 0, 0), 1), ((1, 1, 0), 2), ((0, 1, 0), 3),
                  ((0, 0, 1), 4), ((0, 1, 1), 5)]
+    elif shape == PYR:
+        pairs = [((0, 0, 0), 0), ((1, 0, 0), 1), ((1, 1, 0), 2), ((0, 1, 0), 3), ((0, 0, 1), 4)]
     else:
         pairs = [((0, 0, 0), 0), ((1, 0, 0), 1), ((0, 1, 0), 2), ((0, 0, 1), 3)]
     return [(idx[m], v) for m, v in pairs]
@@ -133,6 +153,8 @@ def reference_vertices(shape):
     if shape == PRISM:
         return np.array([[-1, -1, -1], [1, -1, -1], [1, 1, -1], [-1, 1, -1],
                          [-1, -1, 1], [-1, 1, 1]], dtype=np.float64)
+    if shape == PYR:
+        return np.array([[-1, -1, -1], [1, -1, -1], [1, 1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=np.float64)
     return np.array([[-1, -1, -1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=np.float64)
 
 
@@ -143,6 +165,8 @@ def xi_from_eta(shape, e1, e2, e3):
         return e1, e2, e3
     if shape == PRISM:
         return 0.5 * (1.0 + e1) * (1.0 - e3) - 1.0, e2, e3
+    if shape == PYR:
+        return 0.5 * (1.0 + e1) * (1.0 - e3) - 1.0, 0.5 * (1.0 + e2) * (1.0 - e3) - 1.0, e3
     x3 = e3
     x2 = 0.5 * (1.0 + e2) * (1.0 - e3) - 1.0
     x1 = 0.25 * (1.0 + e1) * (1.0 - e2) * (1.0 - e3) - 1.0
@@ -155,6 +179,8 @@ def eta_from_xi(shape, x1, x2, x3):
         return x1, x2, x3
     if shape == PRISM:
         return 2.0 * (1.0 + x1) / (1.0 - x3) - 1.0, x2, x3
+    if shape == PYR:
+        return 2.0 * (1.0 + x1) / (1.0 - x3) - 1.0, 2.0 * (1.0 + x2) / (1.0 - x3) - 1.0, x3
     e1 = 2.0 * (1.0 + x1) / (-x2 - x3) - 1.0
     e2 = 2.0 * (1.0 + x2) / (1.0 - x3) - 1.0
     return e1, e2, x3
@@ -173,6 +199,13 @@ def deta_dxi(shape, e1, e2, e3):
         out[0, 0] = 2.0 / (1.0 - e3)
         out[0, 2] = (1.0 + e1) / (1.0 - e3)
         out[1, 1] = 1.0
+        out[2, 2] = 1.0
+        return out
+    if shape == PYR:
+        out[0, 0] = 2.0 / (1.0 - e3)
+        out[0, 2] = (1.0 + e1) / (1.0 - e3)
+        out[1, 1] = 2.0 / (1.0 - e3)
+        out[1, 2] = (1.0 + e2) / (1.0 - e3)
         out[2, 2] = 1.0
         return out
     a = (1.0 - e2) * (1.0 - e3)
@@ -200,6 +233,9 @@ def eval_basis_eta(shape, P, e1, e2, e3):
         elif shape == PRISM:
             f = (psi_a(p, e1), psi_a(q, e2), psi_b(p, r, e3))
             g = (dpsi_a(p, e1), dpsi_a(q, e2), dpsi_b(p, r, e3))
+        elif shape == PYR:
+            f = (psi_a(p, e1), psi_a(q, e2), psi_b(max(p, q), r, e3))
+            g = (dpsi_a(p, e1), dpsi_a(q, e2), dpsi_b(max(p, q), r, e3))
         else:
             f = (psi_a(p, e1), psi_b(p, q, e2), psi_b(p + q, r, e3))
             g = (dpsi_a(p, e1), dpsi_b(p, q, e2), dpsi_b(p + q, r, e3))
@@ -215,7 +251,8 @@ def eval_basis_eta(shape, P, e1, e2, e3):
             dphi[0, :, m] += g1 * f2 * f3
             dphi[1, :, m] += f1 * g2 * f3
             dphi[2, :, m] += f1 * f2 * g3
-        if shape == TET and (p, q, r) == (0, 0, 1):
+        if shape in (TET, PYR) and (p, q, r) == (0, 0, 1):
+            # apex vertex: base term plus correction is (1+eta_3)/2 (psi^b_00 = psi^a_0)
             w = 1.0 - psi_a(0, e1) * psi_b(0, 0, e2)
             h = 0.5 * (1.0 + e3)
             phi[:, m] += w * h
@@ -248,6 +285,11 @@ def element_rule(shape, Q):
         z2, w2 = quadrature.gauss_lobatto_legendre(Q)
         z3, w3 = quadrature.gauss_radau_jacobi(Q, 1)
         w3 = 0.5 * w3
+    elif shape == PYR:
+        # d xi = ((1-eta_3)/2)^2 d eta: the collapse factor of both directions in the eta_3 weight
+        z2, w2 = quadrature.gauss_lobatto_legendre(Q)
+        z3, w3 = quadrature.gauss_radau_jacobi(Q, 2)
+        w3 = 0.25 * w3
     else:
         z2, w2 = quadrature.gauss_radau_jacobi(Q, 1)
         w2 = 0.5 * w2

@@ -9,12 +9,15 @@ Maps (a reading: the paper names no mesh):
 * hex: trilinear map of its 8 vertices,
 * prism: linear triangle in (xi_1, xi_3) times linear in xi_2 (6 vertices),
 * tet: affine map of its 4 vertices,
+* pyramid: the five pyramid vertex functions (the vertex modes of the pyramid
+  expansion; bilinear on the quadrilateral base, rational inside), affine when
+  the base is a parallelogram,
 optionally followed by the smooth deformation x_d -> x_d + amp * s(x) for
 every component d, with s(x) = sin(2 pi x) sin(2 pi y) sin(2 pi z).
 """
 import numpy as np
 
-from .basis import HEX, PRISM, TET, element_rule, xi_from_eta
+from .basis import HEX, PRISM, TET, PYR, element_rule, xi_from_eta
 
 
 def shape_functions(shape, x1, x2, x3):
@@ -41,6 +44,21 @@ def shape_functions(shape, x1, x2, x3):
         for (lt, dlt), (ll, dll) in zip(tri, lin):
             N.append(lt * ll)
             dN.append([dlt[0] * ll, lt * dll * one, dlt[2] * ll])
+        return np.array(N), np.array(dN)
+    if shape == PYR:
+        # with t = 1 - xi_3, a = (1+xi_1)/t, b = (1+xi_2)/t, s = t/2 the base vertex functions are
+        # A(a) B(b) s (A, B in {1 - a, a} and {1 - b, b}), the apex function is (1+xi_3)/2:
+        # d/dxi_1 = A' B / 2, d/dxi_2 = A B' / 2, d/dxi_3 = (A' a B + A B' b - A B) / 2
+        t = 1.0 - x3
+        a, b = (1.0 + x1) / t, (1.0 + x2) / t
+        N, dN = [], []
+        for sa, sb in ((0, 0), (1, 0), (1, 1), (0, 1)):
+            A, dA = (a, 1.0) if sa else (1.0 - a, -1.0)
+            B, dB = (b, 1.0) if sb else (1.0 - b, -1.0)
+            N.append(A * B * 0.5 * t)
+            dN.append([0.5 * dA * B, 0.5 * A * dB, 0.5 * (dA * a * B + A * dB * b - A * B)])
+        N.append(0.5 * (1.0 + x3))
+        dN.append([0.0 * one, 0.0 * one, 0.5 * one])
         return np.array(N), np.array(dN)
     N = np.array([-0.5 * (1 + x1 + x2 + x3), 0.5 * (1 + x1), 0.5 * (1 + x2), 0.5 * (1 + x3)])
     g = np.array([[-0.5, -0.5, -0.5], [0.5, 0, 0], [0, 0.5, 0], [0, 0, 0.5]])

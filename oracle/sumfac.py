@@ -3,7 +3,9 @@
 Pure-Python loops written from the sum-factorised forms of the paper
 (section 2.2): backward transform of the hexahedron (eq. (16)) and of the
 tetrahedron (eq. (17)); inner product of the hexahedron (eq. (20)) and of
-the tetrahedron (eq. (21)); standard derivative (eq. (22)).  Readings:
+the tetrahedron (eq. (21)); standard derivative (eq. (22)).  Prisms and
+pyramids take the same nested sums with their own third-direction factor
+(psi^b_{p,r} and psi^b_{max(p,q),r}).  Readings:
 the weights in eqs. (20)/(21) are indexed by the quadrature point (w_1i,
 w_2j, w_3k), |J| stays inside the innermost sum, and the collapsed shapes
 carry the vertex corrections of the modified basis.  Only for P <= 3 and one
@@ -12,7 +14,7 @@ or two elements: it exists to cross-check the dense matrices of
 """
 import numpy as np
 
-from .basis import HEX, PRISM, TET, psi_a, psi_b, modes, element_rule
+from .basis import HEX, PRISM, TET, PYR, psi_a, psi_b, modes, element_rule
 
 
 def _tables(shape, P, Q):
@@ -35,12 +37,14 @@ def bwd_trans(shape, P, Q, uhat):
                     qmax = P - p if shape == TET else P
                     for q in range(qmax):
                         s3 = 0.0
-                        rmax = P if shape == HEX else (P - p if shape == PRISM else P - p - q)
+                        rmax = {HEX: P, PRISM: P - p, PYR: P - max(p, q)}.get(shape, P - p - q)
                         for rr in range(rmax):
                             if shape == HEX:
                                 c = psi_a(rr, z3[k])
                             elif shape == PRISM:
                                 c = psi_b(p, rr, z3[k])
+                            elif shape == PYR:
+                                c = psi_b(max(p, q), rr, z3[k])
                             else:
                                 c = psi_b(p + q, rr, z3[k])
                             s3 += uhat[idx[(p, q, rr)]] * c
@@ -59,6 +63,9 @@ def bwd_trans(shape, P, Q, uhat):
                     for q in range(P):
                         s1 += (psi_a(1, z1[i]) * psi_a(q, z2[j]) * psi_b(0, 1, z3[k])
                                * uhat[idx[(0, q, 1)]])
+                if shape == PYR and P > 1:
+                    s1 += ((1.0 - psi_a(0, z1[i]) * psi_a(0, z2[j])) * 0.5 * (1.0 + z3[k])
+                           * uhat[idx[(0, 0, 1)]])
                 u[i, j, k] = s1
     return u.ravel()
 
@@ -82,6 +89,8 @@ def iprod_wrt_base(shape, P, Q, f, detJ):
                         c = psi_a(rr, z3[k])
                     elif shape == PRISM:
                         c = psi_b(p, rr, z3[k])
+                    elif shape == PYR:
+                        c = psi_b(max(p, q), rr, z3[k])
                     else:
                         c = psi_b(p + q, rr, z3[k])
                     # correction terms of the collapsed shapes enter as extra test functions
@@ -91,6 +100,8 @@ def iprod_wrt_base(shape, P, Q, f, detJ):
                         extra = (1.0 - psi_a(0, z1[i]) * psi_b(0, 0, z2[j])) * 0.5 * (1.0 + z3[k])
                     elif shape == PRISM and p == 0 and rr == 1:
                         extra = psi_a(1, z1[i]) * psi_a(q, z2[j]) * psi_b(0, 1, z3[k])
+                    elif shape == PYR and (p, q, rr) == (0, 0, 1):
+                        extra = (1.0 - psi_a(0, z1[i]) * psi_a(0, z2[j])) * 0.5 * (1.0 + z3[k])
                     else:
                         extra = 0.0
                     b = psi_b(p, q, z2[j]) if shape == TET else psi_a(q, z2[j])

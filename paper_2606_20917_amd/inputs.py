@@ -19,13 +19,16 @@ shapes and sizes the throughput study sweeps, section 4.2):
                      by a seeded shuffle, cell i of a 47x47x46 grid, P_e
                      uniform on {3..8}, deformation amplitude 0.1
 * ``cg48``           48^3 hexes, deformation amplitude 0.1, P=6 (assembled CG)
+* ``pyr24``          24^3 cube with interior jitter U(-0.03h, 0.03h), every cell
+                     split into 6 pyramids (82944) on its faces with the cell
+                     centre as the common apex, vertex map, P in {3,5,8}
 
 Seeds are 20260601 + the workload index (1..5); the draws happen in the
 order vertex jitter, element orders, coefficients.
 """
 import numpy as np
 
-HEX, PRISM, TET = 0, 1, 2
+HEX, PRISM, TET, PYR = 0, 1, 2, 3
 SEED_BASE = 20260601
 
 
@@ -127,17 +130,57 @@ def prism_mesh(n, rng=None, jitter=0.0, cells=None, sub=None):
     return out
 
 
+def _pyr_faces():
+    """Corner offsets of the 6 faces of a unit cell, each in the cyclic order of the reference
+    pyramid's base (V0, V1, V2, V3), oriented so that (V1 - V0) x (V3 - V0) points into the cell,
+    towards the apex at its centre."""
+    faces = [[(0, 0, 0), (0, 1, 0), (0, 1, 1), (0, 0, 1)], [(1, 0, 0), (1, 1, 0), (1, 1, 1), (1, 0, 1)],
+             [(0, 0, 0), (1, 0, 0), (1, 0, 1), (0, 0, 1)], [(0, 1, 0), (1, 1, 0), (1, 1, 1), (0, 1, 1)],
+             [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0)], [(0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)]]
+    out = []
+    for f in faces:
+        v = np.array(f, float)
+        n = np.cross(v[1] - v[0], v[3] - v[0])
+        if n @ (np.full(3, 0.5) - v[0]) < 0:
+            f = [f[0], f[3], f[2], f[1]]
+        out.append(f)
+    return out
+
+
+def pyr_mesh(n, rng=None, jitter=0.0, cells=None, sub=None):
+    """verts[e][5][3]: 6 pyramids per cell (element 6c+s) on the cell's faces, apex at the mean of
+    the cell's 8 corners; or one pyramid per given cell."""
+    X = grid_points(n, n, n, rng, jitter)
+    faces = _pyr_faces()
+    if cells is None:
+        ix, iy, iz = _cells(n, n, n)
+        ix, iy, iz = (np.repeat(a, 6) for a in (ix, iy, iz))
+        sub = np.tile(np.arange(6), n ** 3)
+    else:
+        ix, iy, iz = cells
+    out = np.empty((len(ix), 5, 3))
+    centre = sum(X[ix + a, iy + b, iz + c] for a, b, c in _HEX_CORNERS) / 8.0
+    for s in range(6):
+        sel = sub == s
+        for v, (a, b, c) in enumerate(faces[s]):
+            out[sel, v] = X[ix[sel] + a, iy[sel] + b, iz[sel] + c]
+        out[sel, 4] = centre[sel]
+    return out
+
+
 def coefficients(rng, nelmt, nmodes):
     """Modal coefficients uniform on [-1, 1], shape (nelmt, nmodes)."""
     return rng.uniform(-1.0, 1.0, size=(nelmt, nmodes))
 
 
 def nmodes(shape, P):
-    """Mode count per element (sizes only): P^3, P^2(P+1)/2, P(P+1)(P+2)/6."""
+    """Mode count per element (sizes only): P^3, P^2(P+1)/2, P(P+1)(P+2)/6, P(P+1)(2P+1)/6."""
     if shape == HEX:
         return P ** 3
     if shape == PRISM:
         return P * P * (P + 1) // 2
+    if shape == PYR:
+        return P * (P + 1) * (2 * P + 1) // 6
     return P * (P + 1) * (P + 2) // 6
 
 
@@ -178,6 +221,13 @@ def prism24(P, n=24):
     verts = prism_mesh(n, rng, jitter=0.03)
     return dict(shape=PRISM, P=P, Q=P + 1, verts=verts, amp=0.0, deformed=1,
                 coef=coefficients(rng, len(verts), nmodes(PRISM, P)))
+
+
+def pyr24(P, n=24):
+    rng = rng_for(10)
+    verts = pyr_mesh(n, rng, jitter=0.03)
+    return dict(shape=PYR, P=P, Q=P + 1, verts=verts, amp=0.0, deformed=1,
+                coef=coefficients(rng, len(verts), nmodes(PYR, P)))
 
 
 def mixed100k(nelmt=100000, grid=(47, 47, 46), porders=(3, 8)):

@@ -17,7 +17,7 @@ from oracle.jacobi import jacobi, jacobi_deriv
 from paper_2606_20917_amd import inputs
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-SHAPES = [basis.HEX, basis.PRISM, basis.TET]
+SHAPES = [basis.HEX, basis.PRISM, basis.TET, basis.PYR]
 
 
 def _num(s):
@@ -108,7 +108,7 @@ def _monomials(shape, deg, x):
     return np.array(cols).T
 
 
-@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("shape", [basis.HEX, basis.PRISM, basis.TET])
 @pytest.mark.parametrize("P", [2, 3, 4, 5])
 def test_basis_spans_polynomial_space(shape, P):
     """Every mode is a polynomial of the shape's space, and the modes are a basis of it."""
@@ -120,6 +120,37 @@ def test_basis_spans_polynomial_space(shape, P):
     coef = np.linalg.lstsq(V, phi, rcond=None)[0]
     assert np.abs(V @ coef - phi).max() < 1e-11
     assert np.linalg.matrix_rank(coef) == basis.nmodes(shape, P)
+
+
+@pytest.mark.parametrize("P", [2, 3, 4, 5, 6])
+def test_pyramid_modes_contain_polynomials_and_are_independent(P):
+    """The pyramid space of order P-1 contains every polynomial of total degree <= P-1 in xi (the
+    modes reproduce them by least squares on random points), and its M = P(P+1)(2P+1)/6 modes are
+    linearly independent.  A wrong r range or coupling index (p + q instead of max(p, q)) changes
+    the count or loses polynomials."""
+    rng = np.random.default_rng(17)
+    x = _random_ref_points(basis.PYR, 600, rng)
+    phi, _ = basis.eval_basis_xi(basis.PYR, P, *basis.eta_from_xi(basis.PYR, *x))
+    assert phi.shape[1] == P * (P + 1) * (2 * P + 1) // 6
+    assert np.linalg.matrix_rank(phi, tol=1e-10) == phi.shape[1]
+    V = _monomials(basis.TET, P - 1, x)
+    res = phi @ np.linalg.lstsq(phi, V, rcond=None)[0] - V
+    assert np.abs(res).max() < 1e-10
+
+
+def test_pyramid_vertex_function_is_rational():
+    """The pyramid's vertex function of (1,1,0) is (1+xi_1)(1+xi_2) / (2(1-xi_3)), not a polynomial
+    (no cubic fits it on random points): the space is rational, as a conforming pyramid space must be."""
+    rng = np.random.default_rng(19)
+    x = _random_ref_points(basis.PYR, 400, rng)
+    e = basis.eta_from_xi(basis.PYR, *x)
+    phi, _ = basis.eval_basis_xi(basis.PYR, 3, *e)
+    V = _monomials(basis.HEX, 3, x)
+    fit = lambda f: np.abs(V @ np.linalg.lstsq(V, f, rcond=None)[0] - f).max()
+    ml = basis.modes(basis.PYR, 3)
+    m110 = ml.index((1, 1, 0))
+    assert np.abs(phi[:, m110] - (1 + x[0]) * (1 + x[1]) / (2 * (1 - x[2]))).max() < 1e-14
+    assert fit(phi[:, m110]) > 1e-3
 
 
 def test_uncorrected_tet_modes_are_not_polynomial():
@@ -176,6 +207,22 @@ def _face_points(shape, face, n, rng):
         if face == 2:
             return np.array([-np.ones(n), u, v])
         return np.array([u, v, -u - v - 1])
+    if shape == basis.PYR:
+        # face 0: the quadrilateral base; faces 1..4: xi_2 = -1, xi_1 = -1, xi_1 + xi_3 = 0, xi_2 + xi_3 = 0
+        if face == 0:
+            return np.array([rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), -np.ones(n)])
+        a, b = rng.uniform(0, 1, (2, n))
+        s = a + b > 1
+        a[s], b[s] = 1 - a[s], 1 - b[s]
+        u, v = -1 + 2 * a, -1 + 2 * b        # a point of the triangle u, v >= -1, u + v <= 0
+        t = -np.ones(n)
+        if face == 1:
+            return np.array([u, t, v])
+        if face == 2:
+            return np.array([t, u, v])
+        if face == 3:
+            return np.array([-v, u, v])
+        return np.array([u, -v, v])
     raise ValueError
 
 
@@ -192,8 +239,51 @@ def test_tet_face_modes_count(P):
         assert np.linalg.matrix_rank(phi[:, nz], tol=1e-9) == P * (P + 1) // 2
 
 
+@pytest.mark.parametrize("P", [2, 3, 4, 5])
+def test_pyramid_face_modes(P):
+    """C0 structure of the pyramid: P^2 modes are non-zero on the quadrilateral base and span the
+    tensor space there; P(P+1)/2 modes are non-zero on each triangular face and span the
+    polynomials of degree P-1 on it."""
+    rng = np.random.default_rng(23)
+    for face in range(5):
+        x = _face_points(basis.PYR, face, 300, rng)
+        phi, _ = basis.eval_basis_xi(basis.PYR, P, *basis.eta_from_xi(basis.PYR, *x))
+        nz = np.abs(phi).max(axis=0) > 1e-12
+        want = P * P if face == 0 else P * (P + 1) // 2
+        assert nz.sum() == want, face
+        assert np.linalg.matrix_rank(phi[:, nz], tol=1e-9) == want, face
+
+
+@pytest.mark.parametrize("P", [2, 3, 4, 6])
+def test_pyramid_traces_equal_tet_and_hex_traces(P):
+    """Conformity with the neighbours: the pyramid's face xi_2 = -1 is the tetrahedron's face
+    xi_2 = -1 (same three reference vertices), and its base xi_3 = -1 is the hexahedron's face
+    xi_3 = -1.  Every pyramid mode that is non-zero there has the trace of exactly one tet (hex)
+    mode, one to one, so shared faces assemble mode by mode without a change of basis."""
+    rng = np.random.default_rng(29)
+    for other, face_o, face_p in ((basis.TET, 1, 1), (basis.HEX, None, 0)):
+        x = _face_points(basis.PYR, face_p, 250, rng)
+        pp, _ = basis.eval_basis_xi(basis.PYR, P, *basis.eta_from_xi(basis.PYR, *x))
+        po, _ = basis.eval_basis_xi(other, P, *basis.eta_from_xi(other, *x))
+        nzp = np.where(np.abs(pp).max(axis=0) > 1e-12)[0]
+        nzo = np.where(np.abs(po).max(axis=0) > 1e-12)[0]
+        assert len(nzp) == len(nzo)
+        used = set()
+        for m in nzp:
+            d = np.abs(po[:, nzo] - pp[:, m:m + 1]).max(axis=0)
+            k = int(np.argmin(d))
+            assert d[k] < 1e-12, (other, m)
+            used.add(int(nzo[k]))
+        assert len(used) == len(nzo)
+
+
 def test_reference_volumes_and_moments():
-    for shape, vol in [(basis.HEX, 8.0), (basis.PRISM, 4.0), (basis.TET, 4.0 / 3.0)]:
+    r = basis.element_rule(basis.PYR, 4)
+    x1, _, x3 = basis.xi_from_eta(basis.PYR, r["e1"], r["e2"], r["e3"])
+    # pyramid: square cross-sections of side 1 - xi_3 give int xi_1^2 = 4/5, int (1 + xi_3) = 4/3
+    assert abs(r["w"] @ x1 ** 2 - 4.0 / 5.0) < 1e-14
+    assert abs(r["w"] @ (1 + x3) - 4.0 / 3.0) < 1e-14
+    for shape, vol in [(basis.HEX, 8.0), (basis.PRISM, 4.0), (basis.TET, 4.0 / 3.0), (basis.PYR, 8.0 / 3.0)]:
         for Q in range(2, 12):
             r = basis.element_rule(shape, Q)
             assert abs(r["w"].sum() - vol) < 1e-13
@@ -230,6 +320,11 @@ def _closed_form_index(shape, P, p, q, r):
         return (p * P + q) * P + r
     if shape == basis.PRISM:
         return sum(P * (P - pp) for pp in range(p)) + q * (P - p) + r
+    if shape == basis.PYR:
+        # rows (p', q') hold P - max(p', q') modes; a row p' holds (p'+1)(P-p') + (P-p'-1)(P-p')/2
+        row = lambda pp: (pp + 1) * (P - pp) + (P - pp - 1) * (P - pp) // 2
+        before_q = sum(P - max(p, qq) for qq in range(q))
+        return sum(row(pp) for pp in range(p)) + before_q + r
     T = lambda n: n * (n + 1) * (n + 2) // 6
     return (T(P) - T(P - p)) + (q * (P - p) - q * (q - 1) // 2) + r
 
@@ -250,6 +345,8 @@ def _mesh(shape, P, n=3, amp=0.0, jitter=0.05, seed=0):
         verts = inputs.hex_mesh(n, rng, jitter)
     elif shape == basis.PRISM:
         verts = inputs.prism_mesh(n, rng, jitter)
+    elif shape == basis.PYR:
+        verts = inputs.pyr_mesh(n, rng, jitter)
     else:
         verts = inputs.tet_mesh(n, rng, jitter)
     tab = op.Tables(shape, P, P + 1)
@@ -265,6 +362,17 @@ def test_affine_tet_jacobian_closed_form(shape):
     det = np.linalg.det(A)
     assert np.allclose(geo.detJ, det[:, None] / 8.0, rtol=1e-13)
     assert np.allclose(geo.W.sum(axis=1), det / 6.0, rtol=1e-13)
+
+
+def test_affine_pyramid_jacobian_closed_form():
+    """On an unjittered cube the pyramid bases are squares, so the map is affine:
+    J = [V1 - V0, V3 - V0, V4 - V0] / 2 at every point, and each of the 6 pyramids of a cell of
+    side h has volume h^3 / 6."""
+    verts = inputs.pyr_mesh(2)
+    geo = geometry.Geometry(basis.PYR, 5, verts)
+    A = np.stack([verts[:, 1] - verts[:, 0], verts[:, 3] - verts[:, 0], verts[:, 4] - verts[:, 0]], axis=2) / 2
+    assert np.abs(geo.J - A[:, None]).max() < 1e-15
+    assert np.allclose(geo.W.sum(axis=1), 0.5 ** 3 / 6, rtol=1e-13, atol=0)
 
 
 @pytest.mark.parametrize("shape", SHAPES)
