@@ -286,6 +286,22 @@ nir_status nir_mixed_plan_info(const nir_mixed_plan* plan, int32_t* nitems, int3
                                int64_t* bytes, int64_t* dof);
 nir_status nir_mixed_plan_destroy(nir_mixed_plan* plan);
 
+/* Allocation-free persistent apply, for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): one mixed apply over the
+ * given batches with no plan.  It runs the persistent kernel of NIR_MIXED_PERSISTENT (register
+ * budget of 2 waves per SIMD, one workgroup per CU per resident slot, no tuning), so each batch's
+ * result equals nir_helmholtz_apply with the NIR_VARIANT_PENCIL kernel bit for bit.  Arguments
+ * as nir_mixed_plan_create plus nir_mixed_helmholtz_apply; batches with nelmt = 0 are skipped.
+ * lambda, the batch descriptors and the work list go to one static device array per GPU (about
+ * 2.1 MB, held until the process ends), written by small kernels on `stream`; nothing is
+ * allocated and the host arrays are read before the call returns.  Limits: nbatch <= 32, P <= 8,
+ * at most 131072 work items (element groups of up to 32 elements, by shape and order),
+ * NIR_EINVAL beyond them.  Every call on one GPU shares that array: calls that overlap on one GPU
+ * (different streams or host threads without ordering) race and give wrong results. */
+nir_status nir_mixed_helmholtz_apply_noalloc(int32_t nbatch, const nir_batch* batches, const nir_basis* const* bases,
+                                             const nir_geom* geoms, double lambda, const void* const* coef_in,
+                                             void* const* coef_out, void* stream);
+
 /* ------------------------------------------------------------------ C0 assembly
  * Structured n x n x n hex mesh on a cube, element e = ix + n*(iy + n*iz), every element with
  * the same orientation (the paper leaves assembly out of scope, section 2.1).  The 1-D global

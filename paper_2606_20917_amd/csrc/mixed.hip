@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "generic_ops.h"
@@ -37,7 +38,64 @@
 
 namespace nir {
 
+// ---------------------------------------------------------------- allocation-free persistent apply
+// nir_mixed_helmholtz_apply_noalloc keeps everything the persistent kernel reads besides the
+// caller's operands (lambda, the batch descriptors and the work list) in one static device array
+// per GPU, so that a call allocates nothing.  Layout: lambda at offset 0, up to kNoallocMaxBatch
+// descriptors from kNoallocDescOff, up to kNoallocMaxItems work items from kNoallocItemOff.
+constexpr int kNoallocMaxBatch = 32;
+constexpr int64_t kNoallocMaxItems = int64_t(1) << 17;
+constexpr size_t kNoallocDescOff = 256;
+constexpr size_t kNoallocDescBytes = kNoallocMaxBatch * sizeof(MixedBatch<double>);
+constexpr size_t kNoallocItemOff = kNoallocDescOff + (kNoallocDescBytes + 255) / 256 * 256;
+constexpr size_t kNoallocBytes = kNoallocItemOff + size_t(kNoallocMaxItems) * sizeof(MixedItem);
+static_assert(sizeof(MixedBatch<float>) <= sizeof(MixedBatch<double>), "descriptor region sized for FP64");
+
+// one contiguous run of work items: the element groups of one batch
+struct NoallocSeg {
+  int32_t batch;
+  int32_t elems;     // elements per group
+  int64_t nelmt;
+  int64_t item0;     // index of the run's first item
+};
+struct NoallocSegs {
+  int32_t n;
+  int32_t pad;
+  NoallocSeg s[kNoallocMaxBatch];
+};
+
+// item t -> (batch, first element of its group); one thread per item
+__global__ void __launch_bounds__(256) k_mixed_worklist(NoallocSegs segs, double lambda, double* __restrict__ lam,
+                                                        MixedItem* __restrict__ items, int64_t nitems) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t == 0) *lam = lambda;
+  if (t >= nitems) return;
+  int k = 0;
+  while (k + 1 < segs.n && t >= segs.s[k + 1].item0) ++k;
+  MixedItem w;
+  w.batch = segs.s[k].batch;
+  w.pad = 0;
+  w.first = (t - segs.s[k].item0) * segs.s[k].elems;
+  items[t] = w;
+}
+
+// descriptors of up to kNoallocDescChunk batches, passed by value, copied into device memory
+constexpr int kNoallocDescChunk = 8;
+template <class T>
+struct NoallocDescs {
+  int32_t first, n;
+  MixedBatch<T> d[kNoallocDescChunk];
+};
+template <class T>
+__global__ void __launch_bounds__(64) k_mixed_descriptors(NoallocDescs<T> in, MixedBatch<T>* __restrict__ out) {
+  if (threadIdx.x < unsigned(in.n)) out[in.first + threadIdx.x] = in.d[threadIdx.x];
+}
+
 }  // namespace nir
+
+// The allocation-free apply's device memory (see kNoallocBytes).  In host code this name is
+// not a device address: the address is taken per device with hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[nir::kNoallocBytes];
 
 struct nir_mixed_plan {
   int dtype = 0;
@@ -414,6 +472,149 @@ nir_status nir_mixed_plan_info(const nir_mixed_plan* pl, int32_t* nitems, int32_
   if (bytes) *bytes = pl->bytes;
   if (dof) *dof = pl->dof;
   return NIR_OK;
+}
+
+
+}  // extern "C"
+
+namespace nir {
+
+// device address of `scratch` on the current device (taken once per device), and its CU count
+static nir_status noalloc_scratch(char** out, int* ncu) {
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static char* addr[kMaxDev] = {};
+  static int cus[kMaxDev] = {};
+  int dev = 0;
+  NIR_TRYS(hip_check(hipGetDevice(&dev), "device"));
+  if (dev < 0 || dev >= kMaxDev) return fail(NIR_ENOTSUP, "device %d: at most %d devices", dev, kMaxDev);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    NIR_TRYS(hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch symbol address"));
+    int n = 0;
+    NIR_TRYS(hip_check(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev), "CU count"));
+    cus[dev] = n;
+    addr[dev] = static_cast<char*>(p);
+  }
+  *out = addr[dev];
+  *ncu = cus[dev];
+  return NIR_OK;
+}
+
+template <class T>
+static nir_status noalloc_apply(int nbatch, const nir_batch* batches, const nir_basis* const* bases,
+                                const nir_geom* geoms, double lambda, const void* const* coef_in,
+                                void* const* coef_out, hipStream_t s) {
+  // runs of items, batches in decreasing cost of one group (the plan's cost order, by batch)
+  NoallocSegs segs;
+  std::memset(&segs, 0, sizeof(segs));
+  int64_t cost[kNoallocMaxBatch] = {};
+  const int es = int(sizeof(T));
+  for (int b = 0; b < nbatch; ++b) {
+    const nir_batch& B = batches[b];
+    if (B.nelmt == 0) continue;
+    NoallocSeg& g = segs.s[segs.n];
+    g.batch = b;
+    g.elems = mixed_group_elems<T>(B.shape, B.nmodes);
+    g.nelmt = B.nelmt;
+    const int64_t M = modes_of(B.shape, B.nmodes), NQ = int64_t(B.nquad) * B.nquad * B.nquad;
+    cost[segs.n] = es * (2 * M + 7 * (B.deformed ? NQ : 1)) * g.elems;
+    ++segs.n;
+  }
+  if (segs.n == 0) return NIR_OK;
+  for (int i = 1; i < segs.n; ++i)   // insertion sort, stable, decreasing cost
+    for (int j = i; j > 0 && cost[j] > cost[j - 1]; --j) {
+      std::swap(cost[j], cost[j - 1]);
+      std::swap(segs.s[j], segs.s[j - 1]);
+    }
+  int64_t nitems = 0;
+  for (int i = 0; i < segs.n; ++i) {
+    segs.s[i].item0 = nitems;
+    nitems += (segs.s[i].nelmt + segs.s[i].elems - 1) / segs.s[i].elems;
+  }
+  if (nitems > kNoallocMaxItems)
+    return fail(NIR_EINVAL,
+                "the batches form %lld work items; the allocation-free apply holds at most %lld "
+                "(use a mixed plan, or split the call)",
+                (long long)nitems, (long long)kNoallocMaxItems);
+  char* base = nullptr;
+  int ncu = 0;
+  NIR_TRYS(noalloc_scratch(&base, &ncu));
+  double* dlam = reinterpret_cast<double*>(base);
+  MixedBatch<T>* ddesc = reinterpret_cast<MixedBatch<T>*>(base + kNoallocDescOff);
+  MixedItem* ditems = reinterpret_cast<MixedItem*>(base + kNoallocItemOff);
+  // descriptors, lambda and the work list, written by kernels on the caller's stream
+  for (int b0 = 0; b0 < nbatch; b0 += kNoallocDescChunk) {
+    NoallocDescs<T> d;
+    std::memset(&d, 0, sizeof(d));
+    d.first = b0;
+    d.n = std::min(kNoallocDescChunk, nbatch - b0);
+    for (int k = 0; k < d.n; ++k) {
+      const int b = b0 + k;
+      MixedBatch<T>& m = d.d[k];
+      m.shape = batches[b].shape;
+      m.P = batches[b].nmodes;
+      m.deformed = batches[b].deformed;
+      m.nelmt = batches[b].nelmt;
+      m.x = static_cast<const T*>(coef_in[b]);
+      m.y = static_cast<T*>(coef_out[b]);
+      m.helm = static_cast<const T*>(geoms[b].helm);
+      if constexpr (sizeof(T) == 8) {
+        m.tb = bases[b]->t64;
+        m.pencil = bases[b]->pencil64;
+      } else {
+        m.tb = bases[b]->t32;
+        m.pencil = bases[b]->pencil32;
+      }
+    }
+    hipLaunchKernelGGL((k_mixed_descriptors<T>), dim3(1), dim3(64), 0, s, d, ddesc);
+    NIR_TRYS(hip_check(hipGetLastError(), "descriptor kernel launch"));
+  }
+  hipLaunchKernelGGL(k_mixed_worklist, dim3(unsigned((nitems + 255) / 256)), dim3(256), 0, s, segs, lambda, dlam,
+                     ditems, nitems);
+  NIR_TRYS(hip_check(hipGetLastError(), "work-list kernel launch"));
+  // the persistent kernel at the largest register budget (2 waves per SIMD, no spills) and one
+  // full wave of resident workgroups
+  const int grid = int(std::min<int64_t>(int64_t(std::max(1, mixed_occupancy<T>(2))) * ncu, nitems));
+  return launch_mixed<T>(2, grid, s, ddesc, ditems, int(nitems), nullptr, dlam);
+}
+
+}  // namespace nir
+
+extern "C" {
+
+nir_status nir_mixed_helmholtz_apply_noalloc(int32_t nbatch, const nir_batch* batches, const nir_basis* const* bases,
+                                             const nir_geom* geoms, double lambda, const void* const* coef_in,
+                                             void* const* coef_out, void* stream) {
+  if (nbatch < 1 || !batches || !bases || !geoms || !coef_in || !coef_out)
+    return fail(NIR_EINVAL, "empty or NULL batch list");
+  if (nbatch > kNoallocMaxBatch)
+    return fail(NIR_EINVAL, "%d batches; the allocation-free apply takes at most %d", nbatch, kNoallocMaxBatch);
+  if (!(lambda == lambda)) return fail(NIR_EINVAL, "lambda is NaN");
+  const int dtype = batches[0].dtype;
+  const size_t es = dtype == NIR_F64 ? 8 : 4;
+  for (int b = 0; b < nbatch; ++b) {
+    const nir_batch& B = batches[b];
+    NIR_TRYS(nir_validate_batch(&B, bases[b]));
+    if (B.dtype != dtype) return fail(NIR_EINVAL, "all batches share one dtype");
+    if (B.math != NIR_MATH_NATIVE) return fail(NIR_ENOTSUP, "the persistent kernel uses native contractions");
+    if (B.nelmt == 0) continue;
+    if (B.nmodes > kMixedMaxP)
+      return fail(NIR_ENOTSUP, "batch %d: the persistent kernel covers P <= %d", b, kMixedMaxP);
+    if (!geoms[b].helm) return fail(NIR_EINVAL, "batch %d has no Helmholtz factors", b);
+    if (!coef_in[b] || !coef_out[b]) return fail(NIR_EINVAL, "batch %d: NULL coefficient pointer", b);
+    if ((reinterpret_cast<uintptr_t>(coef_in[b]) % es) || (reinterpret_cast<uintptr_t>(coef_out[b]) % es) ||
+        (reinterpret_cast<uintptr_t>(geoms[b].helm) % es))
+      return fail(NIR_EINVAL, "batch %d: misaligned pointer", b);
+    const size_t nb = size_t(B.nelmt) * size_t(modes_of(B.shape, B.nmodes)) * es;
+    const char* i = static_cast<const char*>(coef_in[b]);
+    const char* o = static_cast<const char*>(coef_out[b]);
+    if (i < o + nb && o < i + nb) return fail(NIR_EINVAL, "batch %d: input and output overlap", b);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return dtype == NIR_F64 ? noalloc_apply<double>(nbatch, batches, bases, geoms, lambda, coef_in, coef_out, s)
+                          : noalloc_apply<float>(nbatch, batches, bases, geoms, lambda, coef_in, coef_out, s);
 }
 
 }  // extern "C"

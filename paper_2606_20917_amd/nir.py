@@ -96,6 +96,7 @@ _SIGS = {
     "nir_mixed_plan_set_strategy": (_i32, [_vp, _i32]),
     "nir_mixed_plan_timings": (_i32, [_vp, _vp, _vp, _vp]),
     "nir_mixed_plan_destroy": (_i32, [_vp]),
+    "nir_mixed_helmholtz_apply_noalloc": (_i32, [_i32, _vp, _vp, _vp, _dbl, _vp, _vp, _vp]),
     "nir_get_helmholtz_variant": (_i32, [_i32, _i32, _i32]),
     "nir_autotune_helmholtz": (_i32, [ctypes.POINTER(nir_batch), _vp, ctypes.POINTER(nir_geom), _dbl, _vp, _vp, _i32,
                                       _vp, _vp, _vp]),
@@ -521,6 +522,27 @@ def nir_mixed_helmholtz_apply(plan, lam, coef_in, coef_out, stream=None):
     outs = (ctypes.c_void_p * n)(*[_ptr(x) for x in coef_out])
     _check(lib().nir_mixed_helmholtz_apply(plan.handle, lam, ctypes.cast(ins, _vp), ctypes.cast(outs, _vp),
                                            _stream(stream)))
+
+
+def nir_mixed_helmholtz_apply_noalloc(batches, bases, geoms, lam, coef_in, coef_out, stream=None):
+    """One persistent mixed apply with no plan and no allocation (lists of nir_batch, Basis,
+    nir_geom and coefficient tensors, one entry per batch)."""
+    n = len(batches)
+    if not (len(bases) == len(geoms) == len(coef_in) == len(coef_out) == n):
+        raise NirError(1, "batches, bases, geoms, coef_in and coef_out differ in length")
+    for k, bb in enumerate(batches):
+        ne, M, _, _ = _dims(bb)
+        _need_geom(bb, geoms[k], helm=True)
+        _need(coef_in[k], f"coef_in[{k}]", ne * M, bb.dtype)
+        _need(coef_out[k], f"coef_out[{k}]", ne * M, bb.dtype)
+    b = (nir_batch * n)(*batches)
+    h = (ctypes.c_void_p * n)(*[_basis(x).value if hasattr(_basis(x), "value") else _basis(x) for x in bases])
+    g = (nir_geom * n)(*geoms)
+    ins = (ctypes.c_void_p * n)(*[_ptr(x) for x in coef_in])
+    outs = (ctypes.c_void_p * n)(*[_ptr(x) for x in coef_out])
+    _check(lib().nir_mixed_helmholtz_apply_noalloc(n, ctypes.cast(b, _vp), ctypes.cast(h, _vp), ctypes.cast(g, _vp),
+                                                   lam, ctypes.cast(ins, _vp), ctypes.cast(outs, _vp),
+                                                   _stream(stream)))
 
 
 def nir_autotune_helmholtz(b, basis, g, lam, coef_in, coef_out, reps=10, stream=None):
