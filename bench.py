@@ -8,6 +8,14 @@ section 4.2), summed over the five orders.  Inputs are resident in HBM before th
 timed region; buffer sets rotate so that every launch streams from HBM (a working
 set under 1.2 GB is replicated until the rotation exceeds it).
 
+With no --workload (and without --headline-only) the same run then measures the rest of the
+metric, each as a key of the one JSON line: the FP32 hex apply (hex_f32), the collapsed shapes in
+FP64 against the FP64-VALU (tet) or HBM (prism) roofline (collapsed_f64), the 100k-element mixed
+mesh with the persistent launch and the per-batch graph in FP32 and FP64 (mixed100k), and the
+assembled solve's time to 1e-10 in FP64, with FP32-inner and with FP16-split-inner refinement
+(cg48).  cpu_baseline is the FP64 oracle on the host: median of three runs with BLAS on every core
+the process may use, plus one single-core run.
+
 Prints one JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 """
 import argparse
@@ -64,33 +72,67 @@ def setup(P, dtype_name, n=32, mathmode=0):
                 amp=c["amp"], nsets=nsets)
 
 
-def cpu_baseline(cases, budget_s):
-    """The FP64 oracle (dense matrices, numpy/BLAS) on a bounded sample of each order."""
-    from threadpoolctl import threadpool_info
-    from oracle import geometry as og, operators as op
-    dof, t_tot, samples, errs = 0, 0.0, [], {}
-    per_p = budget_s / len(cases)
-    for c in cases:
-        P, Q = c["P"], c["Q"]
-        tab = op.Tables(0, P, Q)
-        n = min(c["ne"], 4096)
-        geo = og.Geometry(0, Q, c["verts"][:n], c["amp"])
-        # repeated applies of the oracle on the sample until the per-order budget is spent
+def cpu_model():
+    """Model name of the host CPU (/proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_rate(cases, geos, per_p, nmax):
+    """FP64 oracle GDoF/s over repeated applies of the first nmax elements of each order."""
+    from oracle import operators as op
+    dof, t_tot, samples, refs = 0, 0.0, [], {}
+    for c, (tab, geo) in zip(cases, geos):
+        P, n = c["P"], min(c["ne"], nmax)
         reps, dt = 0, 0.0
         while dt < per_p:
             t = time.perf_counter()
-            ref = op.helmholtz(tab, geo, 1.0, c["coef"][:n])
+            refs[P] = op.helmholtz(tab, geo, 1.0, c["coef"][:n])
             dt += time.perf_counter() - t
             reps += 1
         dof += reps * n * P ** 3
         t_tot += dt
         samples.append(f"P={P}:{n}x{reps}")
-        y = c["sets"][0][2][:n].double().cpu().numpy()
+    return dof / t_tot / 1e9, t_tot, samples, refs
+
+
+def cpu_baseline(cases, budget_s):
+    """The FP64 oracle (dense matrices, numpy/BLAS) on a bounded sample of each order: three runs
+    with BLAS on every core available to the process (the median is the value), then one run on a
+    single core.  Geometry setup is outside the timing."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from oracle import geometry as og, operators as op
+    cores = len(os.sched_getaffinity(0))
+    def geos(n):
+        return [(op.Tables(0, c["P"], c["Q"]), og.Geometry(0, c["Q"], c["verts"][:min(c["ne"], n)], c["amp"]))
+                for c in cases]
+
+    per_run = budget_s / 4.0 / len(cases)
+    with threadpool_limits(limits=cores):
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        g = geos(4096)
+        runs = [_oracle_rate(cases, g, per_run, 4096) for _ in range(3)]
+    g = geos(1024)
+    with threadpool_limits(limits=1):
+        one = _oracle_rate(cases, g, per_run, 1024)
+    errs = {}
+    for c in cases:
+        P, ref = c["P"], runs[0][3][c["P"]]
+        y = c["sets"][0][2][:ref.shape[0]].double().cpu().numpy()
         errs[P] = float((np.linalg.norm(y - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
-    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    return {"value": dof / t_tot / 1e9, "unit": "GDoF/s", "cores": int(threads), "kind": "oracle",
-            "sample": "first elements x repeated applies of the same mesh per order (" + ", ".join(samples)
-                      + f"), {t_tot:.1f} s of FP64 oracle work, geometry setup excluded"}, errs
+    vals = sorted(r[0] for r in runs)
+    return {"value": vals[1], "unit": "GDoF/s", "cores": int(min(threads, cores)), "kind": "oracle",
+            "cpu": cpu_model(), "affinity_cores": cores, "runs": [round(v, 5) for v in vals],
+            "single_core_value": one[0],
+            "sample": "median of 3 runs, each repeated applies of the first elements of the hex_sin32 mesh per "
+                      "order (" + ", ".join(runs[0][2]) + f"), {sum(r[1] for r in runs):.1f} s of FP64 oracle work "
+                      f"in all; single core: " + ", ".join(one[2]) + f", {one[1]:.1f} s; geometry setup excluded"}, errs
 
 
 # HBM bytes per launch of the dominant kernel measured with FETCH_SIZE / WRITE_SIZE (calibrated
@@ -127,6 +169,10 @@ def oracle_residual(verts, amp, n, P, lam, x, chunk=2048):
 
 
 def bench_cg(args):
+    print(json.dumps(run_cg(args, oracle=not args.no_cpu)), flush=True)
+
+
+def run_cg(args, oracle=True):
     """Assembled Jacobi-PCG on 48^3 curved hexes, P=6: FP64 vs FP32-inner refinement, time to 1e-10."""
     import torch
     from paper_2606_20917_amd import inputs, nir
@@ -172,15 +218,21 @@ def bench_cg(args):
         wall = time.perf_counter() - t
         out[name] = {"seconds": round(wall, 4), "inner_iters": info.inner_iters, "outer_iters": info.outer_iters,
                      "rel_residual_gpu": info.rel_residual, "xsum": float(x.sum())}
-        if not args.no_cpu:
+        if oracle:
             out[name]["rel_residual_oracle"] = oracle_residual(c["verts"], amp, n, P, lam, x.cpu().numpy())
     out["value"] = out["mixed_f32"]["seconds"]
     out["speedup_mixed_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed_f32"]["seconds"], 3)
     out["speedup_f16split_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed_f16split"]["seconds"], 3)
-    print(json.dumps(out), flush=True)
+    del plan, A, l2g, helm, helm32, bg, x, dv
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_mixed(args):
+    print(json.dumps(run_mixed(args)), flush=True)
+
+
+def run_mixed(args, eager=True, auto=True):
     """100k mixed elements (hex/prism/tet, P in 3..8, curved), FP32 and FP64: eager per-(shape, P)
     launches, and the mixed plan with its persistent launch, its graph of per-batch launches on
     parallel branches, and its own choice between the two."""
@@ -225,10 +277,12 @@ def bench_mixed(args):
         plans = {}
         for name, strat in (("plan_persistent", nir.MIXED_PERSISTENT), ("plan_per_batch_graph", nir.MIXED_PER_BATCH),
                             ("plan_auto", nir.MIXED_AUTO)):
+            if strat == nir.MIXED_AUTO and not auto:
+                continue
             plans[name] = nir.MixedPlan(batches, [b["basis"] for b in bs], geoms)
             plans[name].set_strategy(strat)
         res = {}
-        fns = [("per_batch_eager", per_batch)] + [
+        fns = ([("per_batch_eager", per_batch)] if eager else []) + [
             (name, (lambda p: (lambda: nir.nir_mixed_helmholtz_apply(p, 1.0, xs, ys, stream)))(p))
             for name, p in plans.items()]
         for name, fn in fns:
@@ -247,8 +301,12 @@ def bench_mixed(args):
             if name in plans:
                 res[name]["info"] = plans[name].info()
         out[dt_name] = res
-    out["value"] = out["f32"]["plan_auto"]["gdofs"]
-    print(json.dumps(out), flush=True)
+        del plans
+    best = max(v["gdofs"] for k, v in out["f32"].items() if k.startswith("plan_"))
+    out["value"] = out["f32"]["plan_auto"]["gdofs"] if auto else best
+    del bs
+    torch.cuda.empty_cache()
+    return out
 
 
 def collapsed_model(shape, P, s, deformed):
@@ -265,7 +323,26 @@ def collapsed_model(shape, P, s, deformed):
     return M, byts, flops
 
 
+def algorithmic_flops(shape, P):
+    """Algorithmic FLOPs per element of the fused Helmholtz apply in its sum-factorised form (MAC = 2):
+    hex 4(P^3 Q + P^2 Q^2 + P Q^3), prism 4(M Q + P^2 Q^2 + P Q^3), tet 4(M Q + P(P+1)/2 Q^2 + P Q^3)
+    for the value sweeps and their transposes, plus 12 Q^4 for the collocation derivatives and 21, 30
+    or 40 Q^3 for the pointwise step (the eta -> xi chain rule of the collapsed shapes included)."""
+    Q = P + 1
+    if shape == 0:
+        return 4 * (P ** 3 * Q + P ** 2 * Q ** 2 + P * Q ** 3) + 12 * Q ** 4 + 21 * Q ** 3
+    if shape == 1:
+        M = P * P * (P + 1) // 2
+        return 4 * (M * Q + P * P * Q * Q + P * Q ** 3) + 12 * Q ** 4 + 30 * Q ** 3
+    M = P * (P + 1) * (P + 2) // 6
+    return 4 * (M * Q + P * (P + 1) // 2 * Q * Q + P * Q ** 3) + 12 * Q ** 4 + 40 * Q ** 3
+
+
 def bench_collapsed(args):
+    print(json.dumps(run_collapsed(args)), flush=True)
+
+
+def run_collapsed(args, dtypes=("f64", "f32"), generic=True):
     """24^3 cube split into 82944 affine tets (per-element factors) or 27648 prisms (per-point
     factors), P in {3, 5, 8}: fused Helmholtz GDoF/s against the FP64-VALU (tet) or HBM (prism) roofline."""
     import torch
@@ -277,6 +354,8 @@ def bench_collapsed(args):
                                   "per-point factors), 24^3 cube with +-0.03h jitter, lambda=1, Q=P+1"}}
     for name, gen, shape in (("tet", inputs.tet24, nir.TET), ("prism", inputs.prism24, nir.PRISM)):
         for dt_name, dt in (("f64", nir.F64), ("f32", nir.F32)):
+            if dt_name not in dtypes:
+                continue
             s = 8 if dt == nir.F64 else 4
             tdt = torch.float64 if dt == nir.F64 else torch.float32
             for P in (3, 5, 8):
@@ -309,24 +388,33 @@ def bench_collapsed(args):
                     torch.cuda.synchronize()
                     return e0.elapsed_time(e1) / args.steps
 
-                try:   # the LDS-staged generic kernel beside the default (register-pencil) one
-                    nir.nir_set_helmholtz_variant(shape, P, dt, nir.VARIANT_GENERIC)
-                    ms_generic = timed()
-                finally:
-                    nir.nir_set_helmholtz_variant(shape, P, dt, nir.VARIANT_AUTO)
+                ms_generic = None
+                if generic:
+                    try:   # the LDS-staged generic kernel beside the default (register-pencil) one
+                        nir.nir_set_helmholtz_variant(shape, P, dt, nir.VARIANT_GENERIC)
+                        ms_generic = timed()
+                    finally:
+                        nir.nir_set_helmholtz_variant(shape, P, dt, nir.VARIANT_AUTO)
                 ms = timed()
                 gbs = ne * byts / ms / 1e6
-                tfl = ne * flops / ms / 1e9
+                # FP64/FP32 VALU fraction against the algorithmic FLOPs of the method; the
+                # kernel's own count (derivatives through B' tables) beside it
+                alg = algorithmic_flops(shape, P)
+                tfl = ne * alg / ms / 1e9
                 peak_fl = 78.6 if dt == nir.F64 else 157.3
-                out[f"{name}_P{P}_{dt_name}"] = {
-                    "nelmt": ne, "ms": round(ms, 4), "gdofs": round(ne * M / ms / 1e6, 3), "gbs": round(gbs, 1),
-                    "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "tflops": round(tfl, 2),
-                    "frac_valu": round(tfl / peak_fl, 4),
-                    "bound": "hbm" if byts * 9.8 > flops or deformed else "alu",
-                    "variant": nir.nir_get_helmholtz_variant(shape, P, dt),
-                    "generic_gdofs": round(ne * M / ms_generic / 1e6, 3)}
+                r = {"nelmt": ne, "ms": round(ms, 4), "gdofs": round(ne * M / ms / 1e6, 3), "gbs": round(gbs, 1),
+                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "flop_per_dof": round(alg / M, 1),
+                     "tflops": round(tfl, 2), "frac_valu": round(tfl / peak_fl, 4),
+                     "frac_valu_kernel_count": round(ne * flops / ms / 1e9 / peak_fl, 4),
+                     "bound": "hbm" if deformed else "alu",
+                     "variant": nir.nir_get_helmholtz_variant(shape, P, dt)}
+                if ms_generic is not None:
+                    r["generic_gdofs"] = round(ne * M / ms_generic / 1e6, 3)
+                out[f"{name}_P{P}_{dt_name}"] = r
+                del sets, x, helm, helm32, g
+                torch.cuda.empty_cache()
     out["value"] = out["tet_P5_f64"]["gdofs"]
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_ops(args):
@@ -717,6 +805,8 @@ def main():
     ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k", "collapsed", "copy", "ops", "fields", "trilinear",
                              "nodal", "convergence"])
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the FP64 hex apply and the oracle baseline (no FP32 hex, collapsed, mixed, CG)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus must be 1)",
@@ -750,12 +840,48 @@ def main():
            "split": nir.VARIANT_PENCIL_SPLIT, "gp": nir.VARIANT_PENCIL_GP,
            "split_gp": nir.VARIANT_PENCIL_SPLIT_GP, "eo": nir.VARIANT_PENCIL_EO,
            "eo_split": nir.VARIANT_PENCIL_EO_SPLIT}[args.variant]
-    for P in ps:
-        nir.nir_set_helmholtz_variant(nir.HEX, P, nir.F64 if args.dtype == "f64" else nir.F32, vid)
     if args.math == "f16split" and args.dtype != "f32":
         print("--math f16split needs --dtype f32", file=sys.stderr)
         sys.exit(2)
-    cases = [setup(P, args.dtype, mathmode=nir.MATH_F16SPLIT if args.math == "f16split" else nir.MATH_NATIVE)
+    out, cases = run_hex(args, ps, args.dtype, args.math, vid)
+    if not args.no_cpu:
+        out["cpu_baseline"], errs = cpu_baseline(cases, args.cpu_seconds)
+        out["max_rel_err_vs_oracle"] = {f"P{p}": e for p, e in errs.items()}
+    del cases
+    torch.cuda.empty_cache()
+    if not args.headline_only:
+        # the rest of the metric, measured in the same run after the headline: the FP32 hex apply,
+        # the collapsed shapes in FP64, the mixed mesh with both launch strategies, and the
+        # assembled solve's time to 1e-10 in FP64 and with FP32-inner refinement
+        other = "f32" if args.dtype == "f64" else "f64"
+        o32, c32 = run_hex(args, ps, other, "native", nir.VARIANT_AUTO)
+        del c32
+        out[f"hex_{other}"] = {"value": o32["value"], "unit": "GDoF/s", "ms_per_step": o32["ms_per_step"],
+                               "roofline": o32["roofline"], "breakdown": o32["breakdown"]}
+        col = run_collapsed(args, dtypes=("f64",), generic=False)
+        out["collapsed_f64"] = {k: v for k, v in col.items() if k.startswith(("tet_", "prism_"))}
+        out["collapsed_f64"]["workload"] = col["config"]["workload"]
+        mx = run_mixed(args, eager=False, auto=False)
+        out["mixed100k"] = {"workload": mx["config"]["workload"],
+                            "f32": {k: {kk: v[kk] for kk in ("ms", "gdofs", "frac_hbm")} for k, v in mx["f32"].items()},
+                            "f64": {k: {kk: v[kk] for kk in ("ms", "gdofs", "frac_hbm")} for k, v in mx["f64"].items()}}
+        cg = run_cg(args, oracle=False)
+        out["cg48"] = {"workload": cg["config"]["workload"], "unit": "s", "inner_rtol": args.inner_rtol,
+                       "speedup_mixed_vs_fp64": cg["speedup_mixed_vs_fp64"],
+                       "speedup_f16split_vs_fp64": cg["speedup_f16split_vs_fp64"]}
+        for k in ("fp64", "mixed_f32", "mixed_f16split"):
+            out["cg48"][k] = {kk: cg[k][kk] for kk in ("seconds", "inner_iters", "outer_iters", "rel_residual_gpu")}
+    print(json.dumps(out), flush=True)
+
+
+def run_hex(args, ps, dtype, mathname, vid):
+    """The headline step: the fused Helmholtz apply on hex_sin32 at every order of `ps`, timed with
+    HIP events around each launch on the launch stream; returns (result dict, cases)."""
+    import torch
+    from paper_2606_20917_amd import nir
+    for P in ps:
+        nir.nir_set_helmholtz_variant(nir.HEX, P, nir.F64 if dtype == "f64" else nir.F32, vid)
+    cases = [setup(P, dtype, mathmode=nir.MATH_F16SPLIT if mathname == "f16split" else nir.MATH_NATIVE)
              for P in ps]
     stream = torch.cuda.current_stream()
 
@@ -785,7 +911,7 @@ def main():
     total_ms = t0.elapsed_time(t1)
     dof_step = sum(c["ne"] * c["P"] ** 3 for c in cases)
     value = dof_step * args.steps / (total_ms * 1e-3) / 1e9
-    s = 8 if args.dtype == "f64" else 4
+    s = 8 if dtype == "f64" else 4
     breakdown = {}
     for c in cases:
         ms = sum(a.elapsed_time(b) for a, b in ev[c["P"]]) / args.steps
@@ -797,32 +923,30 @@ def main():
     dom = max(cases, key=lambda c: breakdown[f"P{c['P']}"]["ms"])
     dms = breakdown[f"P{dom['P']}"]["ms"]
     achieved = hex_bytes(dom["P"], s) * dom["ne"] / (dms * 1e-3) / 1e9
+    variant_now = nir.nir_get_helmholtz_variant(nir.HEX, dom["P"], nir.F64 if dtype == "f64" else nir.F32)
+    for P in ps:
+        nir.nir_set_helmholtz_variant(nir.HEX, P, nir.F64 if dtype == "f64" else nir.F32, nir.VARIANT_AUTO)
+    traffic_ok = (TRAFFIC["P"] == dom["P"] and TRAFFIC["dtype"] == dtype and mathname == "native"
+                  and variant_now == TRAFFIC["variant"]
+                  and kernel_src_sha() == TRAFFIC["src_sha"])
     out = {
         "metric": "Helmholtz apply GDoF/s & %HBM roofline, FP64 vs FP32/mixed, hex P=2-10",
         "value": round(value, 3), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(total_ms / args.steps, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": args.dtype + ("+f16split-mfma" if args.math == "f16split" else ""),
+        "vs_baseline": None, "dtype": dtype + ("+f16split-mfma" if mathname == "f16split" else ""),
         "data": "synthetic",
         "config": {"workload": "hex_sin32: 32^3 = 32768 curved hexes (sin deformation 0.1), per-point factors, "
                                "fused Helmholtz lambda=1, P in {" + ",".join(map(str, ps)) + "}, Q=P+1",
                    "nelmt": cases[0]["ne"], "orders": ps, "kernel": "nir_helmholtz_apply"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": (TRAFFIC["bytes"] if (TRAFFIC["P"] == dom["P"] and TRAFFIC["dtype"] == args.dtype
-                                                      and args.math == "native"
-                                                      and nir.nir_get_helmholtz_variant(
-                                                          nir.HEX, dom["P"], nir.F64 if args.dtype == "f64" else nir.F32)
-                                                      == TRAFFIC["variant"]
-                                                      and kernel_src_sha() == TRAFFIC["src_sha"]) else None),
+                     "traffic": TRAFFIC["bytes"] if traffic_ok else None,
                      "kernel": f"hex Helmholtz P={dom['P']}",
                      "bytes_per_launch": hex_bytes(dom["P"], s) * dom["ne"]},
         "breakdown": breakdown,
         "wall_s": round(wall, 3),
     }
-    if not args.no_cpu:
-        out["cpu_baseline"], errs = cpu_baseline(cases, args.cpu_seconds)
-        out["max_rel_err_vs_oracle"] = {f"P{p}": e for p, e in errs.items()}
-    print(json.dumps(out), flush=True)
+    return out, cases
 
 
 if __name__ == "__main__":

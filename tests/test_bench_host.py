@@ -41,3 +41,17 @@ def test_collapsed_byte_model(shape, P, s, deformed):
     assert M == op.Tables(shape, P, Q).M
     assert byts == s * (2 * M + 7 * (Q ** 3 if deformed else 1))
     assert flops > 0
+
+
+@pytest.mark.parametrize("shape,P,flop_per_dof", [(0, 2, 249), (0, 6, 266), (0, 10, 349), (2, 3, 694), (2, 5, 900),
+                                                  (2, 8, 1227)])
+def test_algorithmic_flop_counts(shape, P, flop_per_dof):
+    """The FLOP model behind frac_valu: sum-factorised value sweeps both ways, 12 Q^4 collocation
+    derivatives and the pointwise step, per local DoF, as tabulated for hexahedra and affine tets."""
+    M = op.Tables(shape, P, P + 1).M
+    assert round(_bench().algorithmic_flops(shape, P) / M) == flop_per_dof
+
+
+def test_cpu_model_is_read_from_proc():
+    model = _bench().cpu_model()
+    assert model is None or (isinstance(model, str) and model)
