@@ -312,28 +312,32 @@ def run_mixed(args, eager=True, auto=True):
 def collapsed_model(shape, P, s, deformed):
     """Algorithmic bytes and FLOPs per element of the fused Helmholtz apply on a collapsed shape."""
     Q = P + 1
-    M = P * P * (P + 1) // 2 if shape == 1 else P * (P + 1) * (P + 2) // 6
+    M = {1: P * P * (P + 1) // 2, 2: P * (P + 1) * (P + 2) // 6, 3: P * (P + 1) * (2 * P + 1) // 6}[shape]
     npts = Q ** 3 if deformed else 1
     byts = s * (2 * M + 7 * npts)
     # sum-factorised count (value and derivative sweeps forward, their transposes backward):
     # A/A^T 2 tables x M x Q, B/B^T 3 x pairs x Q^2 (tet: pair (0,1) once more), C/C^T 4 x P x Q^3
     # multiply-adds each way, plus the pointwise chain rule, factors and mass term
-    npair = (P * P if shape == 1 else P * (P + 1) // 2 + 1)
+    npair = P * P + 1 if shape == 3 else (P * P if shape == 1 else P * (P + 1) // 2 + 1)
     flops = 2 * 2 * (2 * M * Q + 3 * npair * Q * Q + 4 * P * Q ** 3) + (30 if shape == 1 else 40) * Q ** 3
     return M, byts, flops
 
 
 def algorithmic_flops(shape, P):
     """Algorithmic FLOPs per element of the fused Helmholtz apply in its sum-factorised form (MAC = 2):
-    hex 4(P^3 Q + P^2 Q^2 + P Q^3), prism 4(M Q + P^2 Q^2 + P Q^3), tet 4(M Q + P(P+1)/2 Q^2 + P Q^3)
-    for the value sweeps and their transposes, plus 12 Q^4 for the collocation derivatives and 21, 30
-    or 40 Q^3 for the pointwise step (the eta -> xi chain rule of the collapsed shapes included)."""
+    hex 4(P^3 Q + P^2 Q^2 + P Q^3), prism and pyramid 4(M Q + P^2 Q^2 + P Q^3), tet
+    4(M Q + P(P+1)/2 Q^2 + P Q^3) for the value sweeps and their transposes, plus 12 Q^4 for the
+    collocation derivatives and 21, 30 or 40 Q^3 for the pointwise step (the eta -> xi chain rule of
+    the collapsed shapes included; 40 for the two collapsed directions of tets and pyramids)."""
     Q = P + 1
     if shape == 0:
         return 4 * (P ** 3 * Q + P ** 2 * Q ** 2 + P * Q ** 3) + 12 * Q ** 4 + 21 * Q ** 3
     if shape == 1:
         M = P * P * (P + 1) // 2
         return 4 * (M * Q + P * P * Q * Q + P * Q ** 3) + 12 * Q ** 4 + 30 * Q ** 3
+    if shape == 3:
+        M = P * (P + 1) * (2 * P + 1) // 6
+        return 4 * (M * Q + P * P * Q * Q + P * Q ** 3) + 12 * Q ** 4 + 40 * Q ** 3
     M = P * (P + 1) * (P + 2) // 6
     return 4 * (M * Q + P * (P + 1) // 2 * Q * Q + P * Q ** 3) + 12 * Q ** 4 + 40 * Q ** 3
 
@@ -350,9 +354,11 @@ def run_collapsed(args, dtypes=("f64", "f32"), generic=True):
     dev = torch.device("cuda")
     out = {"metric": "collapsed-shape Helmholtz apply GDoF/s and roofline fraction", "unit": "GDoF/s",
            "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
-           "config": {"workload": "tet24 (82944 affine tets, per-element factors) and prism24 (27648 prisms, "
-                                  "per-point factors), 24^3 cube with +-0.03h jitter, lambda=1, Q=P+1"}}
-    for name, gen, shape in (("tet", inputs.tet24, nir.TET), ("prism", inputs.prism24, nir.PRISM)):
+           "config": {"workload": "tet24 (82944 affine tets, per-element factors), prism24 (27648 prisms, "
+                                  "per-point factors) and pyr24 (82944 pyramids, per-point factors), 24^3 cube "
+                                  "with +-0.03h jitter, lambda=1, Q=P+1"}}
+    for name, gen, shape in (("tet", inputs.tet24, nir.TET), ("prism", inputs.prism24, nir.PRISM),
+                             ("pyr", inputs.pyr24, nir.PYR)):
         for dt_name, dt in (("f64", nir.F64), ("f32", nir.F32)):
             if dt_name not in dtypes:
                 continue
@@ -859,7 +865,7 @@ def main():
         out[f"hex_{other}"] = {"value": o32["value"], "unit": "GDoF/s", "ms_per_step": o32["ms_per_step"],
                                "roofline": o32["roofline"], "breakdown": o32["breakdown"]}
         col = run_collapsed(args, dtypes=("f64",), generic=False)
-        out["collapsed_f64"] = {k: v for k, v in col.items() if k.startswith(("tet_", "prism_"))}
+        out["collapsed_f64"] = {k: v for k, v in col.items() if k.startswith(("tet_", "prism_", "pyr_"))}
         out["collapsed_f64"]["workload"] = col["config"]["workload"]
         mx = run_mixed(args, eager=False, auto=False)
         out["mixed100k"] = {"workload": mx["config"]["workload"],

@@ -2,8 +2,8 @@
  * nir.h - C ABI of the MI355X matrix-free spectral/hp operator library (libnir.so).
  *
  * The library evaluates the elemental operators of the spectral/hp element
- * method on batches ("blocks") of alike elements - hexahedra, prisms and
- * tetrahedra with a modified C0 Jacobi basis - and composes them into the
+ * method on batches ("blocks") of alike elements - hexahedra, prisms,
+ * tetrahedra and pyramids with a modified C0 Jacobi basis - and composes them into the
  * Helmholtz operator H = L + lambda M.  The paper's statement of the problem
  * (section 3.1: a block of elements sharing shape, order, quadrature and a
  * deformed flag; operators that take basis/weight/derivative tensors and
@@ -21,8 +21,12 @@
  *    supported by the kernels (NIR_ENOTSUP otherwise).
  *  - Modes of an element are stored contiguously, p outermost, r fastest,
  *    over the shape's mode set (hex p,q,r < P; prism r < P-p; tet q < P-p,
- *    r < P-p-q): the packed order of the tet map, section 2.2 eq. (18),
- *    read lexicographically.  M = nir_nmodes(shape, P).
+ *    r < P-p-q; pyramid r < P-max(p,q)): the packed order of the tet map,
+ *    section 2.2 eq. (18), read lexicographically.  M = nir_nmodes(shape, P).
+ *    The pyramid (no expansion in the paper) uses psi^a_p(eta1) psi^a_q(eta2)
+ *    psi^b_{max(p,q),r}(eta3), both eta1 and eta2 collapsed at the apex, mode
+ *    (0,0,1) being the apex function (1+eta3)/2; GLL points in eta1, eta2 and
+ *    Gauss-Radau-Jacobi (alpha = 2) points in eta3.
  *  - Quadrature values are stored [elem][i][j][k], k fastest, npts = Q^3.
  *  - Geometry is stored SoA within an element: [elem][component][npts], or
  *    [elem][component] when the batch is not deformed (affine elements).
@@ -55,7 +59,7 @@ typedef enum {
   NIR_ENOCONV = 7      /* iteration limit reached before the tolerance */
 } nir_status;
 
-typedef enum { NIR_HEX = 0, NIR_PRISM = 1, NIR_TET = 2 } nir_shape;
+typedef enum { NIR_HEX = 0, NIR_PRISM = 1, NIR_TET = 2, NIR_PYR = 3 } nir_shape;
 typedef enum { NIR_F64 = 0, NIR_F32 = 1 } nir_dtype;               /* storage of coef/phys/geom */
 typedef enum { NIR_MATH_NATIVE = 0, NIR_MATH_F16SPLIT = 1 } nir_math; /* contraction arithmetic */
 
@@ -72,7 +76,8 @@ typedef struct {
   int32_t math;      /* nir_math: NIR_MATH_F16SPLIT only with NIR_F32 */
 } nir_batch;
 
-/* Number of modes per element: P^3 (hex), P^2(P+1)/2 (prism), P(P+1)(P+2)/6 (tet); -1 if invalid. */
+/* Number of modes per element: P^3 (hex), P^2(P+1)/2 (prism), P(P+1)(P+2)/6 (tet),
+ * P(P+1)(2P+1)/6 (pyramid); -1 if invalid. */
 int64_t nir_nmodes(int32_t shape, int32_t P);
 
 /* Thread-local description of the last non-OK status returned on this thread. */
@@ -147,7 +152,11 @@ typedef enum { NIR_MAP_VERTEX = 0, NIR_MAP_VERTEX_SIN = 1 } nir_map;
  *   hex   (nv=8): (-1,-1,-1) (1,-1,-1) (1,1,-1) (-1,1,-1) (-1,-1,1) (1,-1,1) (1,1,1) (-1,1,1)
  *   prism (nv=6): (-1,-1,-1) (1,-1,-1) (1,1,-1) (-1,1,-1) (-1,-1,1) (-1,1,1)
  *   tet   (nv=4): (-1,-1,-1) (1,-1,-1) (-1,1,-1) (-1,-1,1)
- * Map: trilinear hex / linear-triangle x linear prism / affine tet of the vertices; with
+ *   pyramid (nv=5): (-1,-1,-1) (1,-1,-1) (1,1,-1) (-1,1,-1) (-1,-1,1)  (base, then apex)
+ * Map: trilinear hex / linear-triangle x linear prism / affine tet / the five pyramid vertex
+ * functions (bilinear base times (1-xi3)/2 plus the apex function (1+xi3)/2; affine when the
+ * base is a parallelogram) of the vertices; an affine batch (deformed = 0) evaluates its
+ * constant Jacobian at the reference centroid; with
  * NIR_MAP_VERTEX_SIN every component is then moved by amp*sin(2 pi x)sin(2 pi y)sin(2 pi z).
  * Outputs (device, FP64, any may be NULL): dxi_dx, jac, helm64 with npts as above;
  * helm32 (FP32, optional) = round-to-nearest copy of helm64.  The batch dtype is
@@ -372,9 +381,10 @@ nir_status nir_cg_plan_destroy(nir_cg_plan* plan);
  * (shape, P, dtype) is library-global state (one int per combination, set atomically), used by
  * nir_helmholtz_apply and by the CG plans' element apply:
  *   NIR_VARIANT_AUTO       built-in default (a pencil kernel per shape; for hexahedra the
- *                          per-order choice measured fastest on MI355X)
+ *                          per-order choice measured fastest on MI355X; the generic kernel for
+ *                          pyramids)
  *   NIR_VARIANT_GENERIC    LDS-staged kernel, threads over points/modes (any shape)
- *   NIR_VARIANT_PENCIL     register-pencil kernel with uniform basis operands (any shape; on
+ *   NIR_VARIANT_PENCIL     register-pencil kernel with uniform basis operands (not pyramids; on
  *                          prisms and tetrahedra the contractions whose 1-D factor depends on
  *                          p or p+q run one such index per wavefront)
  *   NIR_VARIANT_PENCIL_U2  hex pencil kernel with the streamed point loop unrolled twice

@@ -35,7 +35,7 @@ static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_
 
 static nir_status check_batch(const nir_batch* b, const nir_basis* basis) {
   if (!b) return fail(NIR_EINVAL, "batch descriptor is NULL");
-  if (b->shape < kHex || b->shape > kTet) return fail(NIR_EINVAL, "invalid shape %d", b->shape);
+  if (b->shape < kHex || b->shape > kPyr) return fail(NIR_EINVAL, "invalid shape %d", b->shape);
   if (b->nmodes < kMinP || b->nmodes > kMaxP)
     return fail(NIR_EINVAL, "nmodes P=%d outside [%d, %d]", b->nmodes, kMinP, kMaxP);
   if (b->nquad < b->nmodes) return fail(NIR_EINVAL, "nquad Q=%d < P=%d", b->nquad, b->nmodes);
@@ -91,11 +91,12 @@ static nir_status native_only(const nir_batch* b) {
 }
 
 // variant table [shape][P][dtype]; 0 = auto
-static std::atomic<int> g_variant[3][kMaxP + 1][2];
+static std::atomic<int> g_variant[4][kMaxP + 1][2];
 
 static int resolve_variant(int shape, int P, int dtype) {
   const int v = g_variant[shape][P][dtype].load(std::memory_order_relaxed);
   if (v != NIR_VARIANT_AUTO) return v;
+  if (shape == kPyr) return NIR_VARIANT_GENERIC;
   if (shape != kHex) return NIR_VARIANT_PENCIL;
   // defaults from a sweep of all variants on MI355X (32^3 curved hexes, per-point factors, the
   // fastest of four interleaved rounds per variant): the even-odd folded kernels where the
@@ -150,7 +151,7 @@ nir_status nir_quadrature_host(int32_t rule, int32_t alpha, int32_t Q, double* z
 }
 
 int64_t nir_table_size(int32_t shape, int32_t P, int32_t Q, int32_t id) {
-  if (shape < kHex || shape > kTet || P < 1 || P > 16 || Q < 2 || Q > 17) return -1;
+  if (shape < kHex || shape > kPyr || P < 1 || P > 16 || Q < 2 || Q > 17) return -1;
   const int64_t M = modes_of(shape, P), NP = pairs_of(shape, P), NQ = int64_t(Q) * Q * Q;
   switch (id) {
     case NIR_TAB_Z1: case NIR_TAB_Z2: case NIR_TAB_Z3:
@@ -184,7 +185,7 @@ nir_status nir_table_host(int32_t shape, int32_t P, int32_t Q, int32_t id, void*
 nir_status nir_basis_create(int32_t shape, int32_t P, int32_t Q, nir_basis** out) {
   if (!out) return fail(NIR_EINVAL, "out is NULL");
   *out = nullptr;
-  if (shape < kHex || shape > kTet) return fail(NIR_EINVAL, "invalid shape %d", shape);
+  if (shape < kHex || shape > kPyr) return fail(NIR_EINVAL, "invalid shape %d", shape);
   if (P < kMinP || P > kMaxP) return fail(NIR_EINVAL, "P=%d outside [%d, %d]", P, kMinP, kMaxP);
   if (Q != P + 1) return fail(NIR_ENOTSUP, "only Q = P+1 is supported");
   nir_basis* b = new (std::nothrow) nir_basis();
@@ -276,7 +277,7 @@ nir_status nir_basis_create(int32_t shape, int32_t P, int32_t Q, nir_basis** out
     const int H = (Q + 1) / 2, NE = 1 + (P - 1) / 2, neo = b->shape == kHex && Q == P + 1 ? H * 2 * P : 0;
     // collapsed shapes: the forward sweeps' factors in [slice][point][term] order (col_a_off,
     // col_b_off), values then derivatives
-    const bool col = b->shape != kHex && Q == P + 1;
+    const bool col = (b->shape == kPrism || b->shape == kTet) && Q == P + 1;
     const int na = col ? col_a_off(b->shape, P, P) : 0, nbt = col ? col_b_off(b->shape, P, P) : 0;
     std::vector<double> p64(2 * Q * P + neo + 2 * na + 2 * nbt);
     std::vector<float> p32(p64.size());
@@ -467,7 +468,8 @@ nir_status nir_bwd_trans(const nir_batch* b, const nir_basis* basis, const void*
   if (basis->shape == kHex)
     return launch_ops_hex_pencil(basis, kOpBwd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
   if (basis->shape == kPrism) return launch_bwd_col_prism(basis, b->dtype, a, static_cast<hipStream_t>(stream));
-  return launch_bwd_col_tet(basis, b->dtype, a, static_cast<hipStream_t>(stream));
+  if (basis->shape == kTet) return launch_bwd_col_tet(basis, b->dtype, a, static_cast<hipStream_t>(stream));
+  return launch_generic(basis, kOpBwd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
 }
 
 nir_status nir_iprod_wrt_base(const nir_batch* b, const nir_basis* basis, const nir_geom* g, const void* phys,
@@ -491,7 +493,9 @@ nir_status nir_iprod_wrt_base(const nir_batch* b, const nir_basis* basis, const 
     return launch_ops_hex_pencil(basis, kOpIProd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
   if (basis->shape == kPrism)
     return launch_iprod_col_prism(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
-  return launch_iprod_col_tet(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+  if (basis->shape == kTet)
+    return launch_iprod_col_tet(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+  return launch_generic(basis, kOpIProd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
 }
 
 nir_status nir_phys_deriv(const nir_batch* b, const nir_basis* basis, const nir_geom* g, const void* phys,
@@ -691,7 +695,7 @@ nir_status nir_autotune_helmholtz(const nir_batch* b, const nir_basis* basis, co
                              NIR_VARIANT_PENCIL_EO_SPLIT};
   const int cands_other[2] = {NIR_VARIANT_GENERIC, NIR_VARIANT_PENCIL};
   const int* cands = b->shape == kHex ? cands_hex : cands_other;
-  const int nc = b->shape == kHex ? 10 : 2;
+  const int nc = b->shape == kHex ? 10 : (b->shape == kPyr ? 1 : 2);
   hipEvent_t e0, e1;
   NIR_TRY(hip_check(hipEventCreate(&e0), "event"));
   NIR_TRY(hip_check(hipEventCreate(&e1), "event"));
@@ -782,18 +786,20 @@ nir_status nir_autotune_load(const char* path) {
 }
 
 nir_status nir_set_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype, int32_t variant) {
-  if (shape < kHex || shape > kTet || P < kMinP || P > kMaxP || (dtype != NIR_F64 && dtype != NIR_F32))
+  if (shape < kHex || shape > kPyr || P < kMinP || P > kMaxP || (dtype != NIR_F64 && dtype != NIR_F32))
     return fail(NIR_EINVAL, "invalid (shape %d, P %d, dtype %d)", shape, P, dtype);
   if (variant < NIR_VARIANT_AUTO || variant > NIR_VARIANT_PENCIL_EO_SPLIT)
     return fail(NIR_EINVAL, "invalid variant %d", variant);
   if (variant > NIR_VARIANT_PENCIL && shape != kHex)
     return fail(NIR_ENOTSUP, "variant %d is a hex kernel (prism and tet have GENERIC and PENCIL)", variant);
+  if (variant == NIR_VARIANT_PENCIL && shape == kPyr)
+    return fail(NIR_ENOTSUP, "pyramids have the GENERIC Helmholtz kernel only");
   g_variant[shape][P][dtype].store(variant, std::memory_order_relaxed);
   return NIR_OK;
 }
 
 int32_t nir_get_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype) {
-  if (shape < kHex || shape > kTet || P < kMinP || P > kMaxP || (dtype != NIR_F64 && dtype != NIR_F32)) return -1;
+  if (shape < kHex || shape > kPyr || P < kMinP || P > kMaxP || (dtype != NIR_F64 && dtype != NIR_F32)) return -1;
   return resolve_variant(shape, P, dtype);
 }
 
@@ -805,6 +811,7 @@ nir_status launch_generic(const nir_basis* b, int op, int dtype, int deformed, c
     case kHex: return launch_generic_hex(b, op, dtype, deformed, a, s);
     case kPrism: return launch_generic_prism(b, op, dtype, deformed, a, s);
     case kTet: return launch_generic_tet(b, op, dtype, deformed, a, s);
+    case kPyr: return launch_generic_pyr(b, op, dtype, deformed, a, s);
     default: return fail(NIR_EINVAL, "invalid shape");
   }
 }

@@ -30,9 +30,12 @@ struct Dims {
   static constexpr int Q = P + 1;
   static constexpr int Q2 = Q * Q;
   static constexpr int NQ = Q * Q * Q;
-  static constexpr int M = SHAPE == kHex ? P * P * P : (SHAPE == kPrism ? P * P * (P + 1) / 2 : P * (P + 1) * (P + 2) / 6);
+  static constexpr int M = SHAPE == kHex ? P * P * P
+                           : (SHAPE == kPrism ? P * P * (P + 1) / 2
+                                              : (SHAPE == kPyr ? P * (P + 1) * (2 * P + 1) / 6 : P * (P + 1) * (P + 2) / 6));
   static constexpr int NP = SHAPE == kTet ? P * (P + 1) / 2 : P * P;
-  static constexpr int NX = SHAPE == kTet ? 2 : (SHAPE == kPrism ? P : 0);   // correction rows
+  // correction rows of the transposed direction-2 sweep: tet X0, X1; prism X_q; pyramid X1
+  static constexpr int NX = SHAPE == kTet ? 2 : (SHAPE == kPrism ? P : (SHAPE == kPyr ? 1 : 0));
   static constexpr int TPE = NQ <= 32 ? 32 : (NQ <= 128 ? 64 : (NQ <= 343 ? 128 : 256));
   static constexpr int BLOCK = 256;
   static constexpr int E = BLOCK / TPE;
@@ -54,6 +57,10 @@ struct Chain {
     } else if (SHAPE == kPrism) {
       const T r = T(1) / (T(1) - e3);
       c00 = T(2) * r; c01 = T(0); c02 = (T(1) + e1) * r; c11 = T(1); c12 = T(0);
+    } else if (SHAPE == kPyr) {
+      // eta_1 and eta_2 both collapse towards the apex: d eta_1/d xi_1 = d eta_2/d xi_2 = 2/(1-eta_3)
+      const T r = T(1) / (T(1) - e3);
+      c00 = T(2) * r; c01 = T(0); c02 = (T(1) + e1) * r; c11 = T(2) * r; c12 = (T(1) + e2) * r;
     } else {
       const T r3 = T(1) / (T(1) - e3);
       const T ra = r3 / (T(1) - e2);
@@ -114,6 +121,9 @@ __device__ __forceinline__ T fwd_dir1_point(const DevTab<T>& tb, const T* c, con
     s += tb.T1[D::Q + i] * tb.T2[D::Q + j] * f1[D::Q + k];
     // mode (0,0,1) (index 1): + (1 - psi^a_0 psi^b_00) (1+eta3)/2
     s += c[1] * T(0.5) * (T(1) + tb.z[2][k]) * (T(1) - tb.T1[i] * tb.T2[j]);
+  } else if (SHAPE == kPyr) {
+    // apex mode (0,0,1) (index 1): + (1 - psi^a_0(eta1) psi^a_0(eta2)) (1+eta3)/2
+    s += c[1] * T(0.5) * (T(1) + tb.z[2][k]) * (T(1) - tb.T1[i] * tb.T2[j]);
   } else if (SHAPE == kPrism) {
     // modes (0,q,1) (index q*P+1): + psi^a_1(eta1) psi^a_q(xi2) psi^b_01(xi3)
     T t = T(0);
@@ -159,6 +169,10 @@ __device__ __forceinline__ void bwd_dir2(const DevTab<T>& tb, const T* g1, T* g2
       const int q = pr - D::NP;
 #pragma unroll
       for (int j = 0; j < D::Q; ++j) s += tb.T2[q * D::Q + j] * g1[(D::Q + j) * D::Q + k];
+    } else if (SHAPE == kPyr) {     // X1[k] = sum_ij (1 - psi^a_0(i) psi^a_0(j)) v[i][j][k]
+      // = sum_j psi^a_1(j) g1[0][j][k] + g1[1][j][k], since psi^a_0 + psi^a_1 = 1 (pair (0,1) = 1)
+#pragma unroll
+      for (int j = 0; j < D::Q; ++j) s += tb.T2[D::Q + j] * g1[j * D::Q + k] + g1[(D::Q + j) * D::Q + k];
     }
     g2[o] = s;
   }
@@ -185,6 +199,11 @@ __device__ __forceinline__ T bwd_dir3_mode(const DevTab<T>& tb, const T* g2, int
     if (p == 0 && r == 1) {
 #pragma unroll
       for (int k = 0; k < D::Q; ++k) s += T(0.5) * (T(1) + tb.z[2][k]) * g2[(D::NP + q) * D::Q + k];
+    }
+  } else if (SHAPE == kPyr) {
+    if (m == 1) {
+#pragma unroll
+      for (int k = 0; k < D::Q; ++k) s += T(0.5) * (T(1) + tb.z[2][k]) * g2[D::NP * D::Q + k];
     }
   }
   return s;

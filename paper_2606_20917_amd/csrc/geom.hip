@@ -3,8 +3,9 @@
 // Paper section 2.1: the weights matrix W is the quadrature weight times the
 // Jacobian determinant (text after eq. (8)) and the physical derivative needs
 // d xi_j / d x_i at every point (eq. (9)).  The element map is the vertex map
-// of the shape (trilinear hex, linear-triangle x linear prism, affine tet),
-// optionally followed by x_d += amp * sin(2 pi x) sin(2 pi y) sin(2 pi z).
+// of the shape (trilinear hex, linear-triangle x linear prism, affine tet, the
+// five pyramid vertex functions), optionally followed by
+// x_d += amp * sin(2 pi x) sin(2 pi y) sin(2 pi z).
 // One thread per (element, point); outputs are SoA per element, so a wave
 // writes consecutive points of one component (coalesced).
 
@@ -40,6 +41,24 @@ __device__ __forceinline__ void shape_fn(double x1, double x2, double x3, double
       dN[v][1] = l[a] * dg[b];
       dN[v][2] = dl[a][2] * g[b];
     }
+  } else if (SHAPE == kPyr) {
+    // t = 1 - xi_3 (> 0 away from the apex), a = (1+xi_1)/t, b = (1+xi_2)/t: base vertices
+    // A(a) B(b) t/2 with A in {1-a, a}, B in {1-b, b}; apex (1+xi_3)/2
+    const double t = 1.0 - x3, a = (1.0 + x1) / t, b = (1.0 + x2) / t;
+    const int sa[4] = {0, 1, 1, 0}, sb[4] = {0, 0, 1, 1};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double A = sa[v] ? a : 1.0 - a, dA = sa[v] ? 1.0 : -1.0;
+      const double B = sb[v] ? b : 1.0 - b, dB = sb[v] ? 1.0 : -1.0;
+      N[v] = 0.5 * A * B * t;
+      dN[v][0] = 0.5 * dA * B;
+      dN[v][1] = 0.5 * A * dB;
+      dN[v][2] = 0.5 * (dA * a * B + A * dB * b - A * B);
+    }
+    N[4] = 0.5 * (1.0 + x3);
+    dN[4][0] = 0.0;
+    dN[4][1] = 0.0;
+    dN[4][2] = 0.5;
   } else {
     N[0] = -0.5 * (1.0 + x1 + x2 + x3);
     N[1] = 0.5 * (1.0 + x1);
@@ -103,7 +122,7 @@ __global__ void __launch_bounds__(256) k_geom(const double* __restrict__ verts, 
                                               const double* __restrict__ xi, const double* __restrict__ wq, int NQ,
                                               double amp, double* __restrict__ dxi_dx, double* __restrict__ jac,
                                               double* __restrict__ helm64, float* __restrict__ helm32) {
-  constexpr int NV = SHAPE == kHex ? 8 : (SHAPE == kPrism ? 6 : 4);
+  constexpr int NV = SHAPE == kHex ? 8 : (SHAPE == kPrism ? 6 : (SHAPE == kPyr ? 5 : 4));
   const int64_t total = nelmt * npts;
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
     const int64_t e = t / npts;
@@ -115,9 +134,9 @@ __global__ void __launch_bounds__(256) k_geom(const double* __restrict__ verts, 
       r3 = xi[2 * NQ + n];
       w = wq[n];
     } else {   // affine batch: constant Jacobian, evaluated at the reference centroid
-      r1 = SHAPE == kHex ? 0.0 : (SHAPE == kPrism ? -1.0 / 3.0 : -0.5);
-      r2 = SHAPE == kTet ? -0.5 : 0.0;
-      r3 = r1;
+      r1 = SHAPE == kHex ? 0.0 : (SHAPE == kPrism ? -1.0 / 3.0 : (SHAPE == kPyr ? -0.25 : -0.5));
+      r2 = SHAPE == kTet ? -0.5 : (SHAPE == kPyr ? -0.25 : 0.0);
+      r3 = SHAPE == kPyr ? -0.5 : r1;
       w = 1.0;
     }
     double N[8], dN[8][3];
@@ -175,7 +194,7 @@ template <int SHAPE>
 __global__ void __launch_bounds__(256) k_points(const double* __restrict__ verts, int64_t nelmt,
                                                 const double* __restrict__ xi, int NQ, double amp,
                                                 double* __restrict__ xyz) {
-  constexpr int NV = SHAPE == kHex ? 8 : (SHAPE == kPrism ? 6 : 4);
+  constexpr int NV = SHAPE == kHex ? 8 : (SHAPE == kPrism ? 6 : (SHAPE == kPyr ? 5 : 4));
   const int64_t total = nelmt * NQ;
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
     const int64_t e = t / NQ;
@@ -205,6 +224,8 @@ nir_status launch_points(const nir_basis* b, int64_t nelmt, const double* verts,
     hipLaunchKernelGGL(k_points<kHex>, grid, block, 0, s, verts, nelmt, b->t64.xi, NQ, amp, xyz);
   else if (b->shape == kPrism)
     hipLaunchKernelGGL(k_points<kPrism>, grid, block, 0, s, verts, nelmt, b->t64.xi, NQ, amp, xyz);
+  else if (b->shape == kPyr)
+    hipLaunchKernelGGL(k_points<kPyr>, grid, block, 0, s, verts, nelmt, b->t64.xi, NQ, amp, xyz);
   else
     hipLaunchKernelGGL(k_points<kTet>, grid, block, 0, s, verts, nelmt, b->t64.xi, NQ, amp, xyz);
   return hip_check(hipGetLastError(), "points kernel launch");
@@ -226,6 +247,9 @@ nir_status launch_geom(const nir_basis* b, int deformed, int64_t nelmt, const do
       break;
     case kPrism:
       hipLaunchKernelGGL(k_geom<kPrism>, grid, block, 0, s, verts, nelmt, npts, xi, wq, NQ, amp, dxi_dx, jac, helm64, helm32);
+      break;
+    case kPyr:
+      hipLaunchKernelGGL(k_geom<kPyr>, grid, block, 0, s, verts, nelmt, npts, xi, wq, NQ, amp, dxi_dx, jac, helm64, helm32);
       break;
     default:
       hipLaunchKernelGGL(k_geom<kTet>, grid, block, 0, s, verts, nelmt, npts, xi, wq, NQ, amp, dxi_dx, jac, helm64, helm32);

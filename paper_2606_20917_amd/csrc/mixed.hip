@@ -290,7 +290,8 @@ nir_status nir_mixed_plan_create(int32_t nbatch, const nir_batch* batches, const
   pl->cur_in.assign(nbatch, nullptr);
   pl->cur_out.assign(nbatch, nullptr);
   for (int b = 0; b < nbatch; ++b)
-    if (batches[b].nmodes > kMixedMaxP && batches[b].nelmt > 0) pl->persistent_ok = false;
+    if ((batches[b].nmodes > kMixedMaxP || batches[b].shape == kPyr) && batches[b].nelmt > 0)
+      pl->persistent_ok = false;
   // work list: groups of each batch, decreasing cost (algorithmic bytes of the group)
   struct W {
     int64_t cost;
@@ -443,7 +444,8 @@ nir_status nir_mixed_plan_set_strategy(nir_mixed_plan* pl, int32_t strategy) {
   if (!pl) return fail(NIR_EINVAL, "plan is NULL");
   if (strategy < NIR_MIXED_AUTO || strategy > NIR_MIXED_PER_BATCH) return fail(NIR_EINVAL, "invalid strategy %d", strategy);
   if (strategy == NIR_MIXED_PERSISTENT && !pl->persistent_ok)
-    return fail(NIR_ENOTSUP, "the persistent kernel covers P <= %d; this plan has a batch above", kMixedMaxP);
+    return fail(NIR_ENOTSUP, "the persistent kernel covers hexahedra, prisms and tetrahedra at P <= %d; this plan "
+                             "has another batch", kMixedMaxP);
   pl->strategy_req = strategy;
   if (pl->exec) {   // re-tuned and re-captured at the next apply
     NIR_TRYS(hip_check(hipStreamSynchronize(pl->cap), "sync"));
@@ -602,6 +604,7 @@ nir_status nir_mixed_helmholtz_apply_noalloc(int32_t nbatch, const nir_batch* ba
     if (B.nelmt == 0) continue;
     if (B.nmodes > kMixedMaxP)
       return fail(NIR_ENOTSUP, "batch %d: the persistent kernel covers P <= %d", b, kMixedMaxP);
+    if (B.shape == kPyr) return fail(NIR_ENOTSUP, "batch %d: the persistent kernel has no pyramid groups", b);
     if (!geoms[b].helm) return fail(NIR_EINVAL, "batch %d has no Helmholtz factors", b);
     if (!coef_in[b] || !coef_out[b]) return fail(NIR_EINVAL, "batch %d: NULL coefficient pointer", b);
     if ((reinterpret_cast<uintptr_t>(coef_in[b]) % es) || (reinterpret_cast<uintptr_t>(coef_out[b]) % es) ||

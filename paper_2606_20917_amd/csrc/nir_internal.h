@@ -12,7 +12,7 @@
 
 namespace nir {
 
-constexpr int kHex = 0, kPrism = 1, kTet = 2;
+constexpr int kHex = 0, kPrism = 1, kTet = 2, kPyr = 3;
 constexpr int kMinP = 2, kMaxP = 10;
 
 inline int64_t modes_of(int shape, int P) {
@@ -20,11 +20,12 @@ inline int64_t modes_of(int shape, int P) {
     case kHex: return int64_t(P) * P * P;
     case kPrism: return int64_t(P) * P * (P + 1) / 2;
     case kTet: return int64_t(P) * (P + 1) * (P + 2) / 6;
+    case kPyr: return int64_t(P) * (P + 1) * (2 * P + 1) / 6;
     default: return -1;
   }
 }
 inline int pairs_of(int shape, int P) { return shape == kTet ? P * (P + 1) / 2 : P * P; }
-inline int verts_of(int shape) { return shape == kHex ? 8 : (shape == kPrism ? 6 : 4); }
+inline int verts_of(int shape) { return shape == kHex ? 8 : (shape == kPrism ? 6 : (shape == kPyr ? 5 : 4)); }
 
 // ---------------------------------------------------------------- host tables
 // Built on the host in FP64 for one (shape, P, Q); see tables.cpp.
@@ -78,9 +79,15 @@ struct DevTab {
 
 // Mode numbering of the collapsed shapes (p outer, q, r inner) and pair rows (p, q).
 constexpr int col_pair(int shape, int P, int p, int q) { return shape == kTet ? p * P - p * (p - 1) / 2 + q : p * P + q; }
-// first mode of pair (p,q) in the p-outer, q, r-inner order
+// first mode of pair (p,q) in the p-outer, q, r-inner order (pyramid rows hold P - max(p,q) modes)
 constexpr int col_m0(int shape, int P, int p, int q) {
   int m = 0;
+  if (shape == kPyr) {
+    for (int pp = 0; pp < p; ++pp)
+      for (int qq = 0; qq < P; ++qq) m += P - (pp > qq ? pp : qq);
+    for (int qq = 0; qq < q; ++qq) m += P - (p > qq ? p : qq);
+    return m;
+  }
   for (int pp = 0; pp < p; ++pp) m += shape == kTet ? (P - pp) * (P - pp + 1) / 2 : P * (P - pp);
   return m + (shape == kTet ? q * (P - p) - q * (q - 1) / 2 : q * (P - p));
 }
@@ -152,7 +159,7 @@ nir_status hip_check(hipError_t e, const char* what);
 
 // ---------------------------------------------------------------- launchers
 // Generic (any shape) operator kernels, one entry per operation; implemented in
-// ops_{hex,prism,tet}.hip.  `a` carries every pointer the op needs.
+// ops_{hex,prism,tet,pyr}.hip.  `a` carries every pointer the op needs.
 struct OpArgs {
   const void* in0;      // coef or phys or f0
   const void* in1;      // f1
@@ -176,6 +183,8 @@ nir_status launch_generic_hex(const nir_basis* b, int op, int dtype, int deforme
 nir_status launch_generic_prism(const nir_basis* b, int op, int dtype, int deformed, const OpArgs& a,
                                 hipStream_t s);
 nir_status launch_generic_tet(const nir_basis* b, int op, int dtype, int deformed, const OpArgs& a,
+                              hipStream_t s);
+nir_status launch_generic_pyr(const nir_basis* b, int op, int dtype, int deformed, const OpArgs& a,
                               hipStream_t s);
 
 nir_status launch_geom(const nir_basis* b, int deformed, int64_t nelmt, const double* verts, int map,

@@ -7,16 +7,19 @@
 // direction and in eta_1 / xi_2 of the collapsed shapes; Gauss-Radau-Jacobi
 // rules including x = -1 with weight (1-x)^alpha in the collapsed directions
 // (alpha = 1 for eta_2 of the tet and xi_3 of the prism, alpha = 2 for eta_3 of
-// the tet), their weights scaled by 1/2 and 1/4 so that the tensor rule
-// integrates over the reference shape.  Points by Newton iteration with
+// the tet and of the pyramid), their weights scaled by 1/2 and 1/4 so that the
+// tensor rule integrates over the reference shape.  Points by Newton iteration with
 // deflation on the Jacobi polynomial whose zeros they are; weights in closed
 // form (GLL: 2 / (Q(Q-1) P_{Q-1}(x)^2); Radau: interior Gauss-Jacobi weights of
 // the weight (1+x)(1-x)^alpha divided by (1+x), end weight by completion).
 //
 // Basis (section 2.2, eqs. (16), (17)): psi^a_p, psi^b_pq, psi^c_pqr = psi^b_{p+q,r}
-// of the modified C0 Jacobi family; the collapsed-vertex corrections are
-// applied by the kernels, not folded into the tables.
+// of the modified C0 Jacobi family; the pyramid (no expansion in the paper) takes
+// psi^a_p(eta_1) psi^a_q(eta_2) psi^b_{max(p,q),r}(eta_3), r < P - max(p,q).  The
+// collapsed-vertex corrections are applied by the kernels, not folded into the
+// tables.
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -150,7 +153,7 @@ bool quadrature_1d(int rule, int alpha, int Q, double* z, double* w) {
 }
 
 bool build_tables(int shape, int P, int Q, HostTables& t) {
-  if (shape < kHex || shape > kTet || P < 1 || P > 16 || Q < 2 || Q > 17) return false;
+  if (shape < kHex || shape > kPyr || P < 1 || P > 16 || Q < 2 || Q > 17) return false;
   t.shape = shape;
   t.P = P;
   t.Q = Q;
@@ -159,7 +162,7 @@ bool build_tables(int shape, int P, int Q, HostTables& t) {
   // 1-D rules per direction
   const int rule[3][2] = {{0, 0},
                           {shape == kTet ? 1 : 0, 1},
-                          {shape == kHex ? 0 : 1, shape == kTet ? 2 : 1}};
+                          {shape == kHex ? 0 : 1, shape == kTet || shape == kPyr ? 2 : 1}};
   for (int d = 0; d < 3; ++d) {
     t.z[d].assign(Q, 0.0);
     t.w[d].assign(Q, 0.0);
@@ -171,6 +174,8 @@ bool build_tables(int shape, int P, int Q, HostTables& t) {
     for (auto& v : t.w[1]) v *= 0.5;
     for (auto& v : t.w[2]) v *= 0.25;
   }
+  if (shape == kPyr)   // both collapses in the eta_3 weight: ((1 - eta_3)/2)^2
+    for (auto& v : t.w[2]) v *= 0.25;
   // direction-1 factor
   t.T1.assign(P * Q, 0.0);
   t.dT1.assign(P * Q, 0.0);
@@ -186,7 +191,7 @@ bool build_tables(int shape, int P, int Q, HostTables& t) {
   for (int p = 0; p < P; ++p) {
     const int nq = shape == kTet ? P - p : P;
     for (int q = 0; q < nq; ++q) {
-      const int nr = shape == kHex ? P : (shape == kPrism ? P - p : P - p - q);
+      const int nr = shape == kHex ? P : (shape == kPrism ? P - p : (shape == kPyr ? P - std::max(p, q) : P - p - q));
       t.pair.insert(t.pair.end(), {p, q, m, nr});
       for (int r = 0; r < nr; ++r, ++m) t.mode_pqr.insert(t.mode_pqr.end(), {p, q, r});
     }
@@ -215,6 +220,9 @@ bool build_tables(int shape, int P, int Q, HostTables& t) {
       } else if (shape == kPrism) {
         v = psi_b(p, r, zz);
         dv = dpsi_b(p, r, zz);
+      } else if (shape == kPyr) {
+        v = psi_b(std::max(p, q), r, zz);
+        dv = dpsi_b(std::max(p, q), r, zz);
       } else {
         v = psi_b(p + q, r, zz);
         dv = dpsi_b(p + q, r, zz);
@@ -238,7 +246,8 @@ bool build_tables(int shape, int P, int Q, HostTables& t) {
         t.wq[n] = t.w[0][i] * t.w[1][j] * t.w[2][k];
         const double e1 = t.z[0][i], e2 = t.z[1][j], e3 = t.z[2][k];
         double x1 = e1, x2 = e2, x3 = e3;
-        if (shape == kPrism) x1 = 0.5 * (1.0 + e1) * (1.0 - e3) - 1.0;
+        if (shape == kPrism || shape == kPyr) x1 = 0.5 * (1.0 + e1) * (1.0 - e3) - 1.0;
+        if (shape == kPyr) x2 = 0.5 * (1.0 + e2) * (1.0 - e3) - 1.0;
         if (shape == kTet) {
           x2 = 0.5 * (1.0 + e2) * (1.0 - e3) - 1.0;
           x1 = 0.25 * (1.0 + e1) * (1.0 - e2) * (1.0 - e3) - 1.0;

@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libnir.so")
 
-HEX, PRISM, TET = 0, 1, 2
+HEX, PRISM, TET, PYR = 0, 1, 2, 3
 F64, F32 = 0, 1
 MATH_NATIVE, MATH_F16SPLIT = 0, 1
 MAP_VERTEX, MAP_VERTEX_SIN = 0, 1
@@ -268,7 +268,7 @@ def nir_basis_create(shape, P, Q=None):
     return Basis(shape, P, Q)
 
 
-_NVERT = {HEX: 8, PRISM: 6, TET: 4}
+_NVERT = {HEX: 8, PRISM: 6, TET: 4, PYR: 5}
 
 
 def nir_geom_from_vertices(b, basis, verts, map_, amp, dxi_dx=None, jac=None, helm64=None, helm32=None,

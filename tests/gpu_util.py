@@ -11,6 +11,8 @@ def small_mesh(shape, n, seed, jitter, amp):
         return inputs.hex_mesh(n, rng, jitter)
     if shape == nir.PRISM:
         return inputs.prism_mesh(n, rng, jitter)
+    if shape == nir.PYR:
+        return inputs.pyr_mesh(n, rng, jitter)
     return inputs.tet_mesh(n, rng, jitter)
 
 

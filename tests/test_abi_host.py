@@ -11,7 +11,7 @@ from oracle import basis as ob, operators as op, quadrature as oq
 from paper_2606_20917_amd import nir
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SHAPES = [nir.HEX, nir.PRISM, nir.TET]
+SHAPES = [nir.HEX, nir.PRISM, nir.TET, nir.PYR]
 
 
 def _declared_symbols():
@@ -37,6 +37,7 @@ def test_nmodes():
         assert nir.nir_nmodes(nir.HEX, P) == P ** 3
         assert nir.nir_nmodes(nir.PRISM, P) == P * P * (P + 1) // 2
         assert nir.nir_nmodes(nir.TET, P) == P * (P + 1) * (P + 2) // 6
+        assert nir.nir_nmodes(nir.PYR, P) == len(ob.modes(ob.PYR, P))
     assert nir.nir_nmodes(7, 3) == -1
 
 
@@ -91,6 +92,8 @@ def test_basis_tables_match_oracle(shape, P):
             ref = ob.psi_a(rr, r["z3"])
         elif shape == ob.PRISM:
             ref = ob.psi_b(p, rr, r["z3"])
+        elif shape == ob.PYR:
+            ref = ob.psi_b(max(p, q), rr, r["z3"])
         else:
             ref = ob.psi_b(p + q, rr, r["z3"])
         assert np.abs(T3[m] - ref).max() < 1e-13

@@ -14,7 +14,7 @@ import pytest
 from oracle import operators as op
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-PRISM, TET = 1, 2
+PRISM, TET, PYR = 1, 2, 3
 
 
 def _bench():
@@ -32,7 +32,7 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout == ""
 
 
-@pytest.mark.parametrize("shape", [PRISM, TET])
+@pytest.mark.parametrize("shape", [PRISM, TET, PYR])
 @pytest.mark.parametrize("P", [3, 5, 8])
 @pytest.mark.parametrize("s,deformed", [(8, 1), (8, 0), (4, 1)])
 def test_collapsed_byte_model(shape, P, s, deformed):

@@ -105,6 +105,13 @@ def test_collapsed24_full(shape, P, dtype):
     _check_batch(c, shape, P, dtype)
 
 
+@pytest.mark.parametrize("dtype", [nir.F64, nir.F32])
+@pytest.mark.parametrize("P", [3, 5, 8])
+def test_pyr24_full(P, dtype):
+    """82944 pyramids (6 per cell of the jittered 24^3 cube, apex at the cell centre), per-point factors."""
+    _check_batch(inputs.pyr24(P), nir.PYR, P, dtype)
+
+
 def _mixed_plan(dtype):
     c = inputs.mixed100k()
     groups = {}
