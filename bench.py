@@ -479,7 +479,8 @@ def bench_ops(args):
     # the collapsed shapes (LDS-staged per-element kernels): tet24 with per-element factors,
     # prism24 with per-point factors, P in {3, 5, 8}; npts = geometry points per element
     from paper_2606_20917_amd import inputs
-    for name, gen, shape in (("prism", inputs.prism24, nir.PRISM), ("tet", inputs.tet24, nir.TET)):
+    for name, gen, shape in (("prism", inputs.prism24, nir.PRISM), ("tet", inputs.tet24, nir.TET),
+                             ("pyr", inputs.pyr24, nir.PYR)):
         for P in (3, 5, 8):
             c = gen(P)
             Q, ne, deformed = P + 1, len(c["verts"]), c["deformed"]
@@ -522,7 +523,8 @@ def bench_ops(args):
             out[f"{name}_P{P}"] = res
             del dxi, jac, phys, d, coef, cout
             torch.cuda.empty_cache()
-    out["config"]["collapsed"] = ("tet24 (82944 affine tets, per-element geometry) and prism24 (27648 prisms, "
+    out["config"]["collapsed"] = ("tet24 (82944 affine tets, per-element geometry), pyr24 (82944 pyramids, "
+                                  "per-point geometry) and prism24 (27648 prisms, "
                                   "per-point geometry), P in {3,5,8}")
     out["value"] = out[f"P{ps[-1]}"]["bwd_trans"]["gdofs"]
     print(json.dumps(out), flush=True)

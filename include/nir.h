@@ -381,12 +381,11 @@ nir_status nir_cg_plan_destroy(nir_cg_plan* plan);
  * (shape, P, dtype) is library-global state (one int per combination, set atomically), used by
  * nir_helmholtz_apply and by the CG plans' element apply:
  *   NIR_VARIANT_AUTO       built-in default (a pencil kernel per shape; for hexahedra the
- *                          per-order choice measured fastest on MI355X; the generic kernel for
- *                          pyramids)
+ *                          per-order choice measured fastest on MI355X)
  *   NIR_VARIANT_GENERIC    LDS-staged kernel, threads over points/modes (any shape)
- *   NIR_VARIANT_PENCIL     register-pencil kernel with uniform basis operands (not pyramids; on
- *                          prisms and tetrahedra the contractions whose 1-D factor depends on
- *                          p or p+q run one such index per wavefront)
+ *   NIR_VARIANT_PENCIL     register-pencil kernel with uniform basis operands (any shape; on
+ *                          prisms, tetrahedra and pyramids the contractions whose 1-D factor
+ *                          depends on p, p+q or max(p,q) run one such index per wavefront)
  *   NIR_VARIANT_PENCIL_U2  hex pencil kernel with the streamed point loop unrolled twice
  *   NIR_VARIANT_PENCIL_E1  hex pencil kernel with one element per block (smaller LDS per block)
  *   NIR_VARIANT_PENCIL_PF  hex pencil kernel with each pencil's geometric factors loaded into

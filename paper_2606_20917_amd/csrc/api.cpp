@@ -96,7 +96,6 @@ static std::atomic<int> g_variant[4][kMaxP + 1][2];
 static int resolve_variant(int shape, int P, int dtype) {
   const int v = g_variant[shape][P][dtype].load(std::memory_order_relaxed);
   if (v != NIR_VARIANT_AUTO) return v;
-  if (shape == kPyr) return NIR_VARIANT_GENERIC;
   if (shape != kHex) return NIR_VARIANT_PENCIL;
   // defaults from a sweep of all variants on MI355X (32^3 curved hexes, per-point factors, the
   // fastest of four interleaved rounds per variant): the even-odd folded kernels where the
@@ -115,6 +114,7 @@ nir_status launch_helm_auto(const nir_basis* basis, int dtype, int deformed, con
   const int v = resolve_variant(basis->shape, basis->P, dtype);
   if (basis->shape == kPrism && v == NIR_VARIANT_PENCIL) return launch_helm_col_prism(basis, dtype, deformed, a, s);
   if (basis->shape == kTet && v == NIR_VARIANT_PENCIL) return launch_helm_col_tet(basis, dtype, deformed, a, s);
+  if (basis->shape == kPyr && v == NIR_VARIANT_PENCIL) return launch_helm_col_pyr(basis, dtype, deformed, a, s);
   if (basis->shape != kHex) return launch_generic(basis, kOpHelm, dtype, deformed, a, s);
   if (v == NIR_VARIANT_PENCIL) return launch_helm_hex_pencil(basis, dtype, deformed, a, s, 0);
   if (v == NIR_VARIANT_PENCIL_U2) return launch_helm_hex_pencil(basis, dtype, deformed, a, s, 1);
@@ -277,7 +277,7 @@ nir_status nir_basis_create(int32_t shape, int32_t P, int32_t Q, nir_basis** out
     const int H = (Q + 1) / 2, NE = 1 + (P - 1) / 2, neo = b->shape == kHex && Q == P + 1 ? H * 2 * P : 0;
     // collapsed shapes: the forward sweeps' factors in [slice][point][term] order (col_a_off,
     // col_b_off), values then derivatives
-    const bool col = (b->shape == kPrism || b->shape == kTet) && Q == P + 1;
+    const bool col = b->shape != kHex && Q == P + 1;
     const int na = col ? col_a_off(b->shape, P, P) : 0, nbt = col ? col_b_off(b->shape, P, P) : 0;
     std::vector<double> p64(2 * Q * P + neo + 2 * na + 2 * nbt);
     std::vector<float> p32(p64.size());
@@ -469,7 +469,7 @@ nir_status nir_bwd_trans(const nir_batch* b, const nir_basis* basis, const void*
     return launch_ops_hex_pencil(basis, kOpBwd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
   if (basis->shape == kPrism) return launch_bwd_col_prism(basis, b->dtype, a, static_cast<hipStream_t>(stream));
   if (basis->shape == kTet) return launch_bwd_col_tet(basis, b->dtype, a, static_cast<hipStream_t>(stream));
-  return launch_generic(basis, kOpBwd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+  return launch_bwd_col_pyr(basis, b->dtype, a, static_cast<hipStream_t>(stream));
 }
 
 nir_status nir_iprod_wrt_base(const nir_batch* b, const nir_basis* basis, const nir_geom* g, const void* phys,
@@ -495,7 +495,7 @@ nir_status nir_iprod_wrt_base(const nir_batch* b, const nir_basis* basis, const 
     return launch_iprod_col_prism(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
   if (basis->shape == kTet)
     return launch_iprod_col_tet(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
-  return launch_generic(basis, kOpIProd, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+  return launch_iprod_col_pyr(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
 }
 
 nir_status nir_phys_deriv(const nir_batch* b, const nir_basis* basis, const nir_geom* g, const void* phys,
@@ -531,6 +531,8 @@ nir_status nir_phys_deriv(const nir_batch* b, const nir_basis* basis, const nir_
     return launch_phys_deriv_col_prism(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
   if (basis->shape == kTet)
     return launch_phys_deriv_col_tet(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+  if (basis->shape == kPyr)
+    return launch_phys_deriv_col_pyr(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
   return launch_generic(basis, kOpPhysDeriv, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
 }
 
@@ -566,6 +568,8 @@ nir_status nir_iprod_wrt_deriv_base(const nir_batch* b, const nir_basis* basis, 
     return launch_iprod_deriv_col_prism(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
   if (basis->shape == kTet)
     return launch_iprod_deriv_col_tet(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
+  if (basis->shape == kPyr)
+    return launch_iprod_deriv_col_pyr(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
   return launch_generic(basis, kOpIProdDeriv, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
 }
 
@@ -695,7 +699,7 @@ nir_status nir_autotune_helmholtz(const nir_batch* b, const nir_basis* basis, co
                              NIR_VARIANT_PENCIL_EO_SPLIT};
   const int cands_other[2] = {NIR_VARIANT_GENERIC, NIR_VARIANT_PENCIL};
   const int* cands = b->shape == kHex ? cands_hex : cands_other;
-  const int nc = b->shape == kHex ? 10 : (b->shape == kPyr ? 1 : 2);
+  const int nc = b->shape == kHex ? 10 : 2;
   hipEvent_t e0, e1;
   NIR_TRY(hip_check(hipEventCreate(&e0), "event"));
   NIR_TRY(hip_check(hipEventCreate(&e1), "event"));
@@ -791,9 +795,8 @@ nir_status nir_set_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype, in
   if (variant < NIR_VARIANT_AUTO || variant > NIR_VARIANT_PENCIL_EO_SPLIT)
     return fail(NIR_EINVAL, "invalid variant %d", variant);
   if (variant > NIR_VARIANT_PENCIL && shape != kHex)
-    return fail(NIR_ENOTSUP, "variant %d is a hex kernel (prism and tet have GENERIC and PENCIL)", variant);
-  if (variant == NIR_VARIANT_PENCIL && shape == kPyr)
-    return fail(NIR_ENOTSUP, "pyramids have the GENERIC Helmholtz kernel only");
+    return fail(NIR_ENOTSUP, "variant %d is a hex kernel (prism, tet and pyramid have GENERIC and PENCIL)",
+                variant);
   g_variant[shape][P][dtype].store(variant, std::memory_order_relaxed);
   return NIR_OK;
 }

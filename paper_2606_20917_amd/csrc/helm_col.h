@@ -1,5 +1,5 @@
 // Host launcher of the collapsed-shape register-pencil Helmholtz kernel, instantiated once
-// per shape (helm_col_prism.hip, helm_col_tet.hip).
+// per shape (helm_col_prism.hip, helm_col_tet.hip, helm_col_pyr.hip).
 #pragma once
 
 #include "helm_col_dev.h"
@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(256) k_phys_deriv_col(DevTab<T> tb, const T* _
   __syncthreads();
   if (valid) {
     // chain-rule factors of the (j,k) pencil (eq. (23)); c01 = c02 = c1k (1 + eta_1) for the
-    // tet, c02 = c1k (1 + eta_1) and c01 = 0 for the prism
+    // tet, c02 = c1k (1 + eta_1) and c01 = 0 for the prism and the pyramid
     const T e2v = tb.z[1][hi], e3v = tb.z[2][lo];
     T c00, c1k, c11, c12;
     if (SHAPE == kTet) {
@@ -319,6 +319,12 @@ __global__ void __launch_bounds__(256) k_phys_deriv_col(DevTab<T> tb, const T* _
       const T ra = r3 / (T(1) - e2v);
       c00 = T(4) * ra;
       c1k = T(2) * ra;
+      c11 = T(2) * r3;
+      c12 = (T(1) + e2v) * r3;
+    } else if (SHAPE == kPyr) {
+      const T r3 = T(1) / (T(1) - e3v);
+      c00 = T(2) * r3;
+      c1k = r3;
       c11 = T(2) * r3;
       c12 = (T(1) + e2v) * r3;
     } else {

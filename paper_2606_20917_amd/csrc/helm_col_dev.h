@@ -1,5 +1,5 @@
-// Register-pencil fused Helmholtz apply for the collapsed shapes (prism and tetrahedron),
-// device body of one element group.
+// Register-pencil fused Helmholtz apply for the collapsed shapes (prism, tetrahedron and
+// pyramid), device body of one element group.
 //
 // The operator is the one of the generic kernel (sum factorisation of section 2.2 with the
 // modified C0 basis, eqs. (16)/(17) forward and (20)/(21) transposed), but the derivatives
@@ -28,6 +28,10 @@
 //        all points of psi^c_001 times the mass term plus psi^c_001' times the eta3 flux;
 //  prism modes (0,q,1) add psi^a_1(eta1) psi^a_q(xi2) psi^b_01(xi3): an extra r-term in the
 //        p = 1 rows of A (and of A^T).
+//  pyramid mode (0,0,1) is the apex function (1+eta3)/2 and is handled as the tet's (0,0,1).
+//        Its A factor psi^b_{max(p,q),r} couples through max(p,q): slice sl holds the 2 sl + 1
+//        pairs (sl, 0..sl) and (0..sl-1, sl), each with P - sl terms; B and C are the prism's
+//        (psi^a_q in eta2, psi^a_p in eta1), with both eta1 and eta2 collapsed in the chain rule.
 //
 // LDS per element (values of T): one region of 3 P Q^2 values that holds, in turn, the
 // coefficients, the A rows, the B planes, the C^T planes, the B^T rows and the results;
@@ -77,12 +81,16 @@ __device__ __forceinline__ void row_fence(const T* v) {
 template <int SHAPE, int P, class T, int E_ = 0, int OPM = 0>
 struct ColDims {
   static constexpr int Q = P + 1, Q2 = Q * Q, NQ = Q2 * Q;
-  static constexpr int M = SHAPE == kPrism ? P * P * (P + 1) / 2 : P * (P + 1) * (P + 2) / 6;
+  static constexpr int M = SHAPE == kPrism ? P * P * (P + 1) / 2
+                           : (SHAPE == kPyr ? P * (P + 1) * (2 * P + 1) / 6 : P * (P + 1) * (P + 2) / 6);
   static constexpr int NP = SHAPE == kTet ? P * (P + 1) / 2 : P * P;
   static constexpr int MAIN = (OPM == 0 || OPM == 3 ? 3 : 1) * P * Q2;
-  static constexpr int XTRA = SHAPE == kTet ? Q2 + 3 * Q : 0;   // vertex partials, x0, x1, vertex row
+  // vertex partials, x0, x1 (tet), vertex row (tet and pyramid apex)
+  static constexpr int XTRA = SHAPE == kTet || SHAPE == kPyr ? Q2 + 3 * Q : 0;
   static constexpr int SLAB = OPM == 1 ? P * Q2 : MAIN + XTRA;
-  static constexpr int EW = 64 / Q;                              // elements whose Q lanes fill a wavefront
+  // elements whose lanes fill a slice wavefront: Q lanes each, and for the pyramid up to 2P - 1
+  // pairs of one slice in sweep A
+  static constexpr int EW = SHAPE == kPyr && 64 / (2 * P - 1) < 64 / Q ? 64 / (2 * P - 1) : 64 / Q;
   static constexpr int EL64 = (65536 / int(sizeof(T))) / SLAB;   // elements within 64 KiB of LDS
   static constexpr int LDS_BYTES = SHAPE == kTet ? 160 * 1024 : 80 * 1024;   // standalone group budget
   static constexpr int EL = (LDS_BYTES / int(sizeof(T))) / SLAB;
@@ -131,9 +139,11 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
   constexpr int Q = D::Q, Q2 = D::Q2, NQ = D::NQ, M = D::M, NP = D::NP, E = D::E, SLAB = D::SLAB,
                 MAIN = D::MAIN, BLOCK = D::BLOCK;
   constexpr int PQ2 = P * Q2;
-  constexpr bool TET = SHAPE == kTet;
+  constexpr bool TET = SHAPE == kTet, PYR = SHAPE == kPyr;
+  constexpr bool VTX = TET || PYR;   // a vertex mode (0,0,1) handled point by point
 
   static_assert(E * Q <= 64, "a slice wavefront holds E elements x Q lanes");
+  static_assert(!PYR || E * (2 * P - 1) <= 64, "a pyramid slice wavefront holds E elements x 2 sl + 1 pairs");
   const int wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int sub = wave0 / D::NW;                       // group of this wavefront
   const bool in = sub < NSUB;
@@ -160,9 +170,9 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
   }
   __syncthreads();
 
-  // ---- A: r -> k, one slice (tet: s = p+q, prism: p) per wavefront
+  // ---- A: r -> k, one slice (tet: s = p+q, prism: p, pyramid: max(p,q)) per wavefront
   T c001 = T(0);
-  if (TET && !NOFWD && act) c001 = L[1];
+  if (VTX && !NOFWD && act) c001 = L[1];
   if constexpr (!NOFWD) {
     T a0[Q], a1[Q];
     int dst = -1;   // pair row written by this lane
@@ -180,6 +190,37 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 #pragma unroll
           for (int r = 0; r < nr; ++r) c[r] = (sl == 0 && r == 1) ? T(0) : Ls[m0 + r];   // vertex mode apart
           // one row of nr terms per point k (transposed table): only that row is live in SGPRs
+          constexpr int off = col_a_off(SHAPE, P, sl);
+#pragma unroll
+          for (int k = 0; k < Q; ++k) {
+            const T dep = k > 0 ? a0[k - 1] : c[0];
+            const const_ptr<T> f = fresh_table_after(tb.T3t, dep) + (off + k * nr);
+            const const_ptr<T> df = fresh_table_after(tb.dT3t, dep) + (off + k * nr);
+            T v0 = T(0), v1 = T(0);
+#pragma unroll
+            for (int r = 0; r < nr; ++r) {
+              v0 += f[r] * c[r];
+              v1 += df[r] * c[r];
+            }
+            a0[k] = v0;
+            a1[k] = v1;
+            row_fence<1>(&a0[k]);
+            if constexpr (!BWD) row_fence<1>(&a1[k]);
+          }
+          dst = MO::pair(p, q);
+        }
+      } else if constexpr (PYR) {
+        // lanes (element, pair index t of the slice): t <= sl is (sl, t), t > sl is (t - sl - 1, sl);
+        // factor psi^b_{sl,r}, the apex mode (0,0,1) of slice 0 apart
+        constexpr int np = 2 * sl + 1, nr = P - sl;
+        const int e2 = lane / np, tt = lane - e2 * np;
+        const int p = tt <= sl ? sl : tt - sl - 1, q = tt <= sl ? tt : sl;
+        if (e2 < E) {
+          Ls = lds + e2 * SLAB;
+          const int m0 = MO::m0(p, q);
+          T c[nr];
+#pragma unroll
+          for (int r = 0; r < nr; ++r) c[r] = (sl == 0 && r == 1) ? T(0) : Ls[m0 + r];
           constexpr int off = col_a_off(SHAPE, P, sl);
 #pragma unroll
           for (int k = 0; k < Q; ++k) {
@@ -314,7 +355,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
     T C0[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) C0[p] = act ? L[p * Q2 + s] : T(0);
-    const T uv = TET ? c001 * tb.T3[1 * Q + (act ? kk : 0)] : T(0);   // tet vertex mode
+    const T uv = VTX ? c001 * tb.T3[1 * Q + (act ? kk : 0)] : T(0);   // tet / pyramid vertex mode
     if (valid) {
       T* __restrict__ yo = y + int64_t(base + el) * NQ + s;
 #pragma unroll
@@ -352,7 +393,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
     if (act) {
 #pragma unroll
       for (int p = 0; p < P; ++p) L[p * Q2 + s] = t0[p];
-      if (TET) L[MAIN + s] = tb.T3[1 * Q + kk] * vm;
+      if (VTX) L[MAIN + s] = tb.T3[1 * Q + kk] * vm;
     }
     __syncthreads();
   }
@@ -369,6 +410,12 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
       const T ra = r3 / (T(1) - e2v);
       c00 = T(4) * ra;
       c1k = T(2) * ra;
+      c11 = T(2) * r3;
+      c12 = (T(1) + e2v) * r3;
+    } else if (PYR) {
+      const T r3 = T(1) / (T(1) - e3v);
+      c00 = T(2) * r3;
+      c1k = r3;
       c11 = T(2) * r3;
       c12 = (T(1) + e2v) * r3;
     } else {
@@ -406,6 +453,10 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
           h1 = c00 * y1 + c1 * (y2 + y3);
           h2 = c11 * y2 + c12 * y3;
           v3 += y3;
+        } else if (PYR) {
+          h1 = c00 * y1 + c1 * y3;
+          h2 = c11 * y2 + c12 * y3;
+          v3 += y3;
         } else {
           h1 = c00 * y1 + c1 * y3;
           h2 = y2;
@@ -425,7 +476,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
         L[PQ2 + p * Q2 + s] = t1[p];
         L[2 * PQ2 + p * Q2 + s] = t2[p];
       }
-      if (TET) L[MAIN + s] = tb.dT3[1 * Q + kk] * v3;
+      if (VTX) L[MAIN + s] = tb.dT3[1 * Q + kk] * v3;
     }
     __syncthreads();
   }
@@ -444,12 +495,19 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
     }
     // chain-rule factors of the pencil: d eta / d xi (eq. (23))
     const T e2v = tb.z[1][act ? jj : 0], e3v = tb.z[2][act ? kk : 0];
-    T c00, c1k, c11, c12;   // c01 = c02 = c1k (1 + eta1) for the tet, c02 = c1k (1 + eta1) for the prism
+    // c01 = c02 = c1k (1 + eta1) for the tet, c02 = c1k (1 + eta1) for the prism and the pyramid
+    T c00, c1k, c11, c12;
     if (TET) {
       const T r3 = T(1) / (T(1) - e3v);
       const T ra = r3 / (T(1) - e2v);
       c00 = T(4) * ra;
       c1k = T(2) * ra;
+      c11 = T(2) * r3;
+      c12 = (T(1) + e2v) * r3;
+    } else if (PYR) {
+      const T r3 = T(1) / (T(1) - e3v);
+      c00 = T(2) * r3;
+      c1k = r3;
       c11 = T(2) * r3;
       c12 = (T(1) + e2v) * r3;
     } else {
@@ -459,8 +517,8 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
       c11 = T(1);
       c12 = T(0);
     }
-    T vc = T(0), vd = T(0);   // tet vertex mode: value and eta3-derivative factor at k
-    if (TET) {
+    T vc = T(0), vd = T(0);   // vertex mode (0,0,1): value and eta3-derivative factor at k
+    if (VTX) {
       vc = tb.T3[1 * Q + (act ? kk : 0)];
       vd = tb.dT3[1 * Q + (act ? kk : 0)];
     }
@@ -495,7 +553,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
           d2 += f * C1[p];
           d3 += f * C2[p];
         }
-        if (TET) {
+        if (VTX) {
           u += uv;
           d3 += dv;
         }
@@ -512,6 +570,10 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
         if (TET) {
           x1 = c00 * d1;
           x2 = c1 * d1 + c11 * d2;
+          x3 = c1 * d1 + c12 * d2 + d3;
+        } else if (PYR) {
+          x1 = c00 * d1;
+          x2 = c11 * d2;
           x3 = c1 * d1 + c12 * d2 + d3;
         } else {
           x1 = c00 * d1;
@@ -543,6 +605,11 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
           h2 = c11 * y2 + c12 * y3;
           vm += m;
           v3 += y3;
+        } else if (PYR) {
+          h1 = c00 * y1 + c1 * y3;
+          h2 = c11 * y2 + c12 * y3;
+          vm += m;
+          v3 += y3;
         } else {
           h1 = c00 * y1 + c1 * y3;
           h2 = y2;
@@ -565,7 +632,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
         L[PQ2 + p * Q2 + s] = t1[p];
         L[2 * PQ2 + p * Q2 + s] = t2[p];
       }
-      if (TET) L[MAIN + s] = vc * vm + vd * v3;
+      if (VTX) L[MAIN + s] = vc * vm + vd * v3;
     }
     __syncthreads();
   }
@@ -590,7 +657,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
             tv2[j] = Ls[2 * PQ2 + p * Q2 + j * Q + k];
           }
         }
-        if (TET && p == 0) {
+        if (VTX && p == 0) {
 #pragma unroll
           for (int j = 0; j < Q; ++j) sx += Ls[MAIN + j * Q + k];
         }
@@ -634,7 +701,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
           Ls[MAIN + Q2 + k] = s0[nq];
           if constexpr (!IPR) Ls[MAIN + Q2 + Q + k] = s1[nq];
         }
-        if (TET && p == 0) Ls[MAIN + Q2 + 2 * Q + k] = sx;
+        if (VTX && p == 0) Ls[MAIN + Q2 + 2 * Q + k] = sx;
       };
       col_dispatch<0, P>(pw, writeBT);
     }
@@ -663,6 +730,46 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
           }
           // outer loop over the points k, one row of terms per point (transposed table); the
           // vertex mode (0,0,1) of slice 0 takes the sum of its row instead
+          constexpr int off = col_a_off(SHAPE, P, sl);
+#pragma unroll
+          for (int r = 0; r < nr; ++r) yv[r] = T(0);
+#pragma unroll
+          for (int k = 0; k < Q; ++k) {
+            const T dep = k > 0 ? yv[0] : sv0[0];
+            const const_ptr<T> f = fresh_table_after(tb.T3t, dep) + (off + k * nr);
+            const const_ptr<T> df = fresh_table_after(tb.dT3t, dep) + (off + k * nr);
+#pragma unroll
+            for (int r = 0; r < nr; ++r) {
+              if (sl == 0 && r == 1) continue;
+              yv[r] += f[r] * sv0[k];
+              if constexpr (!IPR) yv[r] += df[r] * sv1[k];
+            }
+            row_fence<nr>(yv);
+          }
+          if constexpr (sl == 0) {
+            T v = T(0);
+#pragma unroll
+            for (int k = 0; k < Q; ++k) v += Ls[MAIN + Q2 + 2 * Q + k];
+            yv[1] = v;
+          }
+          dst = MO::m0(p, q);
+          cnt = nr;
+        }
+      } else if constexpr (PYR) {
+        // lanes (element, pair index t of the slice) as in A; the apex mode (0,0,1) of slice 0
+        // takes the sum of the vertex row
+        constexpr int np = 2 * sl + 1, nr = P - sl;
+        const int e2 = lane / np, tt = lane - e2 * np;
+        const int p = tt <= sl ? sl : tt - sl - 1, q = tt <= sl ? tt : sl;
+        if (e2 < E) {
+          Ls = lds + e2 * SLAB;
+          const int pr = MO::pair(p, q);
+          T sv0[Q], sv1[Q];
+#pragma unroll
+          for (int k = 0; k < Q; ++k) {
+            sv0[k] = Ls[pr * Q + k];
+            if constexpr (!IPR) sv1[k] = Ls[NP * Q + pr * Q + k];
+          }
           constexpr int off = col_a_off(SHAPE, P, sl);
 #pragma unroll
           for (int r = 0; r < nr; ++r) yv[r] = T(0);

@@ -100,11 +100,11 @@ struct ColModes {
 };
 
 // Terms of the forward sweeps of the collapsed shapes per slice: A of slice sl (tet: p+q, prism:
-// p) sums over r (the prism's p = 1 slice also over its (0,q,1) vertex modes), B of p sums over q
-// (the tet's p = 1 plane also over pair (0,1)); the transposed tables hold Q rows of that many
-// terms per slice, slices in order.
+// p, pyramid: max(p,q)) sums over r (the prism's p = 1 slice also over its (0,q,1) vertex modes),
+// B of p sums over q (the tet's p = 1 plane also over pair (0,1)); the transposed tables hold Q
+// rows of that many terms per slice, slices in order.
 constexpr int col_a_terms(int shape, int P, int sl) {
-  return shape == kTet ? P - sl : P - sl + (sl == 1 ? 1 : 0);
+  return shape == kPrism ? P - sl + (sl == 1 ? 1 : 0) : P - sl;
 }
 constexpr int col_b_terms(int shape, int P, int p) { return shape == kTet ? P - p + (p == 1 ? 1 : 0) : P; }
 constexpr int col_a_off(int shape, int P, int sl) {
@@ -196,21 +196,27 @@ nir_status launch_geom_prepare(const nir_basis* b, int deformed, int64_t nelmt, 
 // the four elemental operators on hexahedra with register pencils (ops_hex_pencil.hip)
 nir_status launch_ops_hex_pencil(const nir_basis* b, int op, int dtype, int deformed, const OpArgs& a,
                                  hipStream_t s);
-// register-pencil fused Helmholtz apply of the collapsed shapes (helm_col_{prism,tet}.hip)
+// register-pencil fused Helmholtz apply of the collapsed shapes (helm_col_{prism,tet,pyr}.hip)
 nir_status launch_helm_col_prism(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
 nir_status launch_helm_col_tet(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
-// BwdTrans of prisms / tetrahedra with the register-pencil sweeps of the collapsed Helmholtz kernel
+nir_status launch_helm_col_pyr(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
+// BwdTrans of prisms / tetrahedra / pyramids with the register-pencil sweeps of the collapsed
+// Helmholtz kernel
 nir_status launch_bwd_col_prism(const nir_basis* b, int dtype, const OpArgs& a, hipStream_t s);
 nir_status launch_bwd_col_tet(const nir_basis* b, int dtype, const OpArgs& a, hipStream_t s);
-// IProductWRTBase of prisms / tetrahedra with the transposed register-pencil sweeps
+nir_status launch_bwd_col_pyr(const nir_basis* b, int dtype, const OpArgs& a, hipStream_t s);
+// IProductWRTBase of the collapsed shapes with the transposed register-pencil sweeps
 nir_status launch_iprod_col_prism(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
 nir_status launch_iprod_col_tet(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
-// PhysDeriv of prisms / tetrahedra: collocation pencils with the collapsed chain rule
+nir_status launch_iprod_col_pyr(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
+// PhysDeriv of the collapsed shapes: collocation pencils with the collapsed chain rule
 nir_status launch_phys_deriv_col_prism(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
 nir_status launch_phys_deriv_col_tet(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
-// IProductWRTDerivBase of prisms / tetrahedra with the transposed register-pencil sweeps
+nir_status launch_phys_deriv_col_pyr(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
+// IProductWRTDerivBase of the collapsed shapes with the transposed register-pencil sweeps
 nir_status launch_iprod_deriv_col_prism(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
 nir_status launch_iprod_deriv_col_tet(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
+nir_status launch_iprod_deriv_col_pyr(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
 
 nir_status launch_helm_hex_f16split(const nir_basis* b, int deformed, const OpArgs& a, hipStream_t s);
 // the fused Helmholtz apply with the currently selected kernel variant (native contractions)

@@ -136,7 +136,7 @@ def test_operators_match_oracle(case, P, dtype):
     torch.cuda.synchronize()
     assert elem_relerr(cout.cpu().numpy(), op.iprod_wrt_deriv_base(tab, geo, *f)) <= tolx
 
-    variants = [nir.VARIANT_GENERIC] + ([] if shape == nir.PYR else [nir.VARIANT_PENCIL]) + ([nir.VARIANT_PENCIL_U2, nir.VARIANT_PENCIL_E1,
+    variants = [nir.VARIANT_GENERIC, nir.VARIANT_PENCIL] + ([nir.VARIANT_PENCIL_U2, nir.VARIANT_PENCIL_E1,
                                                              nir.VARIANT_PENCIL_PF, nir.VARIANT_PENCIL_SPLIT,
                                                              nir.VARIANT_PENCIL_GP, nir.VARIANT_PENCIL_SPLIT_GP,
                                                              nir.VARIANT_PENCIL_EO, nir.VARIANT_PENCIL_EO_SPLIT]
