@@ -404,18 +404,25 @@ nir_status nir_cg_plan_destroy(nir_cg_plan* plan);
  *                          and of the modified basis: about half the multiply-adds (results
  *                          differ from the unfolded kernels by rounding only)
  *   NIR_VARIANT_PENCIL_EO_SPLIT  the same on NIR_VARIANT_PENCIL_SPLIT_GP
+ *   NIR_VARIANT_DENSE      prisms, tetrahedra and pyramids with per-element factors (deformed = 0)
+ *                          in FP64: the operator as the seven reference matrices of the shape
+ *                          combined by each element's factors, all elements of a launch stacked
+ *                          into one GEMM on the FP64 matrix cores (the reference matrices are
+ *                          built with the generic kernel at nir_basis_create, for up to 256 modes
+ *                          per element); other batches of these shapes run NIR_VARIANT_PENCIL.
+ *                          The default for tetrahedra up to P = 8.
  * Setting a variant a shape does not support returns NIR_ENOTSUP. */
 typedef enum { NIR_VARIANT_AUTO = 0, NIR_VARIANT_GENERIC = 1, NIR_VARIANT_PENCIL = 2,
                NIR_VARIANT_PENCIL_U2 = 3, NIR_VARIANT_PENCIL_E1 = 4, NIR_VARIANT_PENCIL_PF = 5,
                NIR_VARIANT_PENCIL_SPLIT = 6, NIR_VARIANT_PENCIL_GP = 7, NIR_VARIANT_PENCIL_SPLIT_GP = 8,
-               NIR_VARIANT_PENCIL_EO = 9, NIR_VARIANT_PENCIL_EO_SPLIT = 10 } nir_variant;
+               NIR_VARIANT_PENCIL_EO = 9, NIR_VARIANT_PENCIL_EO_SPLIT = 10, NIR_VARIANT_DENSE = 11 } nir_variant;
 nir_status nir_set_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype, int32_t variant);
 /* The variant a call with these parameters would run now (never NIR_VARIANT_AUTO); -1 if invalid. */
 int32_t nir_get_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype);
 /* Autotuner: times every variant applicable to the batch's shape on the caller's operands
  * (one warm-up and `reps` timed applies each, hipEvents on `stream`; coef_out is overwritten),
  * selects the fastest for (shape, P, dtype) and returns it in *chosen.  ms_per_variant, if not
- * NULL, receives the average time of each variant at index variant-1 (10 doubles; untried
+ * NULL, receives the average time of each variant at index variant-1 (11 doubles; untried
  * entries untouched).  Synchronises the stream. */
 nir_status nir_autotune_helmholtz(const nir_batch* batch, const nir_basis* basis, const nir_geom* geom,
                                   double lambda, const void* coef_in, void* coef_out, int32_t reps,

@@ -96,6 +96,9 @@ static std::atomic<int> g_variant[4][kMaxP + 1][2];
 static int resolve_variant(int shape, int P, int dtype) {
   const int v = g_variant[shape][P][dtype].load(std::memory_order_relaxed);
   if (v != NIR_VARIANT_AUTO) return v;
+  // tetrahedra to P = 8: the reference-matrix GEMM on the matrix cores (affine FP64 batches; the
+  // pencil kernel otherwise)
+  if (shape == kTet && P <= 8) return NIR_VARIANT_DENSE;
   if (shape != kHex) return NIR_VARIANT_PENCIL;
   // defaults from a sweep of all variants on MI355X (32^3 curved hexes, per-point factors, the
   // fastest of four interleaved rounds per variant): the even-odd folded kernels where the
@@ -111,7 +114,11 @@ static int resolve_variant(int shape, int P, int dtype) {
 
 // the fused Helmholtz apply with the selected kernel variant (native contractions)
 nir_status launch_helm_auto(const nir_basis* basis, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
-  const int v = resolve_variant(basis->shape, basis->P, dtype);
+  int v = resolve_variant(basis->shape, basis->P, dtype);
+  if (v == NIR_VARIANT_DENSE) {
+    if (basis->shape != kHex && !deformed && dtype == NIR_F64 && basis->dense64) return launch_helm_dense(basis, a, s);
+    v = NIR_VARIANT_PENCIL;   // per-point factors, FP32 or M > kDenseMaxM: the register-pencil kernel
+  }
   if (basis->shape == kPrism && v == NIR_VARIANT_PENCIL) return launch_helm_col_prism(basis, dtype, deformed, a, s);
   if (basis->shape == kTet && v == NIR_VARIANT_PENCIL) return launch_helm_col_tet(basis, dtype, deformed, a, s);
   if (basis->shape == kPyr && v == NIR_VARIANT_PENCIL) return launch_helm_col_pyr(basis, dtype, deformed, a, s);
@@ -385,6 +392,10 @@ nir_status nir_basis_create(int32_t shape, int32_t P, int32_t Q, nir_basis** out
       return st;
     }
   }
+  if (b->shape != kHex && (st = build_dense_refs(b)) != NIR_OK) {
+    nir_basis_destroy(b);
+    return st;
+  }
   *out = b;
   return NIR_OK;
 }
@@ -397,6 +408,8 @@ nir_status nir_basis_destroy(nir_basis* b) {
   if (b->devpencil) (void)hipFree(b->devpencil);
   if (b->mfma_tabs) (void)hipFree(b->mfma_tabs);
   if (b->mfma_scale) (void)hipFree(b->mfma_scale);
+  if (b->dense64) (void)hipFree(b->dense64);
+  if (b->dense32) (void)hipFree(b->dense32);
   delete b;
   return NIR_OK;
 }
@@ -697,9 +710,9 @@ nir_status nir_autotune_helmholtz(const nir_batch* b, const nir_basis* basis, co
                              NIR_VARIANT_PENCIL_E1, NIR_VARIANT_PENCIL_PF, NIR_VARIANT_PENCIL_SPLIT,
                              NIR_VARIANT_PENCIL_GP, NIR_VARIANT_PENCIL_SPLIT_GP, NIR_VARIANT_PENCIL_EO,
                              NIR_VARIANT_PENCIL_EO_SPLIT};
-  const int cands_other[2] = {NIR_VARIANT_GENERIC, NIR_VARIANT_PENCIL};
+  const int cands_other[3] = {NIR_VARIANT_GENERIC, NIR_VARIANT_PENCIL, NIR_VARIANT_DENSE};
   const int* cands = b->shape == kHex ? cands_hex : cands_other;
-  const int nc = b->shape == kHex ? 10 : 2;
+  const int nc = b->shape == kHex ? 10 : 3;
   hipEvent_t e0, e1;
   NIR_TRY(hip_check(hipEventCreate(&e0), "event"));
   NIR_TRY(hip_check(hipEventCreate(&e1), "event"));
@@ -739,7 +752,7 @@ nir_status nir_autotune_save(const char* path) {
   if (!f) return fail(NIR_EINVAL, "cannot open %s for writing", path);
   std::fprintf(f, "{\"format\": \"libnir-autotune-1\", \"entries\": [\n");
   bool first = true;
-  for (int sh = 0; sh < 3; ++sh)
+  for (int sh = 0; sh <= kPyr; ++sh)
     for (int P = kMinP; P <= kMaxP; ++P)
       for (int dt = 0; dt < 2; ++dt) {
         const int v = g_variant[sh][P][dt].load();
@@ -779,8 +792,9 @@ nir_status nir_autotune_load(const char* path) {
     if (std::sscanf(txt.c_str() + ob, "{\"shape\": %d, \"P\": %d, \"dtype\": %d, \"variant\": %d}", &e.s, &e.P,
                     &e.d, &e.v) != 4)
       return fail(NIR_EINVAL, "%s: malformed entry at offset %zu", path, ob);
-    if (e.s < 0 || e.s > 2 || e.P < kMinP || e.P > kMaxP || e.d < 0 || e.d > 1 || e.v < NIR_VARIANT_AUTO ||
-        e.v > NIR_VARIANT_PENCIL_EO_SPLIT || (e.s != kHex && e.v > NIR_VARIANT_PENCIL))
+    if (e.s < 0 || e.s > kPyr || e.P < kMinP || e.P > kMaxP || e.d < 0 || e.d > 1 || e.v < NIR_VARIANT_AUTO ||
+        e.v > NIR_VARIANT_DENSE || (e.s != kHex && e.v > NIR_VARIANT_PENCIL && e.v != NIR_VARIANT_DENSE) ||
+        (e.s == kHex && e.v == NIR_VARIANT_DENSE))
       return fail(NIR_EINVAL, "%s: invalid entry at offset %zu", path, ob);
     ents.push_back(e);
     pos = cb + 1;
@@ -792,11 +806,13 @@ nir_status nir_autotune_load(const char* path) {
 nir_status nir_set_helmholtz_variant(int32_t shape, int32_t P, int32_t dtype, int32_t variant) {
   if (shape < kHex || shape > kPyr || P < kMinP || P > kMaxP || (dtype != NIR_F64 && dtype != NIR_F32))
     return fail(NIR_EINVAL, "invalid (shape %d, P %d, dtype %d)", shape, P, dtype);
-  if (variant < NIR_VARIANT_AUTO || variant > NIR_VARIANT_PENCIL_EO_SPLIT)
+  if (variant < NIR_VARIANT_AUTO || variant > NIR_VARIANT_DENSE)
     return fail(NIR_EINVAL, "invalid variant %d", variant);
-  if (variant > NIR_VARIANT_PENCIL && shape != kHex)
-    return fail(NIR_ENOTSUP, "variant %d is a hex kernel (prism, tet and pyramid have GENERIC and PENCIL)",
+  if (variant > NIR_VARIANT_PENCIL && variant != NIR_VARIANT_DENSE && shape != kHex)
+    return fail(NIR_ENOTSUP, "variant %d is a hex kernel (prism, tet and pyramid have GENERIC, PENCIL and DENSE)",
                 variant);
+  if (variant == NIR_VARIANT_DENSE && shape == kHex)
+    return fail(NIR_ENOTSUP, "the dense reference-matrix apply covers prisms, tetrahedra and pyramids");
   g_variant[shape][P][dtype].store(variant, std::memory_order_relaxed);
   return NIR_OK;
 }

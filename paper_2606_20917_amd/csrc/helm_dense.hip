@@ -1,0 +1,245 @@
+// Fused Helmholtz apply of affine collapsed-shape elements as one stacked GEMM on the matrix cores.
+//
+// With per-element factors (an affine map: section 2.1, the Jacobian is constant) the elemental
+// operator of eqs. (6), (7) is a combination of seven reference matrices with the element's seven
+// factors g_c:
+//   y_e = sum_{c<6} g_ec S_c x_e + lambda g_e6 M x_e,
+//   S_aa = B_a^T W B_a,  S_ab = B_a^T W B_b + B_b^T W B_a (a < b),  M = B^T W B,
+// with B_a the reference derivative d phi / d xi_a at the quadrature points and W the point
+// weights, c running over (00, 01, 02, 11, 12, 22).  Stacking the elements as rows gives
+//   Y = [g_0 . X, ..., g_6 . X] [S_0; ...; S_6]      (g_c . X: row e of X scaled by g_ec),
+// a dense GEMM with K = 7 M that the FP64 matrix instructions run directly; the scaled A operand
+// is formed in registers from X staged in LDS.  The reference matrices come from the validated
+// sum-factorised generic kernel applied to unit vectors at basis creation (build_dense_refs).
+//
+// v_mfma_f64_16x16x4f64 operand layout (checked on the device): lane l holds A[l%16][l/16] and
+// B[l/16][l%16]; its four results are D[4v + l/16][l%16], v = 0..3.
+#include <cstring>
+#include <vector>
+
+#include "generic_ops.h"
+#include "nir_internal.h"
+
+namespace nir {
+
+typedef double dense_d4 __attribute__((ext_vector_type(4)));
+
+constexpr int dense_ceil(int a, int b) { return (a + b - 1) / b; }
+
+// The 4 wavefronts of a block form a WR x WC grid over the block's RT row tiles and NCT column
+// tiles; WC is the largest of 4, 2, 1 that splits the column tiles most evenly (each wave then
+// reuses every B fragment for its RT / WR row tiles).
+template <int NCT, int RT>
+constexpr int dense_wc() {
+  int best = 1;
+  double be = -1.0;
+  for (int wc = 4; wc >= 1; wc /= 2) {
+    if (RT % (4 / wc)) continue;
+    const double eff = double(NCT) / (wc * dense_ceil(NCT, wc));
+    if (eff > be + 1e-9) {
+      be = eff;
+      best = wc;
+    }
+  }
+  return best;
+}
+
+template <int SHAPE, int P>
+struct DenseDims {
+  static constexpr int M = Dims<SHAPE, P>::M;
+  static constexpr int MP = (M + 15) / 16 * 16;   // padded to whole 16-wide tiles
+  static constexpr int NCT = MP / 16;              // column tiles
+  static constexpr int RT = 4;                     // row tiles per block: 64 elements
+  static constexpr int ROWS = 16 * RT;
+  static constexpr int XSTR = MP + 1;              // LDS row stride (odd: no bank conflicts across rows)
+  static constexpr int WC = dense_wc<NCT, RT>(), WR = 4 / WC;
+  static constexpr int RTW = RT / WR, CTW = dense_ceil(NCT, WC);
+  // from 8 column tiles on, the next K step's B fragments are requested one step ahead
+  static constexpr bool PF = NCT >= 8;
+};
+
+template <int SHAPE, int P>
+__global__ void __launch_bounds__(256) k_helm_dense(const double* __restrict__ S, const double* __restrict__ x,
+                                                    double* __restrict__ y, const double* __restrict__ helm,
+                                                    double lambda, int64_t nelmt) {
+  using D = DenseDims<SHAPE, P>;
+  constexpr int M = D::M, MP = D::MP, NCT = D::NCT, XSTR = D::XSTR, RTW = D::RTW, CTW = D::CTW, WC = D::WC;
+  __shared__ double Xs[D::ROWS * XSTR];
+  const int64_t e0 = int64_t(blockIdx.x) * D::ROWS;
+  const int ne = int(min(int64_t(D::ROWS), nelmt - e0));
+  // stage the block's coefficients, zero-padded to MP columns and ROWS rows
+  for (int f = threadIdx.x; f < D::ROWS * MP; f += 256) {
+    const int r = f / MP, m = f - r * MP;
+    Xs[r * XSTR + m] = (r < ne && m < M) ? x[(e0 + r) * M + m] : 0.0;
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int li = l & 15, lk = l >> 4;
+  const int wr = w / WC, wc = w - wr * WC;   // row tiles wr RTW .. (wr+1) RTW - 1; column tiles wc + WC u
+  // factors of this lane's rows (lambda folded into the mass factor)
+  double g[RTW][7];
+#pragma unroll
+  for (int t = 0; t < RTW; ++t) {
+    const int r = (wr * RTW + t) * 16 + li;
+    const int64_t e = e0 + (r < ne ? r : 0);   // rows past the batch end read element e0 (never stored)
+#pragma unroll
+    for (int c = 0; c < 7; ++c) g[t][c] = helm[e * 7 + c];
+    g[t][6] *= lambda;
+  }
+  dense_d4 acc[RTW][CTW];
+#pragma unroll
+  for (int t = 0; t < RTW; ++t)
+#pragma unroll
+    for (int u = 0; u < CTW; ++u) acc[t][u] = dense_d4{0.0, 0.0, 0.0, 0.0};
+  // B fragments of K step m0: rows m0 + lk of the seven stacked matrices, this wave's column tiles
+  auto load_b = [&](int m0, double (&b)[7][CTW]) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      const double* __restrict__ Sr = S + int64_t(c * MP + m0 + lk) * MP + li;
+#pragma unroll
+      for (int u = 0; u < CTW; ++u) {
+        const int ct = wc + WC * u;
+        b[c][u] = ct < NCT ? Sr[ct * 16] : 0.0;
+      }
+    }
+  };
+  double bn[7][CTW];
+  if constexpr (D::PF) load_b(0, bn);
+  __syncthreads();
+#pragma unroll 1
+  for (int m0 = 0; m0 < MP; m0 += 4) {
+    double xa[RTW];
+#pragma unroll
+    for (int t = 0; t < RTW; ++t) xa[t] = Xs[((wr * RTW + t) * 16 + li) * XSTR + m0 + lk];
+    double b[7][CTW];
+    if constexpr (D::PF) {
+#pragma unroll
+      for (int c = 0; c < 7; ++c)
+#pragma unroll
+        for (int u = 0; u < CTW; ++u) b[c][u] = bn[c][u];
+      if (m0 + 4 < MP) load_b(m0 + 4, bn);
+    } else {
+      load_b(m0, b);
+    }
+#pragma unroll
+    for (int c = 0; c < 7; ++c)
+#pragma unroll
+      for (int t = 0; t < RTW; ++t) {
+        const double a = xa[t] * g[t][c];
+#pragma unroll
+        for (int u = 0; u < CTW; ++u) acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[c][u], acc[t][u], 0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int t = 0; t < RTW; ++t)
+#pragma unroll
+    for (int u = 0; u < CTW; ++u) {
+      const int ct = wc + WC * u, col = ct * 16 + li;
+      if (ct >= NCT || col >= M) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = (wr * RTW + t) * 16 + 4 * v + lk;
+        if (r < ne) y[(e0 + r) * M + col] = acc[t][u][v];
+      }
+    }
+}
+
+template <int SHAPE, int P>
+static nir_status launch_dense_P(const nir_basis* b, const OpArgs& a, hipStream_t s) {
+  using D = DenseDims<SHAPE, P>;
+  if constexpr (D::M > kDenseMaxM) {
+    return fail(NIR_ENOTSUP, "the dense apply covers M <= %d modes", kDenseMaxM);
+  } else {
+    const int64_t nb = (a.nelmt + D::ROWS - 1) / D::ROWS;
+    if (nb > 0x7fffffff) return fail(NIR_EINVAL, "too many elements for one launch");
+    if (nb == 0) return ok();
+    hipLaunchKernelGGL((k_helm_dense<SHAPE, P>), dim3(unsigned(nb)), dim3(256), 0, s, b->dense64,
+                       static_cast<const double*>(a.in0), static_cast<double*>(a.out0),
+                       static_cast<const double*>(a.helm), a.lambda, a.nelmt);
+    return hip_check(hipGetLastError(), "dense Helmholtz launch");
+  }
+}
+
+template <int SHAPE>
+static nir_status launch_dense_shape(const nir_basis* b, const OpArgs& a, hipStream_t s) {
+#define NIR_CASE(PP) \
+  case PP: return launch_dense_P<SHAPE, PP>(b, a, s);
+  switch (b->P) {
+    NIR_CASE(2) NIR_CASE(3) NIR_CASE(4) NIR_CASE(5) NIR_CASE(6)
+    NIR_CASE(7) NIR_CASE(8) NIR_CASE(9) NIR_CASE(10)
+    default: return fail(NIR_ENOTSUP, "P=%d not compiled", b->P);
+  }
+#undef NIR_CASE
+}
+
+// FP64 dense apply of an affine batch (per-element factors helm[nelmt][7])
+nir_status launch_helm_dense(const nir_basis* b, const OpArgs& a, hipStream_t s) {
+  if (!b->dense64) return fail(NIR_ENOTSUP, "no reference matrices for this basis");
+  switch (b->shape) {
+    case kPrism: return launch_dense_shape<kPrism>(b, a, s);
+    case kTet: return launch_dense_shape<kTet>(b, a, s);
+    case kPyr: return launch_dense_shape<kPyr>(b, a, s);
+    default: return fail(NIR_ENOTSUP, "the dense apply covers the collapsed shapes");
+  }
+}
+
+// The seven reference matrices of (shape, P), stacked [7 MP][MP] and zero-padded, in FP64 and an
+// FP32 copy: the generic Helmholtz kernel applied (lambda = 1, per-element factors) to 7 M unit
+// "elements", element (c, m) holding x = e_m and the factors g = e_c, gives row m of matrix c
+// (the matrices are symmetric).  Synchronous; the caller owns b->dense64 / b->dense32 afterwards.
+nir_status build_dense_refs(nir_basis* b) {
+  const int M = b->M, MP = (M + 15) / 16 * 16;
+  if (M > kDenseMaxM) return NIR_OK;   // the sum-factorised kernels only
+  const int64_t ne = int64_t(7) * M;
+  std::vector<double> hx(size_t(ne) * M, 0.0), hg(size_t(ne) * 7, 0.0), hy(size_t(ne) * M, 0.0);
+  for (int c = 0; c < 7; ++c)
+    for (int m = 0; m < M; ++m) {
+      const int64_t e = int64_t(c) * M + m;
+      hx[size_t(e) * M + m] = 1.0;
+      hg[size_t(e) * 7 + c] = 1.0;
+    }
+  double *dx = nullptr, *dg = nullptr, *dy = nullptr;
+  nir_status st = NIR_OK;
+  auto cleanup = [&]() {
+    if (dx) (void)hipFree(dx);
+    if (dg) (void)hipFree(dg);
+    if (dy) (void)hipFree(dy);
+  };
+  if ((st = hip_check(hipMalloc(&dx, hx.size() * 8), "hipMalloc")) != NIR_OK ||
+      (st = hip_check(hipMalloc(&dg, hg.size() * 8), "hipMalloc")) != NIR_OK ||
+      (st = hip_check(hipMalloc(&dy, hy.size() * 8), "hipMalloc")) != NIR_OK ||
+      (st = hip_check(hipMemcpy(dx, hx.data(), hx.size() * 8, hipMemcpyHostToDevice), "copy")) != NIR_OK ||
+      (st = hip_check(hipMemcpy(dg, hg.data(), hg.size() * 8, hipMemcpyHostToDevice), "copy")) != NIR_OK) {
+    cleanup();
+    return st;
+  }
+  OpArgs a{};
+  a.in0 = dx;
+  a.out0 = dy;
+  a.helm = dg;
+  a.lambda = 1.0;
+  a.nelmt = ne;
+  if ((st = launch_generic(b, kOpHelm, NIR_F64, 0, a, nullptr)) != NIR_OK ||
+      (st = hip_check(hipDeviceSynchronize(), "reference matrices")) != NIR_OK ||
+      (st = hip_check(hipMemcpy(hy.data(), dy, hy.size() * 8, hipMemcpyDeviceToHost), "copy")) != NIR_OK) {
+    cleanup();
+    return st;
+  }
+  cleanup();
+  std::vector<double> s64(size_t(7) * MP * MP, 0.0);
+  std::vector<float> s32(s64.size(), 0.0f);
+  for (int c = 0; c < 7; ++c)
+    for (int m = 0; m < M; ++m)
+      for (int n = 0; n < M; ++n) {
+        const size_t o = (size_t(c) * MP + m) * MP + n;
+        s64[o] = hy[(size_t(c) * M + m) * M + n];
+        s32[o] = float(s64[o]);
+      }
+  if ((st = hip_check(hipMalloc(&b->dense64, s64.size() * 8), "hipMalloc")) != NIR_OK ||
+      (st = hip_check(hipMalloc(&b->dense32, s32.size() * 4), "hipMalloc")) != NIR_OK ||
+      (st = hip_check(hipMemcpy(b->dense64, s64.data(), s64.size() * 8, hipMemcpyHostToDevice), "copy")) != NIR_OK ||
+      (st = hip_check(hipMemcpy(b->dense32, s32.data(), s32.size() * 4, hipMemcpyHostToDevice), "copy")) != NIR_OK)
+    return st;
+  return NIR_OK;
+}
+
+}  // namespace nir

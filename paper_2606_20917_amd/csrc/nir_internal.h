@@ -140,6 +140,10 @@ struct nir_basis {
   // power-of-two split scales
   float* mfma_tabs = nullptr;
   float* mfma_scale = nullptr;
+  // collapsed shapes: the seven reference matrices of the affine Helmholtz operator, stacked
+  // [7 MP][MP] (MP = M rounded up to 16), FP64 and an FP32 copy (helm_dense.hip)
+  double* dense64 = nullptr;
+  float* dense32 = nullptr;
   const void* table_dev[NIR_TAB_COUNT];
 };
 
@@ -219,6 +223,13 @@ nir_status launch_iprod_deriv_col_tet(const nir_basis* b, int dtype, int deforme
 nir_status launch_iprod_deriv_col_pyr(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
 
 nir_status launch_helm_hex_f16split(const nir_basis* b, int deformed, const OpArgs& a, hipStream_t s);
+// FP64 fused Helmholtz apply of an affine collapsed-shape batch as one stacked GEMM on the matrix
+// cores, from the reference matrices that build_dense_refs places in the basis (helm_dense.hip)
+// (M <= kDenseMaxM: beyond it the 14 M^2 FLOPs per element outgrow the sum-factorised count and
+// the staged rows outgrow the LDS)
+constexpr int kDenseMaxM = 256;
+nir_status launch_helm_dense(const nir_basis* b, const OpArgs& a, hipStream_t s);
+nir_status build_dense_refs(nir_basis* b);
 // the fused Helmholtz apply with the currently selected kernel variant (native contractions)
 nir_status launch_helm_auto(const nir_basis* basis, int dtype, int deformed, const OpArgs& a, hipStream_t s);
 nir_status launch_points(const nir_basis* b, int64_t nelmt, const double* verts, double amp, double* xyz,

@@ -19,7 +19,7 @@ MAP_VERTEX, MAP_VERTEX_SIN = 0, 1
 MIXED_AUTO, MIXED_PERSISTENT, MIXED_PER_BATCH = range(3)
 (VARIANT_AUTO, VARIANT_GENERIC, VARIANT_PENCIL, VARIANT_PENCIL_U2, VARIANT_PENCIL_E1, VARIANT_PENCIL_PF,
  VARIANT_PENCIL_SPLIT, VARIANT_PENCIL_GP, VARIANT_PENCIL_SPLIT_GP, VARIANT_PENCIL_EO,
- VARIANT_PENCIL_EO_SPLIT) = range(11)
+ VARIANT_PENCIL_EO_SPLIT, VARIANT_DENSE) = range(12)
 CG_FP64, CG_MIXED_F32, CG_MIXED_F16SPLIT = 0, 1, 2
 
 (TAB_Z1, TAB_Z2, TAB_Z3, TAB_W1, TAB_W2, TAB_W3, TAB_T1, TAB_DT1, TAB_T2, TAB_DT2, TAB_T3, TAB_DT3,
@@ -552,10 +552,10 @@ def nir_autotune_helmholtz(b, basis, g, lam, coef_in, coef_out, reps=10, stream=
     _need(coef_out, "coef_out", ne * M, b.dtype)
     _need_geom(b, g, helm=True)
     ch = ctypes.c_int32()
-    ms = (ctypes.c_double * 10)(*([-1.0] * 10))
+    ms = (ctypes.c_double * 11)(*([-1.0] * 11))
     _check(lib().nir_autotune_helmholtz(ctypes.byref(b), _basis(basis), ctypes.byref(g), lam, _ptr(coef_in),
                                         _ptr(coef_out), reps, ctypes.byref(ch), ctypes.cast(ms, _vp), _stream(stream)))
-    return ch.value, {v + 1: ms[v] for v in range(10) if ms[v] >= 0}
+    return ch.value, {v + 1: ms[v] for v in range(11) if ms[v] >= 0}
 
 
 def nir_autotune_save(path):

@@ -161,11 +161,15 @@ def test_autotune_cache_roundtrip(tmp_path):
     try:
         nir.nir_set_helmholtz_variant(nir.HEX, 6, nir.F64, nir.VARIANT_PENCIL_U2)
         nir.nir_set_helmholtz_variant(nir.TET, 3, nir.F32, nir.VARIANT_GENERIC)
+        nir.nir_set_helmholtz_variant(nir.PYR, 5, nir.F64, nir.VARIANT_DENSE)
         path = str(tmp_path / "tune.json")
         nir.nir_autotune_save(path)
         nir.nir_set_helmholtz_variant(nir.HEX, 6, nir.F64, nir.VARIANT_AUTO)
         nir.nir_set_helmholtz_variant(nir.TET, 3, nir.F32, nir.VARIANT_AUTO)
+        nir.nir_set_helmholtz_variant(nir.PYR, 5, nir.F64, nir.VARIANT_AUTO)
         assert nir.nir_get_helmholtz_variant(nir.HEX, 6, nir.F64) == nir.VARIANT_PENCIL_GP
+        assert nir.nir_get_helmholtz_variant(nir.TET, 5, nir.F64) == nir.VARIANT_DENSE
+        assert nir.nir_get_helmholtz_variant(nir.PYR, 5, nir.F64) == nir.VARIANT_PENCIL
         # built-in per-order defaults of the hex kernel family
         H, F64, F32 = nir.HEX, nir.F64, nir.F32
         PF, GP, SGP = nir.VARIANT_PENCIL_PF, nir.VARIANT_PENCIL_GP, nir.VARIANT_PENCIL_SPLIT_GP
@@ -178,6 +182,7 @@ def test_autotune_cache_roundtrip(tmp_path):
         nir.nir_autotune_load(path)
         assert nir.nir_get_helmholtz_variant(nir.HEX, 6, nir.F64) == nir.VARIANT_PENCIL_U2
         assert nir.nir_get_helmholtz_variant(nir.TET, 3, nir.F32) == nir.VARIANT_GENERIC
+        assert nir.nir_get_helmholtz_variant(nir.PYR, 5, nir.F64) == nir.VARIANT_DENSE
         # corrupt or invalid caches are rejected and leave the table unchanged
         bad = tmp_path / "bad.json"
         for txt in ("not json", '{"format": "libnir-autotune-1", "entries": [{"shape": 0, "P": 6}]}',
@@ -194,11 +199,13 @@ def test_autotune_cache_roundtrip(tmp_path):
             nir.nir_set_helmholtz_variant(nir.PRISM, 4, nir.F64, nir.VARIANT_PENCIL_U2)
         with pytest.raises(nir.NirError):
             nir.nir_set_helmholtz_variant(nir.TET, 4, nir.F64, nir.VARIANT_PENCIL_EO)
+        with pytest.raises(nir.NirError):   # the reference-matrix apply is for the collapsed shapes
+            nir.nir_set_helmholtz_variant(nir.HEX, 4, nir.F64, nir.VARIANT_DENSE)
         with pytest.raises(nir.NirError):
-            nir.nir_set_helmholtz_variant(nir.HEX, 4, nir.F64, nir.VARIANT_PENCIL_EO_SPLIT + 1)
+            nir.nir_set_helmholtz_variant(nir.HEX, 4, nir.F64, nir.VARIANT_DENSE + 1)
         nir.nir_set_helmholtz_variant(nir.PRISM, 4, nir.F64, nir.VARIANT_PENCIL)
     finally:
-        for s, P, d in ((nir.HEX, 6, nir.F64), (nir.TET, 3, nir.F32), (nir.PRISM, 4, nir.F64)):
+        for s, P, d in ((nir.HEX, 6, nir.F64), (nir.TET, 3, nir.F32), (nir.PRISM, 4, nir.F64), (nir.PYR, 5, nir.F64)):
             nir.nir_set_helmholtz_variant(s, P, d, nir.VARIANT_AUTO)
 
 
