@@ -404,10 +404,10 @@ nir_status nir_cg_plan_destroy(nir_cg_plan* plan);
  *                          and of the modified basis: about half the multiply-adds (results
  *                          differ from the unfolded kernels by rounding only)
  *   NIR_VARIANT_PENCIL_EO_SPLIT  the same on NIR_VARIANT_PENCIL_SPLIT_GP
- *   NIR_VARIANT_DENSE      prisms, tetrahedra and pyramids with per-element factors (deformed = 0)
- *                          in FP64: the operator as the seven reference matrices of the shape
- *                          combined by each element's factors, all elements of a launch stacked
- *                          into one GEMM on the FP64 matrix cores (the reference matrices are
+ *   NIR_VARIANT_DENSE      prisms, tetrahedra and pyramids with per-element factors (deformed = 0):
+ *                          the operator as the seven reference matrices of the shape combined by
+ *                          each element's factors, all elements of a launch stacked into one GEMM
+ *                          on the FP64 or FP32 matrix cores (the reference matrices are
  *                          built with the generic kernel at nir_basis_create, for up to 256 modes
  *                          per element); other batches of these shapes run NIR_VARIANT_PENCIL.
  *                          The default for tetrahedra up to P = 8.

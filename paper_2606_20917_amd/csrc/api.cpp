@@ -116,8 +116,8 @@ static int resolve_variant(int shape, int P, int dtype) {
 nir_status launch_helm_auto(const nir_basis* basis, int dtype, int deformed, const OpArgs& a, hipStream_t s) {
   int v = resolve_variant(basis->shape, basis->P, dtype);
   if (v == NIR_VARIANT_DENSE) {
-    if (basis->shape != kHex && !deformed && dtype == NIR_F64 && basis->dense64) return launch_helm_dense(basis, a, s);
-    v = NIR_VARIANT_PENCIL;   // per-point factors, FP32 or M > kDenseMaxM: the register-pencil kernel
+    if (basis->shape != kHex && !deformed && basis->dense64) return launch_helm_dense(basis, dtype, a, s);
+    v = NIR_VARIANT_PENCIL;   // per-point factors or M > kDenseMaxM: the register-pencil kernel
   }
   if (basis->shape == kPrism && v == NIR_VARIANT_PENCIL) return launch_helm_col_prism(basis, dtype, deformed, a, s);
   if (basis->shape == kTet && v == NIR_VARIANT_PENCIL) return launch_helm_col_tet(basis, dtype, deformed, a, s);

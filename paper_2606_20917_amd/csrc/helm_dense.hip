@@ -11,9 +11,11 @@
 // a dense GEMM with K = 7 M that the FP64 matrix instructions run directly; the scaled A operand
 // is formed in registers from X staged in LDS.  The reference matrices come from the validated
 // sum-factorised generic kernel applied to unit vectors at basis creation (build_dense_refs).
+// FP32 batches run the same GEMM on the FP32 matrix instructions with FP32 copies of the matrices.
 //
-// v_mfma_f64_16x16x4f64 operand layout (checked on the device): lane l holds A[l%16][l/16] and
-// B[l/16][l%16]; its four results are D[4v + l/16][l%16], v = 0..3.
+// Operand layouts (checked on the device): lane l holds A[l%16][l/16] and B[l/16][l%16] in both
+// v_mfma_f64_16x16x4f64 and v_mfma_f32_16x16x4f32; the four results of lane l are
+// D[4v + l/16][l%16] (FP64) and D[4(l/16) + v][l%16] (FP32), v = 0..3.
 #include <cstring>
 #include <vector>
 
@@ -22,7 +24,21 @@
 
 namespace nir {
 
-typedef double dense_d4 __attribute__((ext_vector_type(4)));
+template <class T>
+using dense_v4 = T __attribute__((ext_vector_type(4)));
+
+template <class T>
+__device__ __forceinline__ dense_v4<T> dense_mfma(T a, T b, dense_v4<T> c) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// row of result v of lane group lk (= l / 16) within a 16 x 16 tile
+template <class T>
+__device__ __forceinline__ int dense_drow(int v, int lk) {
+  return sizeof(T) == 8 ? 4 * v + lk : 4 * lk + v;
+}
 
 constexpr int dense_ceil(int a, int b) { return (a + b - 1) / b; }
 
@@ -58,25 +74,25 @@ struct DenseDims {
   static constexpr bool PF = NCT >= 8;
 };
 
-template <int SHAPE, int P>
-__global__ void __launch_bounds__(256) k_helm_dense(const double* __restrict__ S, const double* __restrict__ x,
-                                                    double* __restrict__ y, const double* __restrict__ helm,
-                                                    double lambda, int64_t nelmt) {
+template <int SHAPE, int P, class T>
+__global__ void __launch_bounds__(256) k_helm_dense(const T* __restrict__ S, const T* __restrict__ x,
+                                                    T* __restrict__ y, const T* __restrict__ helm, T lambda,
+                                                    int64_t nelmt) {
   using D = DenseDims<SHAPE, P>;
   constexpr int M = D::M, MP = D::MP, NCT = D::NCT, XSTR = D::XSTR, RTW = D::RTW, CTW = D::CTW, WC = D::WC;
-  __shared__ double Xs[D::ROWS * XSTR];
+  __shared__ T Xs[D::ROWS * XSTR];
   const int64_t e0 = int64_t(blockIdx.x) * D::ROWS;
   const int ne = int(min(int64_t(D::ROWS), nelmt - e0));
   // stage the block's coefficients, zero-padded to MP columns and ROWS rows
   for (int f = threadIdx.x; f < D::ROWS * MP; f += 256) {
     const int r = f / MP, m = f - r * MP;
-    Xs[r * XSTR + m] = (r < ne && m < M) ? x[(e0 + r) * M + m] : 0.0;
+    Xs[r * XSTR + m] = (r < ne && m < M) ? x[(e0 + r) * M + m] : T(0);
   }
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int li = l & 15, lk = l >> 4;
   const int wr = w / WC, wc = w - wr * WC;   // row tiles wr RTW .. (wr+1) RTW - 1; column tiles wc + WC u
   // factors of this lane's rows (lambda folded into the mass factor)
-  double g[RTW][7];
+  T g[RTW][7];
 #pragma unroll
   for (int t = 0; t < RTW; ++t) {
     const int r = (wr * RTW + t) * 16 + li;
@@ -85,32 +101,32 @@ __global__ void __launch_bounds__(256) k_helm_dense(const double* __restrict__ S
     for (int c = 0; c < 7; ++c) g[t][c] = helm[e * 7 + c];
     g[t][6] *= lambda;
   }
-  dense_d4 acc[RTW][CTW];
+  dense_v4<T> acc[RTW][CTW];
 #pragma unroll
   for (int t = 0; t < RTW; ++t)
 #pragma unroll
-    for (int u = 0; u < CTW; ++u) acc[t][u] = dense_d4{0.0, 0.0, 0.0, 0.0};
+    for (int u = 0; u < CTW; ++u) acc[t][u] = dense_v4<T>{T(0), T(0), T(0), T(0)};
   // B fragments of K step m0: rows m0 + lk of the seven stacked matrices, this wave's column tiles
-  auto load_b = [&](int m0, double (&b)[7][CTW]) {
+  auto load_b = [&](int m0, T (&b)[7][CTW]) {
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
-      const double* __restrict__ Sr = S + int64_t(c * MP + m0 + lk) * MP + li;
+      const T* __restrict__ Sr = S + int64_t(c * MP + m0 + lk) * MP + li;
 #pragma unroll
       for (int u = 0; u < CTW; ++u) {
         const int ct = wc + WC * u;
-        b[c][u] = ct < NCT ? Sr[ct * 16] : 0.0;
+        b[c][u] = ct < NCT ? Sr[ct * 16] : T(0);
       }
     }
   };
-  double bn[7][CTW];
+  T bn[7][CTW];
   if constexpr (D::PF) load_b(0, bn);
   __syncthreads();
 #pragma unroll 1
   for (int m0 = 0; m0 < MP; m0 += 4) {
-    double xa[RTW];
+    T xa[RTW];
 #pragma unroll
     for (int t = 0; t < RTW; ++t) xa[t] = Xs[((wr * RTW + t) * 16 + li) * XSTR + m0 + lk];
-    double b[7][CTW];
+    T b[7][CTW];
     if constexpr (D::PF) {
 #pragma unroll
       for (int c = 0; c < 7; ++c)
@@ -124,9 +140,9 @@ __global__ void __launch_bounds__(256) k_helm_dense(const double* __restrict__ S
     for (int c = 0; c < 7; ++c)
 #pragma unroll
       for (int t = 0; t < RTW; ++t) {
-        const double a = xa[t] * g[t][c];
+        const T a = xa[t] * g[t][c];
 #pragma unroll
-        for (int u = 0; u < CTW; ++u) acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[c][u], acc[t][u], 0, 0, 0);
+        for (int u = 0; u < CTW; ++u) acc[t][u] = dense_mfma<T>(a, b[c][u], acc[t][u]);
       }
   }
 #pragma unroll
@@ -137,13 +153,13 @@ __global__ void __launch_bounds__(256) k_helm_dense(const double* __restrict__ S
       if (ct >= NCT || col >= M) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = (wr * RTW + t) * 16 + 4 * v + lk;
+        const int r = (wr * RTW + t) * 16 + dense_drow<T>(v, lk);
         if (r < ne) y[(e0 + r) * M + col] = acc[t][u][v];
       }
     }
 }
 
-template <int SHAPE, int P>
+template <int SHAPE, int P, class T>
 static nir_status launch_dense_P(const nir_basis* b, const OpArgs& a, hipStream_t s) {
   using D = DenseDims<SHAPE, P>;
   if constexpr (D::M > kDenseMaxM) {
@@ -152,17 +168,21 @@ static nir_status launch_dense_P(const nir_basis* b, const OpArgs& a, hipStream_
     const int64_t nb = (a.nelmt + D::ROWS - 1) / D::ROWS;
     if (nb > 0x7fffffff) return fail(NIR_EINVAL, "too many elements for one launch");
     if (nb == 0) return ok();
-    hipLaunchKernelGGL((k_helm_dense<SHAPE, P>), dim3(unsigned(nb)), dim3(256), 0, s, b->dense64,
-                       static_cast<const double*>(a.in0), static_cast<double*>(a.out0),
-                       static_cast<const double*>(a.helm), a.lambda, a.nelmt);
+    const T* S;
+    if constexpr (sizeof(T) == 8) S = b->dense64; else S = b->dense32;
+    hipLaunchKernelGGL((k_helm_dense<SHAPE, P, T>), dim3(unsigned(nb)), dim3(256), 0, s, S,
+                       static_cast<const T*>(a.in0), static_cast<T*>(a.out0), static_cast<const T*>(a.helm),
+                       T(a.lambda), a.nelmt);
     return hip_check(hipGetLastError(), "dense Helmholtz launch");
   }
 }
 
 template <int SHAPE>
-static nir_status launch_dense_shape(const nir_basis* b, const OpArgs& a, hipStream_t s) {
-#define NIR_CASE(PP) \
-  case PP: return launch_dense_P<SHAPE, PP>(b, a, s);
+static nir_status launch_dense_shape(const nir_basis* b, int dtype, const OpArgs& a, hipStream_t s) {
+#define NIR_CASE(PP)                                                              \
+  case PP:                                                                        \
+    return dtype == NIR_F64 ? launch_dense_P<SHAPE, PP, double>(b, a, s)         \
+                            : launch_dense_P<SHAPE, PP, float>(b, a, s);
   switch (b->P) {
     NIR_CASE(2) NIR_CASE(3) NIR_CASE(4) NIR_CASE(5) NIR_CASE(6)
     NIR_CASE(7) NIR_CASE(8) NIR_CASE(9) NIR_CASE(10)
@@ -171,13 +191,13 @@ static nir_status launch_dense_shape(const nir_basis* b, const OpArgs& a, hipStr
 #undef NIR_CASE
 }
 
-// FP64 dense apply of an affine batch (per-element factors helm[nelmt][7])
-nir_status launch_helm_dense(const nir_basis* b, const OpArgs& a, hipStream_t s) {
+// dense apply of an affine batch (per-element factors helm[nelmt][7]), FP64 or FP32
+nir_status launch_helm_dense(const nir_basis* b, int dtype, const OpArgs& a, hipStream_t s) {
   if (!b->dense64) return fail(NIR_ENOTSUP, "no reference matrices for this basis");
   switch (b->shape) {
-    case kPrism: return launch_dense_shape<kPrism>(b, a, s);
-    case kTet: return launch_dense_shape<kTet>(b, a, s);
-    case kPyr: return launch_dense_shape<kPyr>(b, a, s);
+    case kPrism: return launch_dense_shape<kPrism>(b, dtype, a, s);
+    case kTet: return launch_dense_shape<kTet>(b, dtype, a, s);
+    case kPyr: return launch_dense_shape<kPyr>(b, dtype, a, s);
     default: return fail(NIR_ENOTSUP, "the dense apply covers the collapsed shapes");
   }
 }

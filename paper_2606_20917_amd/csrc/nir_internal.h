@@ -223,12 +223,13 @@ nir_status launch_iprod_deriv_col_tet(const nir_basis* b, int dtype, int deforme
 nir_status launch_iprod_deriv_col_pyr(const nir_basis* b, int dtype, int deformed, const OpArgs& a, hipStream_t s);
 
 nir_status launch_helm_hex_f16split(const nir_basis* b, int deformed, const OpArgs& a, hipStream_t s);
-// FP64 fused Helmholtz apply of an affine collapsed-shape batch as one stacked GEMM on the matrix
-// cores, from the reference matrices that build_dense_refs places in the basis (helm_dense.hip)
+// fused Helmholtz apply of an affine collapsed-shape batch (FP64 or FP32) as one stacked GEMM on
+// the matrix cores, from the reference matrices that build_dense_refs places in the basis
+// (helm_dense.hip)
 // (M <= kDenseMaxM: beyond it the 14 M^2 FLOPs per element outgrow the sum-factorised count and
 // the staged rows outgrow the LDS)
 constexpr int kDenseMaxM = 256;
-nir_status launch_helm_dense(const nir_basis* b, const OpArgs& a, hipStream_t s);
+nir_status launch_helm_dense(const nir_basis* b, int dtype, const OpArgs& a, hipStream_t s);
 nir_status build_dense_refs(nir_basis* b);
 // the fused Helmholtz apply with the currently selected kernel variant (native contractions)
 nir_status launch_helm_auto(const nir_basis* basis, int dtype, int deformed, const OpArgs& a, hipStream_t s);
