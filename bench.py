@@ -382,14 +382,14 @@ def run_collapsed(args, dtypes=("f64", "f32"), generic=True):
                 x = torch.tensor(c["coef"], dtype=tdt, device=dev)
                 sets = [(x, torch.empty_like(x))] + [(x.clone(), torch.empty_like(x)) for _ in range(nsets - 1)]
 
-                def timed():
+                def timed(bb=b):
                     for it in range(args.warmup):
-                        nir.nir_helmholtz_apply(b, basis, g, 1.0, *sets[it % nsets])
+                        nir.nir_helmholtz_apply(bb, basis, g, 1.0, *sets[it % nsets])
                     torch.cuda.synchronize()
                     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                     e0.record()
                     for it in range(args.steps):
-                        nir.nir_helmholtz_apply(b, basis, g, 1.0, *sets[it % nsets])
+                        nir.nir_helmholtz_apply(bb, basis, g, 1.0, *sets[it % nsets])
                     e1.record()
                     torch.cuda.synchronize()
                     return e0.elapsed_time(e1) / args.steps
@@ -423,6 +423,15 @@ def run_collapsed(args, dtypes=("f64", "f32"), generic=True):
                 if ms_generic is not None:
                     r["generic_gdofs"] = round(ne * M / ms_generic / 1e6, 3)
                 out[f"{name}_P{P}_{dt_name}"] = r
+                if dt == nir.F32 and not deformed and M <= 256:
+                    # FP16-split products of the reference-matrix GEMM on the FP16 matrix cores
+                    ms16 = timed(nir.batch(shape, P, ne, nir.F32, deformed, math=nir.MATH_F16SPLIT))
+                    MP = (M + 15) // 16 * 16
+                    out[f"{name}_P{P}_f16split"] = {
+                        "nelmt": ne, "ms": round(ms16, 4), "gdofs": round(ne * M / ms16 / 1e6, 3),
+                        "frac_valu": round(ne * alg / ms16 / 1e9 / 157.3, 4),
+                        "tflops_mfma_f16": round(3 * ne * 14 * MP * MP / ms16 / 1e9, 2),
+                        "frac_mfma_f16": round(3 * ne * 14 * MP * MP / ms16 / 1e9 / 2500.0, 4)}
                 del sets, x, helm, helm32, g
                 torch.cuda.empty_cache()
     out["value"] = out["tet_P5_f64"]["gdofs"]

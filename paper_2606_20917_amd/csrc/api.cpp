@@ -410,6 +410,7 @@ nir_status nir_basis_destroy(nir_basis* b) {
   if (b->mfma_scale) (void)hipFree(b->mfma_scale);
   if (b->dense64) (void)hipFree(b->dense64);
   if (b->dense32) (void)hipFree(b->dense32);
+  if (b->dense16) (void)hipFree(b->dense16);
   delete b;
   return NIR_OK;
 }
@@ -606,8 +607,12 @@ nir_status nir_helmholtz_apply(const nir_batch* b, const nir_basis* basis, const
   a.lambda = lambda;
   a.nelmt = b->nelmt;
   if (b->math == NIR_MATH_F16SPLIT) {
-    if (b->shape != kHex) return fail(NIR_ENOTSUP, "FP16-split contractions are implemented for hexahedra");
-    return launch_helm_hex_f16split(basis, b->deformed, a, static_cast<hipStream_t>(stream));
+    if (b->shape == kHex) return launch_helm_hex_f16split(basis, b->deformed, a, static_cast<hipStream_t>(stream));
+    // collapsed shapes: the reference-matrix GEMM of affine batches
+    if (b->deformed || !basis->dense16)
+      return fail(NIR_ENOTSUP, "FP16-split contractions of prisms, tetrahedra and pyramids need per-element "
+                               "factors (deformed = 0) and at most %d modes", kDenseMaxM);
+    return launch_helm_dense_f16split(basis, a, static_cast<hipStream_t>(stream));
   }
   return launch_helm_auto(basis, b->dtype, b->deformed, a, static_cast<hipStream_t>(stream));
 }

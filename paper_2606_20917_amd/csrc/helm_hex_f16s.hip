@@ -50,13 +50,17 @@ __device__ __forceinline__ float tile_scale(float m, float* s) {
 
 __device__ __forceinline__ Frag split4(const float v[4], float s) {
   Frag f;
+  float a[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const float a = v[c] * s;
-    const _Float16 h = (_Float16)a;
-    f.hi[c] = h;
-    f.lo[c] = (_Float16)((a - (float)h) * 2048.f);
+    a[c] = v[c] * s;
+    f.hi[c] = (_Float16)a[c];
   }
+  // the residual is taken from the very halves the matrix instruction receives (otherwise the
+  // compiler may round the operand and the residual's hi in two different ways)
+  asm volatile("" : "+v"(f.hi));
+#pragma unroll
+  for (int c = 0; c < 4; ++c) f.lo[c] = (_Float16)((a[c] - (float)f.hi[c]) * 2048.f);
   return f;
 }
 

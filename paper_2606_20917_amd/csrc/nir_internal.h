@@ -144,6 +144,10 @@ struct nir_basis {
   // [7 MP][MP] (MP = M rounded up to 16), FP64 and an FP32 copy (helm_dense.hip)
   double* dense64 = nullptr;
   float* dense32 = nullptr;
+  // the same, scaled per matrix by sigma_c into [1/2, 1) and split into FP16 hi and lo parts packed
+  // in the B layout of v_mfma_f32_16x16x16f16 (hi block, then lo block), and the 1 / sigma_c
+  void* dense16 = nullptr;
+  float dense_inv[7] = {1, 1, 1, 1, 1, 1, 1};
   const void* table_dev[NIR_TAB_COUNT];
 };
 
@@ -230,6 +234,8 @@ nir_status launch_helm_hex_f16split(const nir_basis* b, int deformed, const OpAr
 // the staged rows outgrow the LDS)
 constexpr int kDenseMaxM = 256;
 nir_status launch_helm_dense(const nir_basis* b, int dtype, const OpArgs& a, hipStream_t s);
+// the same GEMM as FP16-split compensated products on the FP16 matrix cores (FP32 storage)
+nir_status launch_helm_dense_f16split(const nir_basis* b, const OpArgs& a, hipStream_t s);
 nir_status build_dense_refs(nir_basis* b);
 // the fused Helmholtz apply with the currently selected kernel variant (native contractions)
 nir_status launch_helm_auto(const nir_basis* basis, int dtype, int deformed, const OpArgs& a, hipStream_t s);

@@ -149,18 +149,26 @@ def test_operators_match_oracle(case, P, dtype):
             for lam in (1.0, 0.0, 0.5, 3.0):
                 nir.nir_helmholtz_apply(b, s["basis"], g, lam, dc, cout)
                 torch.cuda.synchronize()
-                assert elem_relerr(cout.cpu().numpy(), op.helmholtz(tab, geo, lam, coef)) <= tolx, (v, lam)
+                err = elem_relerr(cout.cpu().numpy(), op.helmholtz(tab, geo, lam, coef))
+                if v == nir.VARIANT_DENSE:
+                    print(f"dense shape={shape} P={P} dtype={dtype} lambda={lam} err={err:.3e}")
+                assert err <= tolx, (v, lam)
     finally:
         nir.nir_set_helmholtz_variant(shape, P, dtype, nir.VARIANT_AUTO)
 
     if dtype == nir.F32:
         bs = nir.batch(shape, P, ne, nir.F32, s["deformed"], math=nir.MATH_F16SPLIT)
-        if shape == nir.HEX:
-            # FP16-split MFMA products, FP32 accumulation: same bar as the FP32 Helmholtz apply
+        # FP16-split MFMA products, FP32 accumulation: the hex sweeps, and the reference-matrix GEMM
+        # of affine collapsed shapes (up to 256 modes)
+        if shape == nir.HEX or (not s["deformed"] and tab.M <= 256):
+            # the FP32 Helmholtz bar (each split operand keeps 22 bits; measured errors 1e-7 - 1.2e-6)
+            bar = tol * 10
             for lam in (1.0, 0.0, 3.0):
                 nir.nir_helmholtz_apply(bs, s["basis"], g, lam, dc, cout)
                 torch.cuda.synchronize()
-                assert elem_relerr(cout.cpu().numpy(), op.helmholtz(tab, geo, lam, coef)) <= tol * 10, ("f16s", lam)
+                err = elem_relerr(cout.cpu().numpy(), op.helmholtz(tab, geo, lam, coef))
+                print(f"f16split shape={shape} P={P} lambda={lam} err={err:.3e}")
+                assert err <= bar, ("f16s", lam, err)
         else:
             with pytest.raises(nir.NirError) as e:
                 nir.nir_helmholtz_apply(bs, s["basis"], g, 1.0, dc, cout)
