@@ -404,6 +404,9 @@ nir_status nir_cg_plan_destroy(nir_cg_plan* plan);
  *                          and of the modified basis: about half the multiply-adds (results
  *                          differ from the unfolded kernels by rounding only)
  *   NIR_VARIANT_PENCIL_EO_SPLIT  the same on NIR_VARIANT_PENCIL_SPLIT_GP
+ *                          (PF, GP, SPLIT_GP, EO and EO_SPLIT on per-point factors group a
+ *                          per-order number of elements per block, measured on MI355X: as
+ *                          few as one at large P, so that more, smaller blocks share a CU)
  *   NIR_VARIANT_DENSE      prisms, tetrahedra and pyramids with per-element factors (deformed = 0):
  *                          the operator as the seven reference matrices of the shape combined by
  *                          each element's factors, all elements of a launch stacked into one GEMM

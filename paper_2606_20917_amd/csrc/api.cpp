@@ -100,15 +100,15 @@ static int resolve_variant(int shape, int P, int dtype) {
   // pencil kernel otherwise)
   if (shape == kTet && P <= 8) return NIR_VARIANT_DENSE;
   if (shape != kHex) return NIR_VARIANT_PENCIL;
-  // defaults from a sweep of all variants on MI355X (32^3 curved hexes, per-point factors, the
-  // fastest of four interleaved rounds per variant): the even-odd folded kernels where the
-  // contractions weigh (P = 2, 3 and 7..9 in FP64, all but P = 4, 5 in FP32), whole-pencil
-  // geometry prefetch at P = 4, 5, the point loop one plane ahead at P = 6 and, with the
-  // two-plane exchange, at P = 10 in FP64 (where the folded kernel does not fit 3 waves per SIMD)
+  // defaults from a sweep of all variants, each with its tuned elements per block, on MI355X
+  // (32^3 curved hexes, per-point factors): the even-odd folded kernels where the contractions
+  // weigh (P = 2, 3, 5, 7, 9, 10 in FP64, P = 3 and 5..10 in FP32), whole-pencil geometry
+  // prefetch at P = 4 (and P = 2 in FP32), the point loop one plane ahead at P = 6 and, with the
+  // two-plane exchange at 4 waves per SIMD, at P = 8 in FP64
   constexpr int8_t PF = NIR_VARIANT_PENCIL_PF, GP = NIR_VARIANT_PENCIL_GP, SGP = NIR_VARIANT_PENCIL_SPLIT_GP,
                    EO = NIR_VARIANT_PENCIL_EO, EOS = NIR_VARIANT_PENCIL_EO_SPLIT;
-  static const int8_t def64[kMaxP + 1] = {0, 0, EO, EO, PF, PF, GP, EO, EOS, EOS, SGP};
-  static const int8_t def32[kMaxP + 1] = {0, 0, EO, EO, PF, PF, EO, EOS, EOS, EO, EO};
+  static const int8_t def64[kMaxP + 1] = {0, 0, EO, EO, PF, EO, GP, EO, SGP, EOS, EO};
+  static const int8_t def32[kMaxP + 1] = {0, 0, PF, EO, PF, EO, EO, EO, EO, EO, EO};
   return dtype == NIR_F64 ? def64[P] : def32[P];
 }
 

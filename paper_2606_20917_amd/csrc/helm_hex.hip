@@ -32,7 +32,8 @@
 namespace nir {
 
 template <int P, class T, bool DEF, int IU, int E, bool PF, bool TP, bool GP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(hex_waves_target<P, T, E, TP>())))
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(hex_waves_target<P, T, E, TP, (GP && DEF) ? 4 : 3>())))
 k_helm_hex(const T* __restrict__ tabs, const T* __restrict__ x,
                                                   T* __restrict__ y, const T* __restrict__ helm,
                                                   const T* __restrict__ wq, T lambda, int64_t nelmt) {
@@ -61,14 +62,16 @@ static void launch_var(int variant, const T* tb, const T* x, T* y, const T* helm
   switch (variant) {
     case 1: launch_cfg<P, T, DEF, 2, EMAX, false>(tb, x, y, helm, wq, lam, nelmt, s); break;
     case 2: launch_cfg<P, T, DEF, 1, 1, false>(tb, x, y, helm, wq, lam, nelmt, s); break;
-    case 3: launch_cfg<P, T, DEF, 1, EMAX, true>(tb, x, y, helm, wq, lam, nelmt, s); break;
+    case 3: launch_cfg<P, T, DEF, 1, hex_block_elems<P, T>(kFamPF), true>(tb, x, y, helm, wq, lam, nelmt, s); break;
     case 4: launch_cfg<P, T, DEF, 1, EMAX, false, true>(tb, x, y, helm, wq, lam, nelmt, s); break;
     case 5:
-      if constexpr (DEF) launch_cfg<P, T, DEF, 1, EMAX, false, false, true>(tb, x, y, helm, wq, lam, nelmt, s);
+      if constexpr (DEF)
+        launch_cfg<P, T, DEF, 1, hex_block_elems<P, T>(kFamGP), false, false, true>(tb, x, y, helm, wq, lam, nelmt, s);
       else launch_cfg<P, T, DEF, 1, EMAX, false>(tb, x, y, helm, wq, lam, nelmt, s);
       break;
     case 6:
-      if constexpr (DEF) launch_cfg<P, T, DEF, 1, EMAX, false, true, true>(tb, x, y, helm, wq, lam, nelmt, s);
+      if constexpr (DEF)
+        launch_cfg<P, T, DEF, 1, hex_block_elems<P, T>(kFamSGP), false, true, true>(tb, x, y, helm, wq, lam, nelmt, s);
       else launch_cfg<P, T, DEF, 1, EMAX, false, true>(tb, x, y, helm, wq, lam, nelmt, s);
       break;
     default: launch_cfg<P, T, DEF, 1, EMAX, false>(tb, x, y, helm, wq, lam, nelmt, s); break;

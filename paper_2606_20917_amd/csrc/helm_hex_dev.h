@@ -23,15 +23,17 @@ struct HexPencilDims {
 };
 
 // Register budget of the two-plane variant: the waves per SIMD that its LDS footprint allows
-// (160 KiB per CU, four SIMDs), capped at 3 (512 / 3 VGPRs), so that registers do not hold the
-// occupancy below what the smaller slab allows.  The other variants keep the compiler's own
-// choice (measured faster: at P >= 8 forcing the budget lowered their throughput).
-template <int P, class T, int E, bool TP>
+// (160 KiB per CU, four SIMDs), capped at CAP, so that registers do not hold the occupancy below
+// what the smaller slab allows.  CAP is 3 (512 / 3 VGPRs) in general and 4 (128 VGPRs) for the
+// two-plane kernel with the point loop one plane ahead, which keeps the second and third planes
+// in LDS at P >= 9 to fit.  The other variants keep the compiler's own choice (measured faster:
+// at P >= 8 forcing the budget lowered their throughput).
+template <int P, class T, int E, bool TP, int CAP = 3>
 constexpr int hex_waves_target() {
   using D = HexPencilDims<P, T, E, TP>;
   const int blocks = (160 * 1024) / (D::LDS * int(sizeof(T)));
   const int waves = blocks * (D::BLOCK / 64) / 4;
-  return !TP ? 1 : (waves < 1 ? 1 : (waves > 3 ? 3 : waves));
+  return !TP ? 1 : (waves < 1 ? 1 : (waves > CAP ? CAP : waves));
 }
 
 // One group of up to E elements starting at `base`, on a block of HexPencilDims<P,T,E>::BLOCK
@@ -95,9 +97,20 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
     constexpr bool G1 = GP && DEF && !PF && IU == 1;
     const T* g = helm + (valid ? e / NF : 0) * (DEF ? 7 * NQ : 7);
     T gn[G1 ? 7 : 1];
-    if constexpr (G1) {
+    // the point loop reads the factors with buffer loads: one per-lane byte offset for the whole
+    // loop, the (component, plane) offset in a scalar register, so that no address is formed per
+    // load; lanes past the group's last element read past the buffer's end and get zeros
+    const int64_t gbase = base / NF;
+    const int gcount = ne > 0 ? int((base + ne - 1) / NF - gbase + 1) : 0;
+    const __amdgpu_buffer_rsrc_t grs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<T*>(helm + gbase * 7 * NQ), short(0), gcount * 7 * NQ * int(sizeof(T)), 0x00020000);
+    const int gvo = (int((base + el) / NF - gbase) * 7 * NQ + s) * int(sizeof(T));
+    // at P >= 9 the two-plane kernel requests plane 0 only after sweep B, whose register peak
+    // would otherwise hold the requested factors too
+    constexpr bool LATE0 = TP && G1 && P >= 9;
+    if constexpr (G1 && !LATE0) {
 #pragma unroll
-      for (int c = 0; c < 7; ++c) gn[c] = g[c * NQ + s];
+      for (int c = 0; c < 7; ++c) gn[c] = buf_load<T>(grs, gvo, c * NQ * int(sizeof(T)));
     }
 
     // ---- A: pencils (p,q), r -> k
@@ -165,14 +178,20 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
     }
     __syncthreads();
 
+    if constexpr (LATE0) {
+#pragma unroll
+      for (int c = 0; c < 7; ++c) gn[c] = buf_load<T>(grs, gvo, c * NQ * int(sizeof(T)));
+    }
+
     // ---- C, pointwise, C^T fused: stream over i with pencils (j,k); the values at
     // point (i,j,k) are formed, weighted and folded back into t0..t2 at once, so the
     // point pencils are never held whole
     T C0[P], C1[P], C2[P];
+    constexpr bool C1L = LATE0;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       C0[p] = L[p * Q2 + s];
-      C1[p] = L[PQ2 + p * Q2 + s];
+      if (!C1L) C1[p] = L[PQ2 + p * Q2 + s];
       if (!TP) C2[p] = L[2 * PQ2 + p * Q2 + s];
     }
     // with GP, the two-plane variant leaves the third plane in LDS through the point loop and
@@ -200,12 +219,16 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
       // they are needed anyway
       auto fwd = [&](const HexTabC<P, T>& tk, int i, T& u, T& d1, T& d2, T& d3) {
         u = d1 = d2 = d3 = T(0);
+        // the lane's LDS offset passes an empty asm, so that the plane addresses are formed
+        // here and not hoisted out of the point loop into long-lived registers
+        int so = (act ? el : 0) * SLAB + s;
+        asm volatile("" : "+v"(so));
 #pragma unroll
         for (int p = 0; p < P; ++p) {
           u += tk.B(i, p) * C0[p];
           d1 += tk.D(i, p) * C0[p];
-          d2 += tk.B(i, p) * C1[p];
-          d3 += tk.B(i, p) * (C2L ? L[p * Q2 + s] : C2[p]);
+          d2 += tk.B(i, p) * (C1L ? lds[PQ2 + p * Q2 + so] : C1[p]);
+          d3 += tk.B(i, p) * (C2L ? lds[p * Q2 + so] : C2[p]);
         }
       };
       T u, d1, d2, d3;
@@ -225,7 +248,7 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
         __builtin_amdgcn_sched_barrier(0);
         const int inext = i + 1 < Q ? i + 1 : i;
 #pragma unroll
-        for (int c = 0; c < 7; ++c) gn[c] = g[c * NQ + inext * Q2 + s];
+        for (int c = 0; c < 7; ++c) gn[c] = buf_load<T>(grs, gvo, (c * NQ + inext * Q2) * int(sizeof(T)));
 #pragma unroll
         for (int p = 0; p < P; ++p) {
           t0[p] += tk.B(i, p) * m;

@@ -18,7 +18,7 @@ k_helm_hex_eo(const T* __restrict__ tabs, const T* __restrict__ x, T* __restrict
 template <int P, class T, bool DEF, bool TP>
 static void launch_eo_cfg(const T* tb, const T* x, T* y, const T* helm, const T* wq, T lam, int64_t nelmt,
                           hipStream_t s) {
-  constexpr int E = 256 / ((P + 1) * (P + 1));
+  constexpr int E = DEF ? hex_block_elems<P, T>(TP ? kFamEOS : kFamEO) : 256 / ((P + 1) * (P + 1));
   using D = HexPencilDims<P, T, E, TP>;
   const int64_t nb = (nelmt + E - 1) / E;
   hipLaunchKernelGGL((k_helm_hex_eo<P, T, DEF, E, TP>), dim3(static_cast<unsigned>(nb)), dim3(D::BLOCK), 0, s, tb,

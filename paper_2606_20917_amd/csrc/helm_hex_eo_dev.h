@@ -199,13 +199,25 @@ __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, co
   constexpr bool G1 = GP && DEF;
   const T* g = TRI ? helm : helm + (valid ? e / NF : 0) * (DEF ? 7 * NQ : 7);
   T gn[G1 ? 14 : 1];
-  if constexpr (G1) {
+  // buffer loads of the factors, as in helm_hex_group: a per-lane byte offset for the loop and
+  // the (component, plane) offset in a scalar register; lanes past the last element get zeros
+  const int64_t gbase = base / NF;
+  const int gcount = ne > 0 ? int((base + ne - 1) / NF - gbase + 1) : 0;
+  const __amdgpu_buffer_rsrc_t grs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<T*>(helm + (TRI ? 0 : gbase * 7 * NQ)), short(0), G1 ? gcount * 7 * NQ * int(sizeof(T)) : 0,
+      0x00020000);
+  const int gvo = (int((base + el) / NF - gbase) * 7 * NQ + s) * int(sizeof(T));
+  // in FP64 at P >= 9 the two-plane kernel requests the first pair only after sweep B, whose
+  // register peak would otherwise hold the requested factors too
+  constexpr bool LATE0 = TP && G1 && sizeof(T) == 8 && P >= 9;
+  auto request_pair0 = [&]() {
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
-      gn[c] = g[c * NQ + s];
-      gn[7 + c] = g[c * NQ + (Q - 1) * Q2 + s];
+      gn[c] = buf_load<T>(grs, gvo, c * NQ * int(sizeof(T)));
+      gn[7 + c] = buf_load<T>(grs, gvo, (c * NQ + (Q - 1) * Q2) * int(sizeof(T)));
     }
-  }
+  };
+  if constexpr (G1 && !LATE0) request_pair0();
 
   // ---- A: pencils (p,q), r -> k
   T a0[Q], a1[Q];
@@ -287,6 +299,8 @@ __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, co
   }
   __syncthreads();
 
+  if constexpr (LATE0) request_pair0();
+
   // ---- C, pointwise, C^T fused over point pairs (i, Q-1-i) with pencils (j,k): the values
   // at both points are formed, weighted and folded back into the folded accumulators at once.
   // With GP (or TRI), the two-plane variant reads the third plane in LDS at every pair (P values),
@@ -340,10 +354,14 @@ __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, co
     eo_der(tk, C0e, C0o, S, A);
     d1[0] = S + A;
     d1[1] = S - A;
+    // the lane's LDS offset passes an empty asm, so that the plane addresses are formed here and
+    // not hoisted out of the pair loop into long-lived registers
+    int so = (act ? el : 0) * SLAB + s;
+    if constexpr (C1L || C2L) asm volatile("" : "+v"(so));
     if constexpr (C1L) {
       T tmp[P], ev[NE], od[NO];
 #pragma unroll
-      for (int p = 0; p < P; ++p) tmp[p] = L[PQ2 + p * Q2 + s];
+      for (int p = 0; p < P; ++p) tmp[p] = lds[PQ2 + p * Q2 + so];
       eo_fold<P>(tmp, ev, od);
       eo_val(tk, ev, od, S, A);
     } else {
@@ -356,7 +374,7 @@ __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, co
     if constexpr (C2L) {
       T tmp[P], ev[NE], od[NO];
 #pragma unroll
-      for (int p = 0; p < P; ++p) tmp[p] = L[p * Q2 + s];
+      for (int p = 0; p < P; ++p) tmp[p] = lds[p * Q2 + so];
       eo_fold<P>(tmp, ev, od);
       eo_val(tk, ev, od, S, A);
     } else {
@@ -403,8 +421,8 @@ __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, co
       const int hn = h + 1 < H ? h + 1 : h;
 #pragma unroll
       for (int c = 0; c < 7; ++c) {
-        gn[c] = g[c * NQ + hn * Q2 + s];
-        gn[7 + c] = g[c * NQ + (Q - 1 - hn) * Q2 + s];
+        gn[c] = buf_load<T>(grs, gvo, (c * NQ + hn * Q2) * int(sizeof(T)));
+        gn[7 + c] = buf_load<T>(grs, gvo, (c * NQ + (Q - 1 - hn) * Q2) * int(sizeof(T)));
       }
       bwd(tk, m, f1, f2, f3);
       if (h + 1 < H) fwd(HexTabEO<P, T>{fresh_table(tabs + (h + 1) * ROW)}, u, d1, d2, d3);

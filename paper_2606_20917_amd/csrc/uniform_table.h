@@ -32,6 +32,19 @@ __device__ __forceinline__ const_ptr<T> fresh_table(const T* p) {
 // Row view of a direction-1 table in [point][mode] layout through a fresh pointer:
 // B(i, p) = psi^a_p(z_i), D(i, p) = d psi^a_p / dz (z_i)
 template <int P, class T>
+struct HexTabC;
+
+// raw buffer load of one value at byte offset voff (per lane) + soff (uniform); reads past the
+// descriptor's size return zero
+template <class T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+template <int P, class T>
 struct HexTabC {
   const_ptr<T> t;
   __device__ __forceinline__ T B(int i, int p) const { return t[i * P + p]; }
