@@ -89,8 +89,10 @@ inline int mixed_group_elems(int shape, int P) {
 
 // Each (shape, P) item function is compiled on its own (not inlined into the persistent loop),
 // so the register allocation of one variant does not leak into the others: the kernel needs
-// the maximum over variants, not their union.
-template <class T, int P>
+// the maximum over variants, not their union.  The functions are templated on the kernel's
+// register budget W so that each kernel has its own copies: a function shared by the kernels of
+// several budgets is compiled for the tightest of them (128 VGPRs), and spills under the others.
+template <class T, int P, int W>
 __device__ __noinline__ void item_hex(const MixedBatch<T>* __restrict__ B, int64_t first, T lambda, T* lds) {
   constexpr int E = MixedHex<P, T>::E;
   if (B->deformed)
@@ -99,7 +101,7 @@ __device__ __noinline__ void item_hex(const MixedBatch<T>* __restrict__ B, int64
     helm_hex_group<P, T, false, 1, E>(B->pencil, B->x, B->y, B->helm, B->tb.wq, lambda, B->nelmt, first, lds);
 }
 
-template <class T, int S, int P>
+template <class T, int S, int P, int W>
 __device__ __noinline__ void item_col(const MixedBatch<T>* __restrict__ B, int64_t first, T lambda, T* lds) {
   using C = MixedCol<S, P, T>;
   if (B->deformed)
@@ -110,13 +112,13 @@ __device__ __noinline__ void item_col(const MixedBatch<T>* __restrict__ B, int64
                                                   lds);
 }
 
-template <class T>
+template <class T, int W>
 __device__ __forceinline__ void run_item(const MixedBatch<T>* __restrict__ B, int64_t first, T lambda, T* lds) {
   const int key = B->shape * 16 + B->P;
 #define NIR_HEX(PP) \
-  case kHex * 16 + PP: item_hex<T, PP>(B, first, lambda, lds); break;
+  case kHex * 16 + PP: item_hex<T, PP, W>(B, first, lambda, lds); break;
 #define NIR_COL(S, PP) \
-  case S * 16 + PP: item_col<T, S, PP>(B, first, lambda, lds); break;
+  case S * 16 + PP: item_col<T, S, PP, W>(B, first, lambda, lds); break;
   switch (key) {
     NIR_HEX(2) NIR_HEX(3) NIR_HEX(4) NIR_HEX(5) NIR_HEX(6) NIR_HEX(7) NIR_HEX(8)
     NIR_COL(kPrism, 2) NIR_COL(kPrism, 3) NIR_COL(kPrism, 4) NIR_COL(kPrism, 5) NIR_COL(kPrism, 6)
@@ -140,7 +142,7 @@ __global__ void __launch_bounds__(kMixedBlock) __attribute__((amdgpu_waves_per_e
   (void)counter;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const MixedItem w = items[it];
-    run_item<T>(batches + w.batch, w.first, lambda, lds);
+    run_item<T, W>(batches + w.batch, w.first, lambda, lds);
     // The collapsed groups return right after copying their results out of LDS; the next item
     // (another shape or order) writes its coefficients into the same LDS before its first
     // barrier, so every wavefront must be done reading before any starts the next item.
