@@ -150,9 +150,7 @@ def test_operators_match_oracle(case, P, dtype):
                 nir.nir_helmholtz_apply(b, s["basis"], g, lam, dc, cout)
                 torch.cuda.synchronize()
                 err = elem_relerr(cout.cpu().numpy(), op.helmholtz(tab, geo, lam, coef))
-                if v == nir.VARIANT_DENSE:
-                    print(f"dense shape={shape} P={P} dtype={dtype} lambda={lam} err={err:.3e}")
-                assert err <= tolx, (v, lam)
+                assert err <= tolx, (v, lam, err)
     finally:
         nir.nir_set_helmholtz_variant(shape, P, dtype, nir.VARIANT_AUTO)
 
@@ -167,7 +165,6 @@ def test_operators_match_oracle(case, P, dtype):
                 nir.nir_helmholtz_apply(bs, s["basis"], g, lam, dc, cout)
                 torch.cuda.synchronize()
                 err = elem_relerr(cout.cpu().numpy(), op.helmholtz(tab, geo, lam, coef))
-                print(f"f16split shape={shape} P={P} lambda={lam} err={err:.3e}")
                 assert err <= bar, ("f16s", lam, err)
         else:
             with pytest.raises(nir.NirError) as e:
