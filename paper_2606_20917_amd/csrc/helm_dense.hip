@@ -91,6 +91,9 @@ __global__ void __launch_bounds__(256) k_helm_dense(const T* __restrict__ S, con
                                                     int64_t nelmt) {
   using D = DenseDims<SHAPE, P>;
   constexpr int M = D::M, MP = D::MP, NCT = D::NCT, XSTR = D::XSTR, RTW = D::RTW, CTW = D::CTW, WC = D::WC;
+  // the contraction runs over the M modes rounded up to the K step of 4 only (the reference
+  // matrices' padding rows are zero): 120 of 128 at P = 8, 56 of 64 at P = 5, 20 of 32 at P = 3
+  constexpr int MK = (M + 3) / 4 * 4;
   __shared__ T Xs[D::ROWS * XSTR];
   const int64_t e0 = int64_t(blockIdx.x) * D::ROWS;
   const int ne = int(min(int64_t(D::ROWS), nelmt - e0));
@@ -133,7 +136,7 @@ __global__ void __launch_bounds__(256) k_helm_dense(const T* __restrict__ S, con
   if constexpr (D::PF) load_b(0, bn);
   __syncthreads();
 #pragma unroll 1
-  for (int m0 = 0; m0 < MP; m0 += 4) {
+  for (int m0 = 0; m0 < MK; m0 += 4) {
     T xa[RTW];
 #pragma unroll
     for (int t = 0; t < RTW; ++t) xa[t] = Xs[((wr * RTW + t) * 16 + li) * XSTR + m0 + lk];
@@ -143,7 +146,7 @@ __global__ void __launch_bounds__(256) k_helm_dense(const T* __restrict__ S, con
       for (int c = 0; c < 7; ++c)
 #pragma unroll
         for (int u = 0; u < CTW; ++u) b[c][u] = bn[c][u];
-      if (m0 + 4 < MP) load_b(m0 + 4, bn);
+      if (m0 + 4 < MK) load_b(m0 + 4, bn);
     } else {
       load_b(m0, b);
     }
