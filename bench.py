@@ -416,11 +416,12 @@ def run_collapsed(args, dtypes=("f64", "f32"), generic=True):
                      "bound": "hbm" if deformed else "alu",
                      "variant": nir.nir_get_helmholtz_variant(shape, P, dt)}
                 if r["variant"] == nir.VARIANT_DENSE and not deformed:
-                    # the stacked GEMM on the matrix cores: 7 reference matrices of MP x MP (M padded
-                    # to 16) per element, 2 FLOPs per multiply-add; dense FP64 / FP32 matrix peaks
-                    MP = (M + 15) // 16 * 16
-                    r["tflops_mfma"] = round(ne * 14 * MP * MP / ms / 1e9, 2)
-                    r["frac_mfma"] = round(ne * 14 * MP * MP / ms / 1e9 / (78.6 if dt == nir.F64 else 157.3), 4)
+                    # the stacked GEMM on the matrix cores: 7 reference matrices of MK x MP per
+                    # element (K = M padded to 4, N = M padded to 16), 2 FLOPs per multiply-add;
+                    # dense FP64 / FP32 matrix peaks
+                    MP, MK = (M + 15) // 16 * 16, (M + 3) // 4 * 4
+                    r["tflops_mfma"] = round(ne * 14 * MK * MP / ms / 1e9, 2)
+                    r["frac_mfma"] = round(ne * 14 * MK * MP / ms / 1e9 / (78.6 if dt == nir.F64 else 157.3), 4)
                 if ms_generic is not None:
                     r["generic_gdofs"] = round(ne * M / ms_generic / 1e6, 3)
                 out[f"{name}_P{P}_{dt_name}"] = r
