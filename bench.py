@@ -138,15 +138,21 @@ def cpu_baseline(cases, budget_s):
 # HBM bytes per launch of the dominant kernel measured with FETCH_SIZE / WRITE_SIZE (calibrated
 # by a plain 1 GiB copy: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), valid for that kernel variant while
 # the kernel sources hash to `src_sha`
-TRAFFIC = {"P": 10, "dtype": "f64", "variant": 9, "bytes": 2973704523, "src_sha": "72527b9528290437"}
+TRAFFIC = {"P": 10, "dtype": "f64", "variant": 9, "bytes": 2973704523, "src_sha": "1f73d23f34db0891"}
 
 
 def kernel_src_sha():
+    """Hash of the hex kernel sources with comments and blank space removed (a comment edit does
+    not invalidate a traffic measurement; any code change does)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("helm_hex_dev.h", "helm_hex.hip", "helm_hex.h", "uniform_table.h", "helm_hex_eo_dev.h",
               "helm_hex_eo.hip"):
-        h.update(open(os.path.join(ROOT, "paper_2606_20917_amd", "csrc", f), "rb").read())
+        src = open(os.path.join(ROOT, "paper_2606_20917_amd", "csrc", f)).read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -92,8 +92,8 @@ __device__ __forceinline__ void helm_hex_group(const T* __restrict__ tabs, const
     __syncthreads();
 
     // ---- GP: the factors of point plane 0, in flight through the forward sweeps.  Lanes of
-    // an element past the end read element 0's factors (in bounds, finite) unmasked: a mask
-    // would wait for the loads where it is applied, and those lanes' results are never stored
+    // an element past the end read with no mask (a mask would wait for the loads where it is
+    // applied): past the buffer's end they get zeros, and their results are never stored
     constexpr bool G1 = GP && DEF && !PF && IU == 1;
     const T* g = helm + (valid ? e / NF : 0) * (DEF ? 7 * NQ : 7);
     T gn[G1 ? 7 : 1];

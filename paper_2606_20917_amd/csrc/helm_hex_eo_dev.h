@@ -194,7 +194,7 @@ __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, co
   __syncthreads();
 
   // ---- GP: the factors of point planes 0 and Q-1 (the first pair), in flight through the
-  // forward sweeps; lanes past the batch end read element 0's factors (never stored)
+  // forward sweeps; lanes past the batch end get zeros (never stored)
   static_assert(!(TRI && GP), "the trilinear path streams no factors");
   constexpr bool G1 = GP && DEF;
   const T* g = TRI ? helm : helm + (valid ? e / NF : 0) * (DEF ? 7 * NQ : 7);
