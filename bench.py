@@ -747,56 +747,76 @@ def bench_nodal(args):
 
 
 def bench_convergence(args):
-    """Manufactured-solution study: u = cos(pi x) cos(pi y) cos(pi z) on the unit cube (homogeneous
-    Neumann, lambda = 1) on n^3 hexes (straight and sin-deformed), assembled Jacobi-PCG to 1e-12,
-    L2 error of the discrete solution at the quadrature points against u, P = 2..10."""
+    """Manufactured-solution studies on the unit cube (lambda = 1) on n^3 hexes (straight and
+    sin-deformed), assembled Jacobi-PCG to 1e-12, L2 error of the discrete solution at the
+    quadrature points against u, P = 2..10:
+    - u = cos(pi x) cos(pi y) cos(pi z), whose normal derivative vanishes on the cube's faces:
+      right-hand side int phi f with f = (3 pi^2 + lambda) u;
+    - u = sin(pi x) cos(pi y) sin(pi z), the solve's own solution, with the Neumann flux term:
+      right-hand side int phi f + oint phi du/dn = int grad phi . grad u + lambda int phi u (the
+      divergence theorem), from IProductWRTDerivBase of grad u and IProductWRTBase of u."""
     import torch
     from paper_2606_20917_amd import inputs, nir
     dev = torch.device("cuda")
     n, lam = 3, 1.0
+    pi = np.pi
     out = {"metric": "L2 error of the assembled solve against the manufactured solution", "unit": "L2 error",
            "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
-           "config": {"workload": f"{n}^3 hexes on the unit cube, u = cos(pi x)cos(pi y)cos(pi z), homogeneous "
-                                  "Neumann, lambda=1, Q=P+1, PCG FP64 to 1e-12"}}
-    for amp in (0.0, 0.1):
-        res = {}
-        for P in range(2, 11):
-            Q = P + 1
-            verts = inputs.hex_mesh(n)
-            ne = len(verts)
-            basis = nir.Basis(nir.HEX, P)
-            b64 = nir.batch(nir.HEX, P, ne, nir.F64, 1)
-            dv = torch.tensor(verts, device=dev)
-            mp = nir.MAP_VERTEX_SIN if amp else nir.MAP_VERTEX
-            helm = torch.empty(ne, 7, Q ** 3, dtype=torch.float64, device=dev)
-            helm32 = torch.empty(ne, 7, Q ** 3, dtype=torch.float32, device=dev)
-            jac = torch.empty(ne, Q ** 3, dtype=torch.float64, device=dev)
-            nir.nir_geom_from_vertices(b64, basis, dv, mp, amp, None, jac, helm, helm32)
-            xyz = torch.empty(ne, 3, Q ** 3, dtype=torch.float64, device=dev)
-            nir.nir_points_from_vertices(b64, basis, dv, mp, amp, xyz)
-            u = torch.cos(np.pi * xyz[:, 0]) * torch.cos(np.pi * xyz[:, 1]) * torch.cos(np.pi * xyz[:, 2])
-            f = ((3 * np.pi ** 2 + lam) * u).contiguous()
-            ng = nir.nir_c0_nglobal_hex(n, P)
-            l2g = torch.empty(ne, P ** 3, dtype=torch.int32, device=dev)
-            nir.nir_c0_map_hex(n, P, l2g)
-            A = nir.Assembly(l2g, ng)
-            bl = torch.empty(ne, P ** 3, dtype=torch.float64, device=dev)
-            nir.nir_iprod_wrt_base(b64, basis, nir.geom(None, jac, None), f, bl)
-            bg = torch.zeros(ng, dtype=torch.float64, device=dev)
-            nir.nir_scatter_add(A, nir.F64, bl, bg)
-            plan = nir.CGPlan(b64, basis, nir.geom(None, None, helm), helm32, A, lam)
-            x = torch.zeros(ng, dtype=torch.float64, device=dev)
-            _, info = nir.nir_cg_solve(plan, nir.CG_FP64, bg, x, rtol=1e-12, maxit=100000)
-            xl = torch.empty(ne, P ** 3, dtype=torch.float64, device=dev)
-            nir.nir_gather(A, nir.F64, x, xl)
-            uh = torch.empty(ne, Q ** 3, dtype=torch.float64, device=dev)
-            nir.nir_bwd_trans(b64, basis, xl, uh)
-            w = torch.tensor(nir.nir_table_host(nir.HEX, P, Q, nir.TAB_WQ), device=dev)
-            err = float(torch.sqrt((w[None, :] * jac * (uh - u) ** 2).sum()))
-            res[f"P{P}"] = {"l2_error": err, "cg_iters": info.inner_iters, "rel_residual": info.rel_residual,
-                            "nglobal": ng}
-        out["straight" if amp == 0.0 else "curved_sin0.1"] = res
-    out["value"] = out["curved_sin0.1"]["P10"]["l2_error"]
+           "config": {"workload": f"{n}^3 hexes on the unit cube, lambda=1, Q=P+1, PCG FP64 to 1e-12; "
+                                  "u = cos(pi x)cos(pi y)cos(pi z) (zero normal derivative) and "
+                                  "u = sin(pi x)cos(pi y)sin(pi z) with the Neumann flux term"}}
+    for flux in (False, True):
+        for amp in (0.0, 0.1):
+            res = {}
+            for P in range(2, 11):
+                Q = P + 1
+                verts = inputs.hex_mesh(n)
+                ne = len(verts)
+                basis = nir.Basis(nir.HEX, P)
+                b64 = nir.batch(nir.HEX, P, ne, nir.F64, 1)
+                dv = torch.tensor(verts, device=dev)
+                mp = nir.MAP_VERTEX_SIN if amp else nir.MAP_VERTEX
+                helm = torch.empty(ne, 7, Q ** 3, dtype=torch.float64, device=dev)
+                helm32 = torch.empty(ne, 7, Q ** 3, dtype=torch.float32, device=dev)
+                jac = torch.empty(ne, Q ** 3, dtype=torch.float64, device=dev)
+                dxi = torch.empty(ne, 9, Q ** 3, dtype=torch.float64, device=dev)
+                nir.nir_geom_from_vertices(b64, basis, dv, mp, amp, dxi, jac, helm, helm32)
+                xyz = torch.empty(ne, 3, Q ** 3, dtype=torch.float64, device=dev)
+                nir.nir_points_from_vertices(b64, basis, dv, mp, amp, xyz)
+                X, Y, Z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+                ng = nir.nir_c0_nglobal_hex(n, P)
+                l2g = torch.empty(ne, P ** 3, dtype=torch.int32, device=dev)
+                nir.nir_c0_map_hex(n, P, l2g)
+                A = nir.Assembly(l2g, ng)
+                bl = torch.empty(ne, P ** 3, dtype=torch.float64, device=dev)
+                if flux:
+                    u = torch.sin(pi * X) * torch.cos(pi * Y) * torch.sin(pi * Z)
+                    du = [(pi * torch.cos(pi * X) * torch.cos(pi * Y) * torch.sin(pi * Z)).contiguous(),
+                          (-pi * torch.sin(pi * X) * torch.sin(pi * Y) * torch.sin(pi * Z)).contiguous(),
+                          (pi * torch.sin(pi * X) * torch.cos(pi * Y) * torch.cos(pi * Z)).contiguous()]
+                    nir.nir_iprod_wrt_deriv_base(b64, basis, nir.geom(dxi, jac, None), *du, bl)
+                    bm = torch.empty_like(bl)
+                    nir.nir_iprod_wrt_base(b64, basis, nir.geom(None, jac, None), (lam * u).contiguous(), bm)
+                    bl += bm
+                else:
+                    u = torch.cos(pi * X) * torch.cos(pi * Y) * torch.cos(pi * Z)
+                    nir.nir_iprod_wrt_base(b64, basis, nir.geom(None, jac, None),
+                                           ((3 * pi ** 2 + lam) * u).contiguous(), bl)
+                bg = torch.zeros(ng, dtype=torch.float64, device=dev)
+                nir.nir_scatter_add(A, nir.F64, bl, bg)
+                plan = nir.CGPlan(b64, basis, nir.geom(None, None, helm), helm32, A, lam)
+                x = torch.zeros(ng, dtype=torch.float64, device=dev)
+                _, info = nir.nir_cg_solve(plan, nir.CG_FP64, bg, x, rtol=1e-12, maxit=100000)
+                xl = torch.empty(ne, P ** 3, dtype=torch.float64, device=dev)
+                nir.nir_gather(A, nir.F64, x, xl)
+                uh = torch.empty(ne, Q ** 3, dtype=torch.float64, device=dev)
+                nir.nir_bwd_trans(b64, basis, xl, uh)
+                w = torch.tensor(nir.nir_table_host(nir.HEX, P, Q, nir.TAB_WQ), device=dev)
+                err = float(torch.sqrt((w[None, :] * jac * (uh - u) ** 2).sum()))
+                res[f"P{P}"] = {"l2_error": err, "cg_iters": info.inner_iters, "rel_residual": info.rel_residual,
+                                "nglobal": ng}
+            out[("neumann_flux_" if flux else "") + ("straight" if amp == 0.0 else "curved_sin0.1")] = res
+    out["value"] = out["neumann_flux_curved_sin0.1"]["P10"]["l2_error"]
     print(json.dumps(out), flush=True)
 
 
