@@ -629,3 +629,41 @@ def test_manufactured_neumann_solution_converges():
         uh = op.bwd_trans(tab, x[l2g])
         errs.append(np.abs(uh - u(geo.x)).max())
     assert errs[0] < 0.1 and errs[1] < errs[0] / 20 and errs[2] < errs[1] / 20, errs
+
+
+def test_deriv_inner_product_obeys_the_divergence_theorem():
+    """Green's identity, which the Neumann flux study of the solver rests on, pins the oracle's
+    IProductWRTDerivBase against its IProductWRTBase and a face quadrature written here:
+    int grad phi_m . grad u = -int phi_m lap u + oint phi_m grad u . n for every basis function,
+    on one sheared affine hexahedron x = c + A xi (A non-symmetric, so that a transposed metric
+    or a swapped direction shows) with the cubic u = x^2 y + y z^2 + x z.  P = 4, Q = 5: the GLL
+    rule is exact for every integrand (degree <= 5 per direction), so the identity holds to
+    rounding.  On face xi_d = +-1 the outward n dS is +-det(A) A^{-T} e_d dxi_a dxi_b, from A
+    directly.  A wrong sign, transpose or missing weight in IProductWRTDerivBase breaks it."""
+    P, Q = 4, 5
+    A = np.array([[0.5, 0.1, 0.05], [0.2, 1.0, -0.1], [0.0, 0.15, 0.25]])
+    c = np.array([0.3, -0.2, 0.1])
+    ref = [(-1, -1, -1), (1, -1, -1), (1, 1, -1), (-1, 1, -1), (-1, -1, 1), (1, -1, 1), (1, 1, 1), (-1, 1, 1)]
+    verts = np.array([[c + A @ np.array(sv, dtype=float) for sv in ref]])
+    tab = op.Tables(basis.HEX, P, Q)
+    geo = geometry.Geometry(basis.HEX, Q, verts, 0.0)
+    x, y, z = geo.x[0, :, 0], geo.x[0, :, 1], geo.x[0, :, 2]
+    grad = np.array([2 * x * y + z, x ** 2 + z ** 2, 2 * y * z + x])
+    lap = 4.0 * y
+    lhs = op.iprod_wrt_deriv_base(tab, geo, *(g[None, :] for g in grad))[0]
+    vol = -op.iprod_wrt_base(tab, geo, lap[None, :])[0]
+    r = basis.element_rule(basis.HEX, Q)
+    w1 = r["w1"]
+    idx = np.arange(Q ** 3).reshape(Q, Q, Q)           # points (i, j, k), k fastest
+    Ainv_T = np.linalg.inv(A).T
+    detA = np.linalg.det(A)
+    face = np.zeros(tab.M)
+    for d in range(3):
+        nd = detA * Ainv_T[:, d]                       # n dS / (dxi_a dxi_b) on xi_d = +1
+        for end, sign in ((0, -1.0), (Q - 1, 1.0)):
+            pts = np.take(idx, end, axis=d).ravel()
+            wf = np.outer(w1, w1).ravel()
+            flux = sign * (nd @ grad[:, pts])
+            face += (wf * flux) @ tab.B[pts]
+    np.testing.assert_allclose(lhs, vol + face, rtol=0, atol=1e-12 * np.abs(lhs).max())
+    assert np.abs(face).max() > 0.05   # the boundary term is not negligible here
