@@ -138,7 +138,7 @@ def cpu_baseline(cases, budget_s):
 # HBM bytes per launch of the dominant kernel measured with FETCH_SIZE / WRITE_SIZE (calibrated
 # by a plain 1 GiB copy: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), valid for that kernel variant while
 # the kernel sources hash to `src_sha`
-TRAFFIC = {"P": 10, "dtype": "f64", "variant": 9, "bytes": 2973704523, "src_sha": "1f73d23f34db0891"}
+TRAFFIC = {"P": 10, "dtype": "f64", "variant": 9, "bytes": 2973704523, "src_sha": "e2d21559238a50b9"}
 
 
 def kernel_src_sha():

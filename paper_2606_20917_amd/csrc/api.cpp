@@ -102,13 +102,14 @@ static int resolve_variant(int shape, int P, int dtype) {
   if (shape != kHex) return NIR_VARIANT_PENCIL;
   // defaults from a sweep of all variants, each with its tuned elements per block, on MI355X
   // (32^3 curved hexes, per-point factors): the even-odd folded kernels where the contractions
-  // weigh (P = 2, 3, 5, 7, 9, 10 in FP64, P = 3 and 5..10 in FP32), whole-pencil geometry
-  // prefetch at P = 4 (and P = 2 in FP32), the point loop one plane ahead at P = 6 and, with the
-  // two-plane exchange at 4 waves per SIMD, at P = 8 in FP64
+  // weigh (P = 2, 3, 5, 7, 9, 10 in FP64; every order in FP32, whose folded kernel stages each
+  // block's factors through LDS at P <= 4), whole-pencil geometry prefetch at P = 4 in FP64, the
+  // point loop one plane ahead at P = 6 and, with the two-plane exchange at 4 waves per SIMD, at
+  // P = 8 in FP64
   constexpr int8_t PF = NIR_VARIANT_PENCIL_PF, GP = NIR_VARIANT_PENCIL_GP, SGP = NIR_VARIANT_PENCIL_SPLIT_GP,
                    EO = NIR_VARIANT_PENCIL_EO, EOS = NIR_VARIANT_PENCIL_EO_SPLIT;
   static const int8_t def64[kMaxP + 1] = {0, 0, EO, EO, PF, EO, GP, EO, SGP, EOS, EO};
-  static const int8_t def32[kMaxP + 1] = {0, 0, PF, EO, PF, EO, EO, EO, EO, EO, EO};
+  static const int8_t def32[kMaxP + 1] = {0, 0, EO, EO, EO, EO, EO, EO, EO, EO, EO};
   return dtype == NIR_F64 ? def64[P] : def32[P];
 }
 

@@ -7,12 +7,21 @@
 
 namespace nir {
 
-template <int P, class T, bool DEF, int E, bool TP>
+// SF: the block's factors staged through LDS, requested all at once (FP32 at P <= 4 on
+// per-point factors, where it measured 4-11 % faster; in FP64 it measured slower)
+template <int P, class T, bool DEF>
+constexpr bool eo_staged_factors() {
+  return DEF && sizeof(T) == 4 && P <= 4;
+}
+
+template <int P, class T, bool DEF, int E, bool TP, bool SF = eo_staged_factors<P, T, DEF>() && !TP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(hex_waves_target<P, T, E, TP>())))
 k_helm_hex_eo(const T* __restrict__ tabs, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ helm,
               const T* __restrict__ wq, T lambda, int64_t nelmt) {
-  __shared__ T lds[HexPencilDims<P, T, E, TP>::LDS];
-  helm_hex_eo_group<P, T, DEF, E, TP, true>(tabs, x, y, helm, wq, lambda, nelmt, int64_t(blockIdx.x) * E, lds);
+  using D = HexPencilDims<P, T, E, TP>;
+  __shared__ T lds[D::LDS + (SF ? E * 7 * D::NQ + D::BLOCK : 0)];
+  helm_hex_eo_group<P, T, DEF, E, TP, true, 1, false, SF>(tabs, x, y, helm, wq, lambda, nelmt,
+                                                           int64_t(blockIdx.x) * E, lds);
 }
 
 template <int P, class T, bool DEF, bool TP>

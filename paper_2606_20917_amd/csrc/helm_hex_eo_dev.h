@@ -161,8 +161,14 @@ __device__ __forceinline__ void tri_factors(const double* J1, const double* A2, 
 // each element, which share its geometric factors (as in helm_hex_group).  TRI: no factor stream;
 // the factors are computed at every point from the element's 8 vertices (vtx, [element][8][3]
 // FP64, the trilinear map) with the 1-D GLL points z1 and weights w1 (FP64).
+// SF (per-point factors, one field, small P): the block's factors, one contiguous run of
+// E 7 Q^3 values, are all requested at the start, right after the coefficients, and stay in
+// flight in registers through sweeps A and B; they are then stored into LDS after `lds`'s
+// HexPencilDims<P,T,E,TP>::LDS values, where the point loop reads them.  Every block's whole
+// factor stream is then in flight at once, as in a plain copy.  The caller's LDS holds
+// HexPencilDims<P,T,E,TP>::LDS + E 7 Q^3 + BLOCK values (the last BLOCK a junk row).
 template <int P, class T, bool DEF, int E_ = 256 / ((P + 1) * (P + 1)), bool TP = false, bool GP = false,
-          int NF = 1, bool TRI = false>
+          int NF = 1, bool TRI = false, bool SF = false>
 __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, const T* __restrict__ x,
                                                   T* __restrict__ y, const T* __restrict__ helm,
                                                   const T* __restrict__ wq, T lambda, int64_t nelmt, int64_t base,
@@ -186,17 +192,46 @@ __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, co
   const int64_t e = base + el;
   const bool valid = act && el < ne;
 
-  // ---- stage coefficients (coalesced) into padded mode pencils
-  for (int f = t; f < ne * M; f += BLOCK) {
-    const int e2 = f / M, m = f - e2 * M, pq = m / P, r = m - pq * P;
-    lds[e2 * SLAB + pq * PP + r] = x[base * M + f];
+  static_assert(!SF || (DEF && NF == 1 && !TRI), "staged factors: per-point factors of one field");
+  constexpr int NF7 = 7 * NQ, PERF = SF ? (E * NF7 + BLOCK - 1) / BLOCK : 1;
+  constexpr int PERX = SF ? (E * M + BLOCK - 1) / BLOCK : 1;
+  T* Fs = lds + D::LDS;
+  T fv[PERF];
+  if constexpr (SF) {
+    // the coefficients, then the block's factors, with buffer loads and no branch (reads past a
+    // descriptor's size return zeros), so that each wait counts exactly the requests it needs:
+    // the coefficients are requested first because the vector memory counter completes in order
+    const __amdgpu_buffer_rsrc_t xrs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<T*>(x + base * M), short(0), (ne > 0 ? ne : 0) * M * int(sizeof(T)), 0x00020000);
+    const __amdgpu_buffer_rsrc_t frs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<T*>(helm + base * NF7), short(0), (ne > 0 ? ne : 0) * NF7 * int(sizeof(T)), 0x00020000);
+    T xv[PERX];
+#pragma unroll
+    for (int k = 0; k < PERX; ++k) xv[k] = buf_load<T>(xrs, t * int(sizeof(T)), k * BLOCK * int(sizeof(T)));
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < PERF; ++k) fv[k] = buf_load<T>(frs, t * int(sizeof(T)), k * BLOCK * int(sizeof(T)));
+    // unconditional stores (threads past the group's coefficients write the junk row), so that no
+    // coefficient load is sunk into a branch behind the factors' requests
+#pragma unroll
+    for (int k = 0; k < PERX; ++k) {
+      const int f = t + k * BLOCK;
+      const int e2 = f / M, m = f - e2 * M, pq = m / P, r = m - pq * P;
+      lds[f < E * M ? e2 * SLAB + pq * PP + r : D::LDS + E * NF7 + t] = xv[k];
+    }
+  } else {
+    // ---- stage coefficients (coalesced) into padded mode pencils
+    for (int f = t; f < ne * M; f += BLOCK) {
+      const int e2 = f / M, m = f - e2 * M, pq = m / P, r = m - pq * P;
+      lds[e2 * SLAB + pq * PP + r] = x[base * M + f];
+    }
   }
   __syncthreads();
 
   // ---- GP: the factors of point planes 0 and Q-1 (the first pair), in flight through the
   // forward sweeps; lanes past the batch end get zeros (never stored)
   static_assert(!(TRI && GP), "the trilinear path streams no factors");
-  constexpr bool G1 = GP && DEF;
+  constexpr bool G1 = GP && DEF && !SF;
   const T* g = TRI ? helm : helm + (valid ? e / NF : 0) * (DEF ? 7 * NQ : 7);
   T gn[G1 ? 14 : 1];
   // buffer loads of the factors, as in helm_hex_group: a per-lane byte offset for the loop and
@@ -295,6 +330,13 @@ __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, co
       L[pb * Q2 + j * Q + kb] = c0[j];
       L[PQ2 + pb * Q2 + j * Q + kb] = c1[j];
       if (!TP) L[2 * PQ2 + pb * Q2 + j * Q + kb] = c2[j];
+    }
+  }
+  if constexpr (SF) {   // the factors, in flight since the start, into their LDS region
+#pragma unroll
+    for (int k = 0; k < PERF; ++k) {
+      const int f = t + k * BLOCK;
+      if (f < E * NF7) Fs[f] = fv[k];
     }
   }
   __syncthreads();
@@ -468,6 +510,9 @@ __device__ __forceinline__ void helm_hex_eo_group(const T* __restrict__ tabs, co
         T G[7];
         if constexpr (TRI) {
           tri_factors(J1, A2, B2, A3, B3, z1[iq], w1[iq] * wjk, G);
+        } else if constexpr (SF) {
+#pragma unroll
+          for (int c = 0; c < 7; ++c) G[c] = Fs[(act ? el : 0) * NF7 + c * NQ + n];
         } else if constexpr (DEF) {
 #pragma unroll
           for (int c = 0; c < 7; ++c) G[c] = g[c * NQ + n];

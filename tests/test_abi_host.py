@@ -177,7 +177,7 @@ def test_autotune_cache_roundtrip(tmp_path):
         assert [nir.nir_get_helmholtz_variant(H, P, F64) for P in range(2, 11)] == \
             [EO, EO, PF, EO, GP, EO, SGP, EOS, EO]
         assert [nir.nir_get_helmholtz_variant(H, P, F32) for P in range(2, 11)] == \
-            [PF, EO, PF, EO, EO, EO, EO, EO, EO]
+            [EO, EO, EO, EO, EO, EO, EO, EO, EO]
         assert nir.nir_get_helmholtz_variant(nir.PRISM, 10, nir.F32) == nir.VARIANT_PENCIL
         nir.nir_autotune_load(path)
         assert nir.nir_get_helmholtz_variant(nir.HEX, 6, nir.F64) == nir.VARIANT_PENCIL_U2
