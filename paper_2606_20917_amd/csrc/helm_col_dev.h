@@ -72,8 +72,9 @@ __device__ __forceinline__ void row_fence(const T* v) {
 
 // E_ = 0: the default group size: full slice wavefronts (E Q <= 64) within the LDS budget of a
 // standalone group, half a CU's 160 KiB for the prism (two groups per CU for its HBM-bound
-// stream) and all of it for the tetrahedron (one group per CU, but up to 64/Q elements in every
-// slice wavefront instead of the 64 KiB share: at P = 8 in FP64, 7 elements instead of 3)
+// stream) and all of it for the tetrahedron and the pyramid (one group per CU, but up to 64/Q
+// elements in every slice wavefront instead of the 64 KiB share: at P = 8 in FP64, 7 elements
+// instead of 3 for the tetrahedron, 7 instead of 4 for the pyramid)
 // OPM: 0 the Helmholtz apply; 1 the backward transform alone, whose stages touch only the first
 // P Q^2 values of an element's region (coefficients, value rows of A, value planes of B); 2 the
 // inner product with the basis alone (value planes of C^T, then the tet's vertex region at P Q^2);
@@ -88,15 +89,15 @@ struct ColDims {
   // vertex partials, x0, x1 (tet), vertex row (tet and pyramid apex)
   static constexpr int XTRA = SHAPE == kTet || SHAPE == kPyr ? Q2 + 3 * Q : 0;
   static constexpr int SLAB = OPM == 1 ? P * Q2 : MAIN + XTRA;
-  // elements whose lanes fill a slice wavefront: Q lanes each, and for the pyramid up to 2P - 1
-  // pairs of one slice in sweep A
-  static constexpr int EW = SHAPE == kPyr && 64 / (2 * P - 1) < 64 / Q ? 64 / (2 * P - 1) : 64 / Q;
+  // elements whose lanes fill a slice wavefront: Q lanes each (the pyramid's sweeps A and A^T,
+  // whose slices hold up to 2P - 1 pairs per element, take a second pass where they need it)
+  static constexpr int EW = 64 / Q;
   static constexpr int EL64 = (65536 / int(sizeof(T))) / SLAB;   // elements within 64 KiB of LDS
-  static constexpr int LDS_BYTES = SHAPE == kTet ? 160 * 1024 : 80 * 1024;   // standalone group budget
+  static constexpr int LDS_BYTES = SHAPE == kPrism ? 80 * 1024 : 160 * 1024;   // standalone group budget
   static constexpr int EL = (LDS_BYTES / int(sizeof(T))) / SLAB;
-  // FP32 Helmholtz groups of prisms and tetrahedra at P = 8: 6 elements (8 wavefronts, one per
-  // slice) instead of 7 (9 wavefronts, one of them idle in the slice stages): measured 1.3-1.4x
-  static constexpr int E_FIT = (OPM == 0 && P == 8 && sizeof(T) == 4 && (SHAPE == kTet || SHAPE == kPrism)) ? 6 : 0;
+  // FP32 Helmholtz groups at P = 8: 6 elements (8 wavefronts, one per slice) instead of 7
+  // (9 wavefronts, one of them idle in the slice stages): measured 1.3-1.4x on prisms and tets
+  static constexpr int E_FIT = (OPM == 0 && P == 8 && sizeof(T) == 4) ? 6 : 0;
   static constexpr int E = E_ > 0 ? E_ : (E_FIT > 0 ? E_FIT : (EW < EL ? EW : (EL > 0 ? EL : 1)));
   static constexpr int NT = E * Q2;                              // pencil threads
   static constexpr int NWP = (NT + 63) / 64;
@@ -115,6 +116,14 @@ __device__ __forceinline__ void col_dispatch(int v, F& f) {
       col_dispatch<I + 1, N>(v, f);
   }
 }
+
+// one (element, pair) unit of a pyramid slice stage: its row or mode offset (-1: none), the
+// count of values it writes and its element's LDS region
+template <class T>
+struct ColUnit {
+  int d, n;
+  T* L;
+};
 
 // OPM = 1: the backward transform only (u = B c at the points, into y[nelmt][Q^3]): the value
 // halves of A and B, then C without the pointwise step; helm and lambda are not used.
@@ -146,7 +155,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
   constexpr bool VTX = TET || PYR;   // a vertex mode (0,0,1) handled point by point
 
   static_assert(E * Q <= 64, "a slice wavefront holds E elements x Q lanes");
-  static_assert(!PYR || E * (2 * P - 1) <= 64, "a pyramid slice wavefront holds E elements x 2 sl + 1 pairs");
+  static_assert(!PYR || E * (2 * P - 1) <= 128, "a pyramid slice takes at most two passes of its wavefront");
   const int wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int sub = wave0 / D::NW;                       // group of this wavefront
   const bool in = sub < NSUB;
@@ -180,6 +189,10 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
     T a0[Q], a1[Q];
     int dst = -1;   // pair row written by this lane
     T* Ls = lds;
+    // pyramid slices of more than 64 (element, pair) units: the second pass's unit lane + 64
+    T a0b[PYR ? Q : 1], a1b[PYR ? Q : 1];
+    int dstb = -1;
+    T* Lsb = lds;
     auto stageA = [&](auto ic) {
       constexpr int sl = decltype(ic)::value;
       if constexpr (TET) {
@@ -213,35 +226,56 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
           dst = MO::pair(p, q);
         }
       } else if constexpr (PYR) {
-        // lanes (element, pair index t of the slice): t <= sl is (sl, t), t > sl is (t - sl - 1, sl);
-        // factor psi^b_{sl,r}, the apex mode (0,0,1) of slice 0 apart
+        // units (element, pair index t of the slice): t <= sl is (sl, t), t > sl is (t - sl - 1, sl);
+        // factor psi^b_{sl,r}, the apex mode (0,0,1) of slice 0 apart.  Unit u = lane, then
+        // u = lane + 64 where the slice has more than 64 units
         constexpr int np = 2 * sl + 1, nr = P - sl;
-        const int e2 = lane / np, tt = lane - e2 * np;
-        const int p = tt <= sl ? sl : tt - sl - 1, q = tt <= sl ? tt : sl;
-        if (e2 < E) {
-          Ls = lds + e2 * SLAB;
-          const int m0 = MO::m0(p, q);
-          T c[nr];
+        // returns the unit's pair row (-1: no unit) and element region by value: written through
+        // references, the two passes' results were merged into one stack slot indexed at run time
+        auto unitA = [&](int u, T (&o0)[Q], T (&o1)[Q]) -> ColUnit<T> {
+          const int e2 = u / np, tt = u - e2 * np;
+          const int p = tt <= sl ? sl : tt - sl - 1, q = tt <= sl ? tt : sl;
+          ColUnit<T> res{-1, 0, lds};
+          if (e2 < E) {
+            T* oL = lds + e2 * SLAB;
+            res.L = oL;
+            const int m0 = MO::m0(p, q);
+            T c[nr];
 #pragma unroll
-          for (int r = 0; r < nr; ++r) c[r] = (sl == 0 && r == 1) ? T(0) : Ls[m0 + r];
-          constexpr int off = col_a_off(SHAPE, P, sl);
+            for (int r = 0; r < nr; ++r) c[r] = (sl == 0 && r == 1) ? T(0) : oL[m0 + r];
+            constexpr int off = col_a_off(SHAPE, P, sl);
 #pragma unroll
-          for (int k = 0; k < Q; ++k) {
-            const T dep = k > 0 ? a0[k - 1] : c[0];
-            const const_ptr<T> f = fresh_table_after(tb.T3t, dep) + (off + k * nr);
-            const const_ptr<T> df = fresh_table_after(tb.dT3t, dep) + (off + k * nr);
-            T v0 = T(0), v1 = T(0);
+            for (int k = 0; k < Q; ++k) {
+              const T dep = k > 0 ? o0[k - 1] : c[0];
+              const const_ptr<T> f = fresh_table_after(tb.T3t, dep) + (off + k * nr);
+              const const_ptr<T> df = fresh_table_after(tb.dT3t, dep) + (off + k * nr);
+              T v0 = T(0), v1 = T(0);
 #pragma unroll
-            for (int r = 0; r < nr; ++r) {
-              v0 += f[r] * c[r];
-              v1 += df[r] * c[r];
+              for (int r = 0; r < nr; ++r) {
+                v0 += f[r] * c[r];
+                v1 += df[r] * c[r];
+              }
+              o0[k] = v0;
+              o1[k] = v1;
+              row_fence<1>(&o0[k]);
+              if constexpr (!BWD) row_fence<1>(&o1[k]);
             }
-            a0[k] = v0;
-            a1[k] = v1;
-            row_fence<1>(&a0[k]);
-            if constexpr (!BWD) row_fence<1>(&a1[k]);
+            res.d = MO::pair(p, q);
           }
-          dst = MO::pair(p, q);
+          return res;
+        };
+        const ColUnit<T> r0 = unitA(lane, a0, a1);
+        dst = r0.d;
+        Ls = r0.L;
+        // every slice assigns both units' results, so that the slices' code stays alike and the
+        // compiler keeps them in registers
+        if constexpr (np * E > 64) {
+          const ColUnit<T> r1 = unitA(lane + 64, a0b, a1b);
+          dstb = r1.d;
+          Lsb = r1.L;
+        } else {
+          dstb = -1;
+          Lsb = lds;
         }
       } else {
         // lanes (element, q); factor psi^b_{sl,r}; p = 1 adds the (0,q,1) vertex modes
@@ -284,6 +318,15 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
       for (int k = 0; k < Q; ++k) {
         Ls[dst * Q + k] = a0[k];
         if constexpr (!BWD) Ls[NP * Q + dst * Q + k] = a1[k];
+      }
+    }
+    if constexpr (PYR) {
+      if (dstb >= 0) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          Lsb[dstb * Q + k] = a0b[k];
+          if constexpr (!BWD) Lsb[NP * Q + dstb * Q + k] = a1b[k];
+        }
       }
     }
     __syncthreads();
@@ -716,6 +759,10 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
     T yv[P];
     int dst = -1, cnt = 0;
     T* Ls = lds;
+    // pyramid slices of more than 64 (element, pair) units: the second pass's unit lane + 64
+    T yvb[PYR ? P : 1];
+    int dstb = -1, cntb = 0;
+    T* Lsb = lds;
     auto stageAT = [&](auto ic) {
       constexpr int sl = decltype(ic)::value;
       if constexpr (TET) {
@@ -759,44 +806,63 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
           cnt = nr;
         }
       } else if constexpr (PYR) {
-        // lanes (element, pair index t of the slice) as in A; the apex mode (0,0,1) of slice 0
-        // takes the sum of the vertex row
+        // units (element, pair index t of the slice) as in A, with the same second pass; the apex
+        // mode (0,0,1) of slice 0 takes the sum of the vertex row
         constexpr int np = 2 * sl + 1, nr = P - sl;
-        const int e2 = lane / np, tt = lane - e2 * np;
-        const int p = tt <= sl ? sl : tt - sl - 1, q = tt <= sl ? tt : sl;
-        if (e2 < E) {
-          Ls = lds + e2 * SLAB;
-          const int pr = MO::pair(p, q);
-          T sv0[Q], sv1[Q];
+        auto unitAT = [&](int u, T (&oy)[P]) -> ColUnit<T> {
+          const int e2 = u / np, tt = u - e2 * np;
+          const int p = tt <= sl ? sl : tt - sl - 1, q = tt <= sl ? tt : sl;
+          ColUnit<T> res{-1, 0, lds};
+          if (e2 < E) {
+            T* oL = lds + e2 * SLAB;
+            res.L = oL;
+            const int pr = MO::pair(p, q);
+            T sv0[Q], sv1[Q];
 #pragma unroll
-          for (int k = 0; k < Q; ++k) {
-            sv0[k] = Ls[pr * Q + k];
-            if constexpr (!IPR) sv1[k] = Ls[NP * Q + pr * Q + k];
-          }
-          constexpr int off = col_a_off(SHAPE, P, sl);
-#pragma unroll
-          for (int r = 0; r < nr; ++r) yv[r] = T(0);
-#pragma unroll
-          for (int k = 0; k < Q; ++k) {
-            const T dep = k > 0 ? yv[0] : sv0[0];
-            const const_ptr<T> f = fresh_table_after(tb.T3t, dep) + (off + k * nr);
-            const const_ptr<T> df = fresh_table_after(tb.dT3t, dep) + (off + k * nr);
-#pragma unroll
-            for (int r = 0; r < nr; ++r) {
-              if (sl == 0 && r == 1) continue;
-              yv[r] += f[r] * sv0[k];
-              if constexpr (!IPR) yv[r] += df[r] * sv1[k];
+            for (int k = 0; k < Q; ++k) {
+              sv0[k] = oL[pr * Q + k];
+              if constexpr (!IPR) sv1[k] = oL[NP * Q + pr * Q + k];
             }
-            row_fence<nr>(yv);
-          }
-          if constexpr (sl == 0) {
-            T v = T(0);
+            constexpr int off = col_a_off(SHAPE, P, sl);
 #pragma unroll
-            for (int k = 0; k < Q; ++k) v += Ls[MAIN + Q2 + 2 * Q + k];
-            yv[1] = v;
+            for (int r = 0; r < nr; ++r) oy[r] = T(0);
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+              const T dep = k > 0 ? oy[0] : sv0[0];
+              const const_ptr<T> f = fresh_table_after(tb.T3t, dep) + (off + k * nr);
+              const const_ptr<T> df = fresh_table_after(tb.dT3t, dep) + (off + k * nr);
+#pragma unroll
+              for (int r = 0; r < nr; ++r) {
+                if (sl == 0 && r == 1) continue;
+                oy[r] += f[r] * sv0[k];
+                if constexpr (!IPR) oy[r] += df[r] * sv1[k];
+              }
+              row_fence<nr>(oy);
+            }
+            if constexpr (sl == 0) {
+              T v = T(0);
+#pragma unroll
+              for (int k = 0; k < Q; ++k) v += oL[MAIN + Q2 + 2 * Q + k];
+              oy[1] = v;
+            }
+            res.d = MO::m0(p, q);
+            res.n = nr;
           }
-          dst = MO::m0(p, q);
-          cnt = nr;
+          return res;
+        };
+        const ColUnit<T> r0 = unitAT(lane, yv);
+        dst = r0.d;
+        cnt = r0.n;
+        Ls = r0.L;
+        if constexpr (np * E > 64) {
+          const ColUnit<T> r1 = unitAT(lane + 64, yvb);
+          dstb = r1.d;
+          cntb = r1.n;
+          Lsb = r1.L;
+        } else {
+          dstb = -1;
+          cntb = 0;
+          Lsb = lds;
         }
       } else {
         constexpr int p = sl, nr = P - p;
@@ -848,6 +914,13 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 #pragma unroll
       for (int r = 0; r < P; ++r)
         if (r < cnt) Ls[dst + r] = yv[r];
+    }
+    if constexpr (PYR) {
+      if (dstb >= 0) {
+#pragma unroll
+        for (int r = 0; r < P; ++r)
+          if (r < cntb) Lsb[dstb + r] = yvb[r];
+      }
     }
     __syncthreads();
   }
