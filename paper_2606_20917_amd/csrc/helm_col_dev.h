@@ -71,10 +71,13 @@ __device__ __forceinline__ void row_fence(const T* v) {
 }
 
 // E_ = 0: the default group size: full slice wavefronts (E Q <= 64) within the LDS budget of a
-// standalone group, half a CU's 160 KiB for the prism (two groups per CU for its HBM-bound
-// stream) and all of it for the tetrahedron and the pyramid (one group per CU, but up to 64/Q
-// elements in every slice wavefront instead of the 64 KiB share: at P = 8 in FP64, 7 elements
-// instead of 3 for the tetrahedron, 7 instead of 4 for the pyramid)
+// standalone group, half a CU's 160 KiB for the prism up to P = 8 (two groups per CU for its
+// HBM-bound stream) and all of it for the prism from P = 9, the tetrahedron and the pyramid (one
+// group per CU, but up to 64/Q elements in every slice wavefront instead of the 64 KiB share: at
+// P = 8 in FP64, 7 elements instead of 3 for the tetrahedron, 7 instead of 4 for the pyramid).
+// Half the LDS holds only 3 (P = 9) or 2 (P = 10) FP64 prisms, and two such groups per CU ask
+// for four waves per SIMD, whose 128 registers spill a kernel that needs 152-168: with all of
+// it, 6 or 5 prisms and three waves per SIMD run 2.2x (P = 9) and 3.0x (P = 10) faster
 // OPM: 0 the Helmholtz apply; 1 the backward transform alone, whose stages touch only the first
 // P Q^2 values of an element's region (coefficients, value rows of A, value planes of B); 2 the
 // inner product with the basis alone (value planes of C^T, then the tet's vertex region at P Q^2);
@@ -93,7 +96,7 @@ struct ColDims {
   // whose slices hold up to 2P - 1 pairs per element, take a second pass where they need it)
   static constexpr int EW = 64 / Q;
   static constexpr int EL64 = (65536 / int(sizeof(T))) / SLAB;   // elements within 64 KiB of LDS
-  static constexpr int LDS_BYTES = SHAPE == kPrism ? 80 * 1024 : 160 * 1024;   // standalone group budget
+  static constexpr int LDS_BYTES = SHAPE == kPrism && P < 9 ? 80 * 1024 : 160 * 1024;   // standalone group budget
   static constexpr int EL = (LDS_BYTES / int(sizeof(T))) / SLAB;
   // FP32 Helmholtz groups at P = 8: 6 elements (8 wavefronts, one per slice) instead of 7
   // (9 wavefronts, one of them idle in the slice stages): measured 1.3-1.4x on prisms and tets
