@@ -413,7 +413,7 @@ nir_status nir_cg_plan_destroy(nir_cg_plan* plan);
  *                          on the FP64 or FP32 matrix cores (the reference matrices are
  *                          built with the generic kernel at nir_basis_create, for up to 256 modes
  *                          per element); other batches of these shapes run NIR_VARIANT_PENCIL.
- *                          The default for tetrahedra up to P = 8.
+ *                          The default for tetrahedra, prisms to P = 4 and pyramids to P = 6.
  * Setting a variant a shape does not support returns NIR_ENOTSUP. */
 typedef enum { NIR_VARIANT_AUTO = 0, NIR_VARIANT_GENERIC = 1, NIR_VARIANT_PENCIL = 2,
                NIR_VARIANT_PENCIL_U2 = 3, NIR_VARIANT_PENCIL_E1 = 4, NIR_VARIANT_PENCIL_PF = 5,

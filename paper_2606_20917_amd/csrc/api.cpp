@@ -96,9 +96,10 @@ static std::atomic<int> g_variant[4][kMaxP + 1][2];
 static int resolve_variant(int shape, int P, int dtype) {
   const int v = g_variant[shape][P][dtype].load(std::memory_order_relaxed);
   if (v != NIR_VARIANT_AUTO) return v;
-  // tetrahedra to P = 8: the reference-matrix GEMM on the matrix cores (affine FP64 batches; the
-  // pencil kernel otherwise)
-  if (shape == kTet && P <= 8) return NIR_VARIANT_DENSE;
+  // the reference-matrix GEMM on the matrix cores for affine batches (the pencil kernel runs the
+  // others): tetrahedra at every order (still 1.5x the pencil kernel at P = 10), prisms to P = 4
+  // and pyramids to P = 6, past which the pencil kernel is faster (measured on MI355X, 24^3 cubes)
+  if (shape == kTet || (shape == kPrism && P <= 4) || (shape == kPyr && P <= 6)) return NIR_VARIANT_DENSE;
   if (shape != kHex) return NIR_VARIANT_PENCIL;
   // defaults from a sweep of all variants, each with its tuned elements per block, on MI355X
   // (32^3 curved hexes, per-point factors): the even-odd folded kernels where the contractions

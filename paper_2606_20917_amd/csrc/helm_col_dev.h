@@ -120,6 +120,20 @@ __device__ __forceinline__ void col_dispatch(int v, F& f) {
   }
 }
 
+// calls f(ic, v) for v < N (uniform across the wavefront): with ic = integral_constant<v> when the
+// body's loops depend on v (DEP: one copy of the body per value), else with ic =
+// integral_constant<0> and v known only at run time (one copy for all values: the body then keeps
+// v out of its loop bounds and factor values, and uses it in addresses only)
+template <bool DEP, int N, class F>
+__device__ __forceinline__ void col_planes(int v, F& f) {
+  if constexpr (DEP) {
+    auto g = [&](auto ic) { f(ic, int(decltype(ic)::value)); };
+    col_dispatch<0, N>(v, g);
+  } else if (v < N) {
+    f(std::integral_constant<int, 0>{}, v);
+  }
+}
+
 // one (element, pair) unit of a pyramid slice stage: its row or mode offset (-1: none), the
 // count of values it writes and its element's LDS region
 template <class T>
@@ -159,6 +173,8 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
 
   static_assert(E * Q <= 64, "a slice wavefront holds E elements x Q lanes");
   static_assert(!PYR || E * (2 * P - 1) <= 128, "a pyramid slice takes at most two passes of its wavefront");
+  static_assert(TET || (col_b_terms(SHAPE, P, 0) == P && col_b_off(SHAPE, P, 1) == P * Q),
+                "prism and pyramid B rows: P terms per point, planes P Q values apart");
   const int wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int sub = wave0 / D::NW;                       // group of this wavefront
   const bool in = sub < NSUB;
@@ -341,9 +357,11 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
     const int e2 = lane / Q, k = lane - e2 * Q;
     T* Ls = lds + (e2 < E ? e2 : 0) * SLAB;
     int pw = -1;
-    auto stageB = [&](auto ic) {
-      constexpr int p = decltype(ic)::value, nq = MO::nq(p);
-      constexpr bool X = TET && p == 1;   // pair (0,1) enters the p = 1 plane
+    // the tet's factor psi^b_pq depends on p: one body per plane; the prism's and the pyramid's
+    // psi^a_q does not: one body, p at run time (the rows of every plane are alike)
+    auto stageB = [&](auto ic, const int p) {
+      constexpr int pc = decltype(ic)::value, nq = MO::nq(pc);
+      constexpr bool X = TET && pc == 1;   // pair (0,1) enters the p = 1 plane
       if (e2 < E) {
         T av[nq + 1], bv[nq + 1];
 #pragma unroll
@@ -356,7 +374,8 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
           if constexpr (!BWD) bv[nq] = Ls[NP * Q + MO::pair(0, 1) * Q + k];
         }
         // one row of terms per point j (transposed table), the pair (0,1) term last for X
-        constexpr int nt = col_b_terms(SHAPE, P, p), off = col_b_off(SHAPE, P, p);
+        constexpr int nt = col_b_terms(SHAPE, P, pc);
+        const int off = TET ? col_b_off(SHAPE, P, pc) : p * (P * Q);
         static_assert(nt == nq + (X ? 1 : 0), "B terms");
 #pragma unroll
         for (int j = 0; j < Q; ++j) {
@@ -384,7 +403,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
         pw = p;
       }
     };
-    col_dispatch<0, P>(wave, stageB);
+    col_planes<TET, P>(wave, stageB);
     __syncthreads();
     if (pw >= 0) {
 #pragma unroll
@@ -693,9 +712,10 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
     const int e2 = lane / Q, k = lane - e2 * Q;
     T* Ls = lds + (e2 < E ? e2 : 0) * SLAB;
     int pw = -1;
-    auto stageBT = [&](auto ic) {
-      constexpr int p = decltype(ic)::value, nq = MO::nq(p);
-      constexpr bool X = TET && p == 1;
+    // one body per plane for the tet, one for all planes (p at run time) for the prism and the
+    // pyramid, as in B
+    auto stageBT = [&](auto ic, const int p) {
+      constexpr int pc = decltype(ic)::value;
       if (e2 < E) {
         T tv0[Q], tv1[Q], tv2[Q];
 #pragma unroll
@@ -712,7 +732,8 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
         }
         // outer loop over the points j, one row of terms per point (transposed table): only that
         // row is live in SGPRs; the pair (0,1) term last for X
-        constexpr int nt = col_b_terms(SHAPE, P, p), off = col_b_off(SHAPE, P, p);
+        constexpr int nt = col_b_terms(SHAPE, P, pc);
+        const int off = TET ? col_b_off(SHAPE, P, pc) : p * (P * Q);
 #pragma unroll
         for (int q = 0; q < nt; ++q) s0[q] = s1[q] = T(0);
 #pragma unroll
@@ -734,13 +755,13 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
         pw = p;
       }
     };
-    col_dispatch<0, P>(wave, stageBT);
+    col_planes<TET, P>(wave, stageBT);
     __syncthreads();
     if (pw >= 0) {
       // rows of pair (pw, q); the tet's p = 1 wavefront also writes the (0,1) extra rows, the
       // p = 0 wavefront the vertex row
-      auto writeBT = [&](auto ic) {
-        constexpr int p = decltype(ic)::value, nq = MO::nq(p);
+      auto writeBT = [&](auto ic, const int p) {
+        constexpr int nq = MO::nq(decltype(ic)::value);
 #pragma unroll
         for (int q = 0; q < nq; ++q) {
           Ls[MO::pair(p, q) * Q + k] = s0[q];
@@ -752,7 +773,7 @@ __device__ __forceinline__ void helm_col_group(const DevTab<T>& tb, const T* __r
         }
         if (VTX && p == 0) Ls[MAIN + Q2 + 2 * Q + k] = sx;
       };
-      col_dispatch<0, P>(pw, writeBT);
+      col_planes<TET, P>(pw, writeBT);
     }
     __syncthreads();
   }

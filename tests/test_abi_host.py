@@ -161,15 +161,21 @@ def test_autotune_cache_roundtrip(tmp_path):
     try:
         nir.nir_set_helmholtz_variant(nir.HEX, 6, nir.F64, nir.VARIANT_PENCIL_U2)
         nir.nir_set_helmholtz_variant(nir.TET, 3, nir.F32, nir.VARIANT_GENERIC)
-        nir.nir_set_helmholtz_variant(nir.PYR, 5, nir.F64, nir.VARIANT_DENSE)
+        nir.nir_set_helmholtz_variant(nir.PYR, 8, nir.F64, nir.VARIANT_DENSE)
         path = str(tmp_path / "tune.json")
         nir.nir_autotune_save(path)
         nir.nir_set_helmholtz_variant(nir.HEX, 6, nir.F64, nir.VARIANT_AUTO)
         nir.nir_set_helmholtz_variant(nir.TET, 3, nir.F32, nir.VARIANT_AUTO)
-        nir.nir_set_helmholtz_variant(nir.PYR, 5, nir.F64, nir.VARIANT_AUTO)
+        nir.nir_set_helmholtz_variant(nir.PYR, 8, nir.F64, nir.VARIANT_AUTO)
         assert nir.nir_get_helmholtz_variant(nir.HEX, 6, nir.F64) == nir.VARIANT_PENCIL_GP
-        assert nir.nir_get_helmholtz_variant(nir.TET, 5, nir.F64) == nir.VARIANT_DENSE
-        assert nir.nir_get_helmholtz_variant(nir.PYR, 5, nir.F64) == nir.VARIANT_PENCIL
+        assert nir.nir_get_helmholtz_variant(nir.PYR, 8, nir.F64) == nir.VARIANT_PENCIL
+        # collapsed shapes: the dense GEMM (affine batches) for every tet, prisms to P = 4 and
+        # pyramids to P = 6; the register pencils past them
+        D, PC = nir.VARIANT_DENSE, nir.VARIANT_PENCIL
+        for dt in (nir.F64, nir.F32):
+            assert [nir.nir_get_helmholtz_variant(nir.TET, P, dt) for P in range(2, 11)] == [D] * 9
+            assert [nir.nir_get_helmholtz_variant(nir.PRISM, P, dt) for P in range(2, 11)] == [D] * 3 + [PC] * 6
+            assert [nir.nir_get_helmholtz_variant(nir.PYR, P, dt) for P in range(2, 11)] == [D] * 5 + [PC] * 4
         # built-in per-order defaults of the hex kernel family
         H, F64, F32 = nir.HEX, nir.F64, nir.F32
         PF, GP, SGP = nir.VARIANT_PENCIL_PF, nir.VARIANT_PENCIL_GP, nir.VARIANT_PENCIL_SPLIT_GP
@@ -182,7 +188,7 @@ def test_autotune_cache_roundtrip(tmp_path):
         nir.nir_autotune_load(path)
         assert nir.nir_get_helmholtz_variant(nir.HEX, 6, nir.F64) == nir.VARIANT_PENCIL_U2
         assert nir.nir_get_helmholtz_variant(nir.TET, 3, nir.F32) == nir.VARIANT_GENERIC
-        assert nir.nir_get_helmholtz_variant(nir.PYR, 5, nir.F64) == nir.VARIANT_DENSE
+        assert nir.nir_get_helmholtz_variant(nir.PYR, 8, nir.F64) == nir.VARIANT_DENSE
         # corrupt or invalid caches are rejected and leave the table unchanged
         bad = tmp_path / "bad.json"
         for txt in ("not json", '{"format": "libnir-autotune-1", "entries": [{"shape": 0, "P": 6}]}',
@@ -205,7 +211,7 @@ def test_autotune_cache_roundtrip(tmp_path):
             nir.nir_set_helmholtz_variant(nir.HEX, 4, nir.F64, nir.VARIANT_DENSE + 1)
         nir.nir_set_helmholtz_variant(nir.PRISM, 4, nir.F64, nir.VARIANT_PENCIL)
     finally:
-        for s, P, d in ((nir.HEX, 6, nir.F64), (nir.TET, 3, nir.F32), (nir.PRISM, 4, nir.F64), (nir.PYR, 5, nir.F64)):
+        for s, P, d in ((nir.HEX, 6, nir.F64), (nir.TET, 3, nir.F32), (nir.PRISM, 4, nir.F64), (nir.PYR, 8, nir.F64)):
             nir.nir_set_helmholtz_variant(s, P, d, nir.VARIANT_AUTO)
 
 
