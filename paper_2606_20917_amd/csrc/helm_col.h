@@ -6,22 +6,27 @@
 
 namespace nir {
 
-// Register budget of the prism kernel: the waves per SIMD that one block's LDS footprint allows
-// (160 KiB per CU, four SIMDs), capped at 4, requested from the compiler so that registers do
-// not hold the occupancy below what LDS allows (a block holds at least P wavefronts).  Measured
-// on MI355X at P = 8 in FP64: prisms gain a third (40 B of spills), tetrahedra lose a third
-// (132 B of spills), so the tetrahedron keeps the compiler's own budget.
-template <int SHAPE, int P, class T>
+// Register budget of the prism and pyramid kernels: the waves per SIMD that the blocks LDS
+// allows on a CU (160 KiB, four SIMDs) need, capped at 4, requested from the compiler so that
+// registers do not hold the occupancy below what LDS allows (a block holds at least P
+// wavefronts).  A block's NW wavefronts take ceil(NW/4) slots on some SIMD, so k blocks need
+// k ceil(NW/4) there, not k NW / 4 (the compiler's count): a second 7-wavefront pyramid group at
+// P = 6 in FP64 fits only at 128 VGPRs (pyr24: 11.7 -> 16.0 GDoF/s, no spills).  With per-element
+// factors the same budget spills (affine prisms at P = 7: 50 registers, 5 % slower), so those
+// keep the total-waves count.  Measured on MI355X at P = 8 in FP64: prisms gain a third (40 B of
+// spills), tetrahedra lose a third (132 B of spills), so the tetrahedron keeps the compiler's own
+// budget.
+template <int SHAPE, int P, class T, bool DEF = true>
 constexpr int col_waves_target() {
   using D = ColDims<SHAPE, P, T>;
   const int blocks = (160 * 1024) / (D::LDS * int(sizeof(T)));
-  const int waves = blocks * D::NW / 4;
+  const int waves = DEF ? blocks * ((D::NW + 3) / 4) : blocks * D::NW / 4;
   return SHAPE == kTet ? 1 : (waves < 1 ? 1 : (waves > 4 ? 4 : waves));
 }
 
 template <int SHAPE, int P, class T, bool DEF>
 __global__ void __launch_bounds__((ColDims<SHAPE, P, T>::BLOCK))
-__attribute__((amdgpu_waves_per_eu(col_waves_target<SHAPE, P, T>())))
+__attribute__((amdgpu_waves_per_eu(col_waves_target<SHAPE, P, T, DEF>())))
     k_helm_col(DevTab<T> tb, const T* __restrict__ pen, const T* __restrict__ x, T* __restrict__ y,
                const T* __restrict__ helm, T lambda, int64_t nelmt) {
   using D = ColDims<SHAPE, P, T>;
