@@ -6,22 +6,27 @@
 
 namespace nir {
 
-// Register budget of the prism and pyramid kernels: the waves per SIMD that the blocks LDS
-// allows on a CU (160 KiB, four SIMDs) need, capped at 4, requested from the compiler so that
-// registers do not hold the occupancy below what LDS allows (a block holds at least P
-// wavefronts).  A block's NW wavefronts take ceil(NW/4) slots on some SIMD, so k blocks need
-// k ceil(NW/4) there, not k NW / 4 (the compiler's count): a second 7-wavefront pyramid group at
-// P = 6 in FP64 fits only at 128 VGPRs (pyr24: 11.7 -> 16.0 GDoF/s, no spills).  With per-element
-// factors the same budget spills (affine prisms at P = 7: 50 registers, 5 % slower), so those
-// keep the total-waves count.  Measured on MI355X at P = 8 in FP64: prisms gain a third (40 B of
-// spills), tetrahedra lose a third (132 B of spills), so the tetrahedron keeps the compiler's own
-// budget.
+// Register budget: the waves per SIMD that the blocks LDS allows on a CU (160 KiB, four SIMDs)
+// need, requested from the compiler so that registers do not hold the occupancy below what LDS
+// allows (a block holds at least P wavefronts).  A block's NW wavefronts take ceil(NW/4) slots
+// on some SIMD, so k blocks need k ceil(NW/4) there, not k NW / 4: a second 7-wavefront FP64
+// group at P = 6 fits only at 128 VGPRs (pyr24: 11.7 -> 16.0 GDoF/s, deformed tets 8.2 -> 10.1,
+// no spills), three 8-wavefront FP32 tet groups at P = 7 only at 80 (20.9 -> 24.1).  The compiler
+// grants no more than its own count, ceil(k NW / 4).  Capped at 4 waves in FP64 (and in FP32 to
+// P = 4, where 8 gained nothing and cost 4 %): measured on MI355X at P = 8 in FP64, prisms gain
+// a third from 4 (40 B of spills).  Kernels with per-element factors keep the total-waves count
+// (affine prisms at P = 7 spill 50 registers at 128 and run 5 % slower), and the affine
+// tetrahedron the compiler's own budget (it lost a third with the prism's at P = 8).
 template <int SHAPE, int P, class T, bool DEF = true>
 constexpr int col_waves_target() {
   using D = ColDims<SHAPE, P, T>;
   const int blocks = (160 * 1024) / (D::LDS * int(sizeof(T)));
-  const int waves = DEF ? blocks * ((D::NW + 3) / 4) : blocks * D::NW / 4;
-  return SHAPE == kTet ? 1 : (waves < 1 ? 1 : (waves > 4 ? 4 : waves));
+  const int granted = (blocks * D::NW + 3) / 4;
+  const int need = blocks * ((D::NW + 3) / 4);
+  const int waves = DEF ? (need < granted ? need : granted) : blocks * D::NW / 4;
+  const int cap = sizeof(T) == 4 && P >= 5 ? 8 : 4;
+  if (SHAPE == kTet && !DEF) return 1;
+  return waves < 1 ? 1 : (waves > cap ? cap : waves);
 }
 
 template <int SHAPE, int P, class T, bool DEF>
