@@ -17,9 +17,9 @@ namespace nir {
 // a third from 4 (40 B of spills).  Kernels with per-element factors keep the total-waves count
 // (affine prisms at P = 7 spill 50 registers at 128 and run 5 % slower), and the affine
 // tetrahedron the compiler's own budget (it lost a third with the prism's at P = 8).
-template <int SHAPE, int P, class T, bool DEF = true>
+template <int SHAPE, int P, class T, bool DEF = true, int OPM = 0>
 constexpr int col_waves_target() {
-  using D = ColDims<SHAPE, P, T>;
+  using D = ColDims<SHAPE, P, T, 0, OPM>;
   const int blocks = (160 * 1024) / (D::LDS * int(sizeof(T)));
   const int granted = (blocks * D::NW + 3) / 4;
   const int need = blocks * ((D::NW + 3) / 4);
@@ -183,9 +183,12 @@ nir_status launch_iprod_col_shape(const nir_basis* b, int dtype, int deformed, c
 }
 
 // IProductWRTDerivBase (y = sum_i (D_{x_i} B)^T W f_i, eq. (7)) of the collapsed shapes: the xi
-// fluxes of the three fields at the points, then the transposed sweeps of the Helmholtz group
+// fluxes of the three fields at the points, then the transposed sweeps of the Helmholtz group.
+// The Helmholtz kernel's register budget (prism24 P = 8 in FP64: 130 -> 108 VGPRs, no spills,
+// 16.3 -> 19.1 GDoF/s; the other operators gained nothing from it)
 template <int SHAPE, int P, class T, bool DEF>
 __global__ void __launch_bounds__((ColDims<SHAPE, P, T, 0, 3>::BLOCK))
+__attribute__((amdgpu_waves_per_eu(col_waves_target<SHAPE, P, T, DEF, 3>())))
     k_iprod_deriv_col(DevTab<T> tb, const T* __restrict__ pen, const T* __restrict__ f0, const T* __restrict__ f1,
                       const T* __restrict__ f2, T* __restrict__ y, const T* __restrict__ dxi,
                       const T* __restrict__ jac, int64_t nelmt) {
