@@ -21,7 +21,8 @@ TOL64 = 1e-12
 TOL32 = 2e-5
 
 # (shape, n, jitter, amp, deformed): curved hexes, jittered prisms, affine tets, jittered
-# (non-affine) pyramids, plus the other geometry path of each shape (affine pyramids: square bases)
+# (non-affine) pyramids, plus the other geometry path of each shape (affine pyramids: square
+# bases; affine prisms: right prisms of the unjittered cube)
 CASES = [
     (nir.HEX, 3, 0.05, 0.1, 1),
     (nir.PRISM, 3, 0.05, 0.0, 1),
@@ -31,9 +32,12 @@ CASES = [
     (nir.TET, 2, 0.05, 0.0, 1),
     (nir.PYR, 2, 0.0, 0.0, 0),
     (nir.PYR, 2, 0.05, 0.1, 1),
+    (nir.PRISM, 2, 0.0, 0.0, 0),
 ]
 PS = {c: list(range(2, 11)) for c in (nir.HEX, nir.PRISM, nir.TET, nir.PYR)}   # every compiled order
-PARAMS = [(c, P) for c in CASES for P in PS[c[0]] if (c[3] == 1 or c[2] > 0 or P in (2, 5))]
+# the unjittered affine cases at P = 2, 4 (the last order whose default for affine prisms is the
+# dense GEMM), 5 and 8 (past it: the register pencils)
+PARAMS = [(c, P) for c in CASES for P in PS[c[0]] if (c[3] == 1 or c[2] > 0 or P in (2, 4, 5, 8))]
 
 _CACHE = {}
 
