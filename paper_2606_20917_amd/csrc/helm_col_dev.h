@@ -100,10 +100,11 @@ struct ColDims {
   static constexpr int EL = (LDS_BYTES / int(sizeof(T))) / SLAB;
   // FP32 Helmholtz groups at P = 8: 6 elements (8 wavefronts, one per slice) instead of 7
   // (9 wavefronts, one of them idle in the slice stages): measured 1.3-1.4x on prisms and tets.
-  // Helmholtz groups at P = 4: 10 elements (4 wavefronts, one slot per SIMD) instead of 12 (5,
-  // two slots on one SIMD for every group): measured in FP64 1.13x (prism), 1.49x (pyramid),
-  // 1.44x (tet), in FP32 1.06-1.16x
-  static constexpr int E_FIT = OPM == 0 && P == 8 && sizeof(T) == 4 ? 6 : (OPM == 0 && P == 4 ? 10 : 0);
+  // Groups at P = 4: 10 elements (4 wavefronts, one slot per SIMD) instead of 12 (5, two slots
+  // on one SIMD for every group): measured on the Helmholtz apply in FP64 1.13x (prism), 1.49x
+  // (pyramid), 1.44x (tet), in FP32 1.06-1.16x; on BwdTrans, IProductWRTBase and
+  // IProductWRTDerivBase up to 1.19x (FP64 IProductWRTBase of prisms 72.3 -> 82.0 GDoF/s)
+  static constexpr int E_FIT = OPM == 0 && P == 8 && sizeof(T) == 4 ? 6 : (P == 4 ? 10 : 0);
   static constexpr int E = E_ > 0 ? E_ : (E_FIT > 0 ? E_FIT : (EW < EL ? EW : (EL > 0 ? EL : 1)));
   static constexpr int NT = E * Q2;                              // pencil threads
   static constexpr int NWP = (NT + 63) / 64;
