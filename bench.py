@@ -364,6 +364,9 @@ def run_collapsed(args, dtypes=("f64", "f32"), generic=True):
            "config": {"workload": "tet24 (82944 affine tets, per-element factors), prism24 (27648 prisms, "
                                   "per-point factors) and pyr24 (82944 pyramids, per-point factors), 24^3 cube "
                                   "with +-0.03h jitter, lambda=1, Q=P+1"}}
+    out["config"]["orders"] = getattr(args, "col_ps", "3,5,8")
+    if getattr(args, "col_factors", "mesh") == "point":
+        out["config"]["factors"] = "per-point factors for every shape (the tets too)"
     for name, gen, shape in (("tet", inputs.tet24, nir.TET), ("prism", inputs.prism24, nir.PRISM),
                              ("pyr", inputs.pyr24, nir.PYR)):
         for dt_name, dt in (("f64", nir.F64), ("f32", nir.F32)):
@@ -371,9 +374,11 @@ def run_collapsed(args, dtypes=("f64", "f32"), generic=True):
                 continue
             s = 8 if dt == nir.F64 else 4
             tdt = torch.float64 if dt == nir.F64 else torch.float32
-            for P in (3, 5, 8):
+            for P in [int(p) for p in getattr(args, "col_ps", "3,5,8").split(",")]:
                 c = gen(P)
-                ne, Q, deformed = len(c["verts"]), P + 1, c["deformed"]
+                # per-point factors for every shape on request (the tets of tet24 are affine)
+                point = getattr(args, "col_factors", "mesh") == "point"
+                ne, Q, deformed = len(c["verts"]), P + 1, 1 if point else c["deformed"]
                 npts = Q ** 3 if deformed else 1
                 basis = nir.Basis(shape, P)
                 helm = torch.empty(ne, 7, npts, dtype=torch.float64, device=dev)
@@ -420,7 +425,10 @@ def run_collapsed(args, dtypes=("f64", "f32"), generic=True):
                      "tflops": round(tfl, 2), "frac_valu": round(tfl / peak_fl, 4),
                      "frac_valu_kernel_count": round(ne * flops / ms / 1e9 / peak_fl, 4),
                      "bound": "hbm" if deformed else "alu",
-                     "variant": nir.nir_get_helmholtz_variant(shape, P, dt)}
+                     # the kernel that ran: batches with per-point factors take the pencil kernel
+                     # under the dense default
+                     "variant": (nir.VARIANT_PENCIL if deformed and nir.nir_get_helmholtz_variant(shape, P, dt)
+                                 == nir.VARIANT_DENSE else nir.nir_get_helmholtz_variant(shape, P, dt))}
                 if r["variant"] == nir.VARIANT_DENSE and not deformed:
                     # the stacked GEMM on the matrix cores: 7 reference matrices of MK x MP per
                     # element (K = M padded to 4, N = M padded to 16), 2 FLOPs per multiply-add;
@@ -442,7 +450,9 @@ def run_collapsed(args, dtypes=("f64", "f32"), generic=True):
                         "frac_mfma_f16": round(3 * ne * 14 * MP * MP / ms16 / 1e9 / 2500.0, 4)}
                 del sets, x, helm, helm32, g
                 torch.cuda.empty_cache()
-    out["value"] = out["tet_P5_f64"]["gdofs"]
+    out["value"] = next((out[k]["gdofs"] for k in ("tet_P5_f64", "tet_P3_f64") if k in out), None)
+    if out["value"] is None:
+        out["value"] = next(v["gdofs"] for k, v in out.items() if isinstance(v, dict) and "gdofs" in v)
     return out
 
 
@@ -856,6 +866,10 @@ def main():
     ap.add_argument("--workload", default="helm", choices=["helm", "cg48", "mixed100k", "collapsed", "copy", "ops", "fields", "trilinear",
                              "nodal", "convergence"])
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
+    ap.add_argument("--col-ps", default="3,5,8", help="orders of the collapsed-shape workload")
+    ap.add_argument("--col-factors", default="mesh", choices=["mesh", "point"],
+                    help="collapsed workload: each mesh's own factors (affine tets per element) or "
+                         "per-point factors for every shape")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the FP64 hex apply and the oracle baseline (no FP32 hex, collapsed, mixed, CG)")
     args = ap.parse_args()
