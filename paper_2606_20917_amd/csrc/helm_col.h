@@ -6,17 +6,18 @@
 
 namespace nir {
 
-// Register budget: the waves per SIMD that the blocks LDS allows on a CU (160 KiB, four SIMDs)
-// need, requested from the compiler so that registers do not hold the occupancy below what LDS
-// allows (a block holds at least P wavefronts).  A block's NW wavefronts take ceil(NW/4) slots
-// on some SIMD, so k blocks need k ceil(NW/4) there, not k NW / 4: a second 7-wavefront FP64
-// group at P = 6 fits only at 128 VGPRs (pyr24: 11.7 -> 16.0 GDoF/s, deformed tets 8.2 -> 10.1,
-// no spills), three 8-wavefront FP32 tet groups at P = 7 only at 80 (20.9 -> 24.1).  The compiler
-// grants no more than its own count, ceil(k NW / 4).  Capped at 4 waves in FP64 (and in FP32 to
-// P = 4, where 8 gained nothing and cost 4 %): measured on MI355X at P = 8 in FP64, prisms gain
-// a third from 4 (40 B of spills).  Kernels with per-element factors keep the total-waves count
-// (affine prisms at P = 7 spill 50 registers at 128 and run 5 % slower), and the affine
-// tetrahedron the compiler's own budget (it lost a third with the prism's at P = 8).
+// Register budget, as waves per SIMD requested from the compiler, so that registers do not hold
+// the occupancy below what LDS allows.  LDS (160 KiB per CU) admits k blocks of NW wavefronts
+// (at least P: one per slice).  A block's wavefronts take ceil(NW/4) slots on some SIMD, so k
+// blocks need k ceil(NW/4) waves per SIMD there, not the k NW / 4 the compiler counts, and the
+// compiler grants no more than its own count, ceil(k NW / 4).  Measured on MI355X: a second
+// 7-wavefront FP64 group at P = 6 fits only at 128 VGPRs (pyr24 11.7 -> 16.0 GDoF/s, deformed
+// tets 8.2 -> 10.1, no spills); three 8-wavefront FP32 tet groups at P = 7 only at 80 (20.9 ->
+// 24.1).  Capped at 4 waves in FP64, where prisms at P = 8 gain a third from 4 (40 B of spills),
+// and in FP32 to P = 4, where 8 gained nothing and cost 4 %.  Kernels with per-element factors
+// keep the total-waves count (affine prisms at P = 7 spill 50 registers at 128 and run 5 %
+// slower), and the affine tetrahedron the compiler's own budget (it lost a third with the
+// prism's at P = 8).
 template <int SHAPE, int P, class T, bool DEF = true, int OPM = 0>
 constexpr int col_waves_target() {
   using D = ColDims<SHAPE, P, T, 0, OPM>;
